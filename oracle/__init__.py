@@ -1,0 +1,191 @@
+"""CPU oracle for the FX-correlator hot path: TEST INFRASTRUCTURE ONLY.
+
+Only `tests/`, `__graft_entry__.smoke()` and the CPU-baseline leg of
+`bench.py` may import this package.  The product library never loads it and
+shares no code with it.  The arithmetic lives in `afc_oracle.c` (double
+precision, exact int64 for the int8 path); this module only marshals numpy
+arrays through ctypes.  Each function cites the passage of the paper it
+follows; see afc_oracle.c for the definitions.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liborc.so")
+_lib = None
+
+_p = C.c_void_p
+_i64 = C.c_int64
+_f32 = C.c_float
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = C.CDLL(_LIB_PATH)
+    lib.orc_ppf_stream.argtypes = [_p, _i64, _i64, _i64, _p, _i64, _i64, _i64, _i64, _p]
+    lib.orc_ppf_stream.restype = C.c_int
+    lib.orc_ppf_stream_direct.argtypes = lib.orc_ppf_stream.argtypes
+    lib.orc_ppf_stream_direct.restype = C.c_int
+    lib.orc_requant.argtypes = [_p, _i64, _f32, _p]
+    lib.orc_requant.restype = None
+    lib.orc_xcorr_pairs_f64.argtypes = [_p, _i64, _i64, _i64, _p, _p]
+    lib.orc_xcorr_pairs_f64.restype = None
+    lib.orc_xcorr_pairs_i64.argtypes = [_p, _i64, _i64, _i64, _p, _p]
+    lib.orc_xcorr_pairs_i64.restype = None
+    lib.orc_xcorr_f64.argtypes = [_p, _i64, _i64, _p, _p, _p]
+    lib.orc_xcorr_f64.restype = None
+    lib.orc_xcorr_i64.argtypes = [_p, _i64, _i64, _p, _p, _p]
+    lib.orc_xcorr_i64.restype = C.c_int
+    lib.orc_cal_loss_grad.argtypes = [_p, _p, _p, _i64, _i64, _p, _p]
+    lib.orc_cal_loss_grad.restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(np.asarray(a), dtype=dtype)
+
+
+def _to_complex(a: np.ndarray) -> np.ndarray:
+    return a[..., 0] + 1j * a[..., 1]
+
+
+# --------------------------------------------------------------------------
+# channeliser (Sec. "Polyphase Filterbank")
+# --------------------------------------------------------------------------
+def ppf_stream(x: np.ndarray, taps: np.ndarray, input: int, P: int, T: int,
+               s0: int, s1: int, direct: bool = False) -> np.ndarray:
+    """Channelised spectra s0..s1-1 of one input: complex128 [s1-s0][P].
+
+    x: int16 [L][R][2] (one subband, R receivers) or [L][Na][2][2].
+    """
+    x = _c(x, np.int16)
+    L = x.shape[0]
+    R = x.size // (2 * L)
+    taps = _c(taps, np.float32)
+    assert taps.size == P * T
+    y = np.empty((s1 - s0, P, 2), np.float64)
+    fn = _load().orc_ppf_stream_direct if direct else _load().orc_ppf_stream
+    rc = fn(_ptr(x), L, R, input, _ptr(taps), P, T, s0, s1, _ptr(y))
+    if rc != 0:
+        raise ValueError("orc_ppf_stream: invalid range or sizes")
+    return _to_complex(y)
+
+
+def ppf_subband(x: np.ndarray, taps: np.ndarray, P: int, T: int, S: int,
+                inputs=None) -> np.ndarray:
+    """All (or the listed) inputs of one subband: complex128 [P][S][R']."""
+    x = _c(x, np.int16)
+    L = x.shape[0]
+    R = x.size // (2 * L)
+    inputs = range(R) if inputs is None else list(inputs)
+    out = np.empty((P, S, len(inputs)), np.complex128)
+    for n, i in enumerate(inputs):
+        out[:, :, n] = ppf_stream(x, taps, i, P, T, 0, S).T
+    return out
+
+
+# --------------------------------------------------------------------------
+# requantiser (Sec. "LOFAR Digital Processing", bit modes)
+# --------------------------------------------------------------------------
+def requant(y: np.ndarray, gain: float) -> np.ndarray:
+    """float32 values (any shape) -> int8, clamp(rint(fp32(y*gain)), +-127)."""
+    y = _c(y, np.float32)
+    q = np.empty(y.shape, np.int8)
+    _load().orc_requant(_ptr(y), y.size, float(np.float32(gain)), _ptr(q))
+    return q
+
+
+# --------------------------------------------------------------------------
+# correlator (Sec. "Correlation Kernel")
+# --------------------------------------------------------------------------
+def xcorr_pairs(rows: np.ndarray, pairs: np.ndarray) -> np.ndarray:
+    """rows: complex [S][R] (or float [S][R][2]); pairs int [n][2] -> complex128 [n]."""
+    if np.iscomplexobj(rows):
+        rows = np.stack([rows.real, rows.imag], -1)
+    rows = _c(rows, np.float64)
+    S, R = rows.shape[0], rows.shape[1]
+    pairs = _c(pairs, np.int32).reshape(-1, 2)
+    out = np.empty((pairs.shape[0], 2), np.float64)
+    _load().orc_xcorr_pairs_f64(_ptr(rows), S, R, pairs.shape[0], _ptr(pairs), _ptr(out))
+    return _to_complex(out)
+
+
+def xcorr_pairs_int(rows: np.ndarray, pairs: np.ndarray) -> np.ndarray:
+    """rows: int8 [S][R][2]; pairs [n][2] -> int64 [n][2] exact sums."""
+    rows = _c(rows, np.int8)
+    S, R = rows.shape[0], rows.shape[1]
+    pairs = _c(pairs, np.int32).reshape(-1, 2)
+    out = np.empty((pairs.shape[0], 2), np.int64)
+    _load().orc_xcorr_pairs_i64(_ptr(rows), S, R, pairs.shape[0], _ptr(pairs), _ptr(out))
+    return out
+
+
+def xcorr(z: np.ndarray, flags: Optional[np.ndarray] = None) -> Tuple[np.ndarray, np.ndarray]:
+    """Lower triangle of one channel.
+
+    z: complex [S][2*Na] (or float [S][2*Na][2]).
+    Returns V complex128 [Nbl][2][2] and W int32 [Nbl].
+    """
+    if np.iscomplexobj(z):
+        z = np.stack([z.real, z.imag], -1)
+    z = _c(z, np.float64)
+    S, R = z.shape[0], z.shape[1]
+    Na = R // 2
+    nbl = Na * (Na + 1) // 2
+    V = np.empty((nbl, 2, 2, 2), np.float64)
+    W = np.empty(nbl, np.int32)
+    fl = None if flags is None else _c(flags, np.uint8)
+    _load().orc_xcorr_f64(_ptr(z), S, Na, _ptr(fl), _ptr(V), _ptr(W))
+    return _to_complex(V), W
+
+
+def xcorr_int(z: np.ndarray, flags: Optional[np.ndarray] = None) -> Tuple[np.ndarray, np.ndarray]:
+    """Exact integer lower triangle: z int8 [S][2*Na][2] -> V int64 [Nbl][2][2][2], W."""
+    z = _c(z, np.int8)
+    S, R = z.shape[0], z.shape[1]
+    Na = R // 2
+    nbl = Na * (Na + 1) // 2
+    V = np.empty((nbl, 2, 2, 2), np.int64)
+    W = np.empty(nbl, np.int32)
+    fl = None if flags is None else _c(flags, np.uint8)
+    rc = _load().orc_xcorr_i64(_ptr(z), S, Na, _ptr(fl), _ptr(V), _ptr(W))
+    if rc != 0:
+        raise OverflowError("integer visibility does not fit in int32")
+    return V, W
+
+
+# --------------------------------------------------------------------------
+# gain calibration (Sec. "Calibration Pipeline")
+# --------------------------------------------------------------------------
+def cal_loss_grad(V: np.ndarray, M: np.ndarray, g: np.ndarray,
+                  want_grad: bool = True) -> Tuple[np.ndarray, Optional[np.ndarray]]:
+    """V, M float32 [P][Nbl][2][2][2]; g float32 [P][Na][2][2].
+
+    Returns loss float64 [P][2] and grad complex128 [P][Na][2] (or None).
+    """
+    V = _c(V, np.float32)
+    M = _c(M, np.float32)
+    g = _c(g, np.float32)
+    P, Na = g.shape[0], g.shape[1]
+    assert V.shape[:2] == (P, Na * (Na + 1) // 2) and M.shape == V.shape
+    loss = np.empty((P, 2), np.float64)
+    grad = np.empty((P, Na, 2, 2), np.float64) if want_grad else None
+    rc = _load().orc_cal_loss_grad(_ptr(V), _ptr(M), _ptr(g), Na, P, _ptr(loss), _ptr(grad))
+    if rc != 0:
+        raise MemoryError("orc_cal_loss_grad")
+    return loss, (None if grad is None else _to_complex(grad))
