@@ -1,0 +1,220 @@
+/*
+ * afc.h -- C ABI of an MI355X (gfx950) FX correlator for AARTFAAC-style
+ * all-sky monitors (arXiv 1609.04205).
+ *
+ * The library implements the correlator's data-parallel hot path:
+ *   afc_channelise      polyphase filter bank (FIR + FFT) with the corner turn
+ *                       to the correlator's input-major layout, optional
+ *                       requantisation to int8 or conversion to fp16
+ *   afc_correlate       X-engine: lower triangle of the time-integrated
+ *                       Hermitian visibility matrix per channel, on MFMA
+ *   afc_calibrate_grad  gain-calibration loss ||V - G M G^H||_F^2 and its
+ *                       gradient with respect to the complex gains
+ *   afc_plan_*          batching form: many subbands with their own
+ *                       integration length, sample type and antenna flags in
+ *                       one graph of one channeliser and one persistent
+ *                       correlator launch, tile shape from a measured tuner
+ *
+ * Conventions (all entry points):
+ *   - Pointers are DEVICE pointers unless the comment says "host".  The caller
+ *     owns every buffer; the library never allocates or frees device memory
+ *     on these calls (plans allocate only at afc_plan_create).
+ *   - Every call is asynchronous on `stream` (a hipStream_t; 0 = null stream).
+ *     Argument errors are found on the host before anything is launched and
+ *     return a negative afc_status; afc_last_error() then holds a message
+ *     (thread-local).  Faults inside kernels surface at the caller's next
+ *     synchronisation of the stream.  No C++ exception crosses the ABI.
+ *   - Receivers: an antenna has n_pols = 2 polarisations; receiver (input)
+ *     i = 2*a + p (p = 0 "X", 1 "Y"), N = 2*n_antennas receivers.
+ *   - Baselines: antennas a >= b, bl(a, b) = a*(a+1)/2 + b,
+ *     Nbl = n_antennas*(n_antennas+1)/2.
+ */
+#ifndef AFC_H
+#define AFC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AFC_API __attribute__((visibility("default")))
+
+typedef enum {
+    AFC_OK = 0,
+    AFC_ERR_INVALID = -1,      /* a NULL pointer, a bad size or layout        */
+    AFC_ERR_UNSUPPORTED = -2,  /* valid in principle, not built (e.g. P != 64) */
+    AFC_ERR_HIP = -3,          /* a HIP runtime call failed                    */
+    AFC_ERR_WORKSPACE = -4     /* workspace missing or too small               */
+} afc_status;
+
+typedef enum {
+    AFC_F32 = 0,               /* complex float32  (8 bytes per sample)        */
+    AFC_F16 = 1,               /* complex float16  (4 bytes per sample)        */
+    AFC_I8 = 2                 /* complex int8 in [-127, 127] (2 bytes)        */
+} afc_dtype;
+
+/* Spectra per block in the channelised layout (see afc_channelise). */
+#define AFC_SPECTRUM_BLOCK 8
+/* Largest subband count one call accepts. */
+#define AFC_MAX_SUBBANDS 256
+
+/* Problem shape, following the paper's statement of the correlator's input:
+ * subbanded complex voltages of each polarisation of every antenna
+ * (Sec. "The AARTFAAC Correlator"), channelised by a T-tap, P-channel
+ * polyphase filter bank (Sec. "Polyphase Filterbank") and integrated over
+ * n_spectra spectra (about 1 s at P = 64: 3051 spectra). */
+typedef struct afc_dims {
+    int32_t n_antennas;   /* Na >= 1                                          */
+    int32_t n_pols;       /* must be 2                                         */
+    int32_t n_subbands;   /* B, 1 .. AFC_MAX_SUBBANDS                          */
+    int32_t n_channels;   /* P, must be 64                                     */
+    int32_t n_taps;       /* T, must be 16                                     */
+    int32_t n_spectra;    /* S >= 1 (the maximum over subbands when batched)   */
+} afc_dims;
+
+/* Bytes of the channelised array z for `d` and sample type `dt`:
+ * B * P * ceil(S/8) * N * 8 * sample_bytes.  0 if `d` is invalid. */
+AFC_API size_t afc_channelised_bytes(const afc_dims* d, afc_dtype dt);
+
+/* Bytes of the visibility array for `d`: B * P * Nbl * 4 * 8 (both float2
+ * and int2 samples are 8 bytes). */
+AFC_API size_t afc_visibility_bytes(const afc_dims* d);
+
+/* ---------------------------------------------------------------------------
+ * afc_channelise -- polyphase filter bank per receiver and subband
+ * (Sec. "Polyphase Filterbank": a bank of 16-tap FIR filters followed by a
+ * complex FFT, here P = 64 channels; Sec. "Delay, Bandpass Compensation and
+ * Transpose Kernel": the corner turn from channel-major to receiver-major is
+ * fused into the store).
+ *
+ *   u[s][p] = sum_{t<T} taps[t*P + p] * x[(s+t)*P + p]          (FIR, p < P)
+ *   y[s][k] = sum_{p<P} u[s][p] * exp(-2 pi i k p / P)          (FFT, k < P)
+ *
+ * Channel k is the natural FFT order (k = 0 is the subband centre, k >= P/2
+ * are negative frequency offsets); no normalisation.
+ *
+ * x     int16 [B][L][N][2], L = (S + T - 1) * P rows of N receivers, re/im
+ *       interleaved (time-major; all receivers of a time sample contiguous).
+ *       Rows beyond L are not read.
+ * taps  float [T*P], in the order taps[t*P + p].  Any real filter.
+ * out   [B][P][Sb][N][8] complex of out_dtype, Sb = ceil(S/8): spectrum s of
+ *       receiver i in channel k of subband b sits at block s/8, slot s%8.
+ *       Slots of spectra >= S are written as zero.  Size from
+ *       afc_channelised_bytes().
+ * out_dtype AFC_F32: the float32 value.  AFC_F16: rounded to nearest even.
+ *       AFC_I8: per real component q = clamp(rint(y * requant_gain), -127,
+ *       127), the product rounded to float32 and rint ties to even
+ *       (Sec. "LOFAR Digital Processing": fewer bits per sample for more
+ *       subbands); requant_gain is ignored for the other types.
+ * Limits: P = 64, T = 16, n_pols = 2, L*N*2 < 2^31 per subband.
+ * ------------------------------------------------------------------------- */
+AFC_API int afc_channelise(const afc_dims* d, const int16_t* x, const float* taps,
+                           afc_dtype out_dtype, float requant_gain, void* out,
+                           hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * afc_correlate -- X-engine (Sec. "Correlation Kernel": only one triangle of
+ * the Hermitian covariance matrix is computed, per channel, and the
+ * visibilities are accumulated over the integration; Sec. "CPU Data
+ * Collation": a weighting matrix accompanies the visibilities).
+ *
+ *   V[b][k][bl(a,c)][p][q] = sum_{s < S_b} z_i(s) * conj(z_j(s)),
+ *                            i = 2a+p, j = 2c+q, a >= c
+ *
+ * z        channelised samples in the afc_channelise layout, type in_dtype;
+ *          int8 samples must lie in [-127, 127].
+ * n_spectra_per_sb  host int32 [B] with 1 <= S_b <= d->n_spectra, or NULL
+ *          (all S).  Spectra >= S_b of subband b are ignored whatever they
+ *          hold.
+ * flags    uint8 [B][Na] (nonzero = flagged antenna) or NULL.  A baseline
+ *          that touches a flagged antenna gets V = 0 and weight 0.
+ * vis      [B][P][Nbl][2][2] complex: float2 for AFC_F32 / AFC_F16 (float32
+ *          accumulation), int2 for AFC_I8 (exact int32 accumulation; exact
+ *          while 2 * 127^2 * S_b < 2^31).  Autocorrelations (i == j) have
+ *          imaginary part exactly 0.
+ * weights  int32 [B][Nbl] or NULL: S_b, or 0 for flagged baselines.
+ * ------------------------------------------------------------------------- */
+AFC_API int afc_correlate(const afc_dims* d, afc_dtype in_dtype, const void* z,
+                          const int32_t* n_spectra_per_sb, const uint8_t* flags,
+                          void* vis, int32_t* weights, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * afc_calibrate_grad -- gain-calibration loss and its gradient
+ * (Sec. "Calibration Pipeline": per-channel amplitude and phase calibration
+ * of XX and YY against a point-source sky model; least-squares reading).
+ * Per channel k and polarisation pol in {X, Y}:
+ *
+ *   R_ab = V_ab - g_a M_ab conj(g_b),   L = sum_{a,b} |R_ab|^2 (full matrix)
+ *   grad_a = dL/dRe g_a + i dL/dIm g_a
+ *          = -2 sum_b [ R_ab conj(M_ab) + conj(R_ba) M_ba ] g_b
+ *
+ * V, M     float2 [P][Nbl][2][2] lower triangles in the afc_correlate layout;
+ *          the upper triangle is the conjugate.  XX = [0][0], YY = [1][1];
+ *          XY, YX are not read.
+ * g        float2 [P][Na][2]: gain of antenna a, polarisation pol.
+ * loss     double [P][2] (XX, YY).  Residuals are evaluated in float32 with
+ *          error-free product/sum transformations (no float64); the loss sum
+ *          is float32, stored widened.
+ * grad     float2 [P][Na][2], or NULL for the loss only.  Per-element terms
+ *          in float32; the per-antenna sums are accumulated in float64.
+ * workspace  device buffer of afc_calibrate_workspace_bytes(Na, P) bytes.
+ * Limits: n_antennas <= 4096.
+ * ------------------------------------------------------------------------- */
+AFC_API size_t afc_calibrate_workspace_bytes(int32_t n_antennas, int32_t n_channels);
+AFC_API int afc_calibrate_grad(int32_t n_antennas, int32_t n_channels, const void* V,
+                               const void* M, const void* g, double* loss, void* grad,
+                               void* workspace, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Batching form (Sec. "GPU Processing": each subband is an independent unit
+ * of work; the paper hands subbands to free GPUs one by one, here all of them
+ * go into one channeliser launch and one persistent correlator launch,
+ * replayed as a HIP graph).
+ *
+ * afc_plan_create    d: shape with n_spectra = max S_b; dtype_per_sb host
+ *                    [B] (AFC_F16 or AFC_I8 each, or AFC_F32); n_spectra_per_sb
+ *                    host [B]; tune_cache_path: a JSON file of measured tile
+ *                    choices (read, and written after tuning), or NULL for
+ *                    the built-in default.  Tuning runs kernels on the current
+ *                    device at creation time on scratch memory it allocates
+ *                    and frees there.
+ * afc_plan_workspace_bytes  bytes of the caller-owned workspace that holds
+ *                    the channelised samples of all subbands (each subband in
+ *                    its own type).
+ * afc_plan_launch    x: int16 [B][L][N][2] with L = (n_spectra + T - 1) * P
+ *                    (subband b reads its first (S_b + T - 1) * P rows);
+ *                    gain_per_sb host float [B] (used for int8 subbands);
+ *                    flags uint8 [B][Na] or NULL; vis [B][P][Nbl][2][2]
+ *                    (float2 or int2 per subband type); weights int32 [B][Nbl]
+ *                    or NULL.  The first launch on a stream captures the work
+ *                    into a HIP graph; later launches with the same pointers
+ *                    and stream replay it.
+ * afc_plan_destroy   frees the plan and its graph.
+ * ------------------------------------------------------------------------- */
+typedef struct afc_plan afc_plan;
+
+AFC_API int afc_plan_create(const afc_dims* d, const afc_dtype* dtype_per_sb,
+                            const int32_t* n_spectra_per_sb, const char* tune_cache_path,
+                            afc_plan** out);
+AFC_API size_t afc_plan_workspace_bytes(const afc_plan* p);
+AFC_API int afc_plan_launch(afc_plan* p, const int16_t* x, const float* taps,
+                            const float* gain_per_sb, void* z_workspace,
+                            const uint8_t* flags, void* vis, int32_t* weights,
+                            hipStream_t stream);
+/* Tile configuration the plan's correlator uses (host out-params). */
+AFC_API int afc_plan_info(const afc_plan* p, int32_t* tile_rows, int32_t* tile_cols,
+                          int32_t* n_workgroups, int32_t* n_work_items);
+AFC_API void afc_plan_destroy(afc_plan* p);
+
+/* Message for the last non-OK return on this thread ("" if none). */
+AFC_API const char* afc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AFC_H */

@@ -59,6 +59,12 @@ int orc_ppf_stream(const int16_t *x, int64_t n_rows, int64_t row_stride, int64_t
                    double *y)
 {
     if (P <= 0 || T <= 0 || s0 < 0 || s1 < s0 || (s1 + T - 1) * P > n_rows) return -1;
+    /* table of exp(-2 pi i (k p mod P) / P), each entry from twiddle() */
+    double *wc = (double *)malloc(sizeof(double) * P * P);
+    double *ws = (double *)malloc(sizeof(double) * P * P);
+    if (!wc || !ws) { free(wc); free(ws); return -1; }
+    for (int64_t k = 0; k < P; ++k)
+        for (int64_t p = 0; p < P; ++p) twiddle(k * p, P, &wc[k * P + p], &ws[k * P + p]);
     int64_t s;
 #pragma omp parallel for schedule(static)
     for (s = s0; s < s1; ++s) {
@@ -80,8 +86,7 @@ int orc_ppf_stream(const int16_t *x, int64_t n_rows, int64_t row_stride, int64_t
         for (int64_t k = 0; k < P; ++k) {
             double yr = 0.0, yi = 0.0;
             for (int64_t p = 0; p < P; ++p) {
-                double c, sn;
-                twiddle(k * p, P, &c, &sn);
+                const double c = wc[k * P + p], sn = ws[k * P + p];
                 yr += ur[p] * c - ui[p] * sn;
                 yi += ur[p] * sn + ui[p] * c;
             }
@@ -91,6 +96,8 @@ int orc_ppf_stream(const int16_t *x, int64_t n_rows, int64_t row_stride, int64_t
         free(ur);
         free(ui);
     }
+    free(wc);
+    free(ws);
     return 0;
 }
 

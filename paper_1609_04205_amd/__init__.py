@@ -1,0 +1,285 @@
+"""Python binding of the MI355X FX-correlator library (libafc.so).
+
+Argument marshalling only: every step of the channeliser, the correlator and
+the calibration gradient runs in the HIP kernels behind the C ABI declared in
+include/afc.h.  PyTorch provides device memory and the current stream.  If
+the built library is missing, importing this package raises: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libafc.so")
+
+AFC_F32, AFC_F16, AFC_I8 = 0, 1, 2
+DTYPES = {"f32": AFC_F32, "f16": AFC_F16, "i8": AFC_I8}
+SPECTRUM_BLOCK = 8
+N_CHANNELS = 64
+N_TAPS = 16
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_1609_04205_amd/build.py (or __graft_entry__.build())")
+
+_lib = C.CDLL(LIB_PATH)
+
+
+class Dims(C.Structure):
+    _fields_ = [("n_antennas", C.c_int32), ("n_pols", C.c_int32), ("n_subbands", C.c_int32),
+                ("n_channels", C.c_int32), ("n_taps", C.c_int32), ("n_spectra", C.c_int32)]
+
+
+_vp, _i32, _f32, _sz = C.c_void_p, C.c_int32, C.c_float, C.c_size_t
+_lib.afc_last_error.restype = C.c_char_p
+_lib.afc_channelised_bytes.argtypes = [C.POINTER(Dims), C.c_int]
+_lib.afc_channelised_bytes.restype = _sz
+_lib.afc_visibility_bytes.argtypes = [C.POINTER(Dims)]
+_lib.afc_visibility_bytes.restype = _sz
+_lib.afc_channelise.argtypes = [C.POINTER(Dims), _vp, _vp, C.c_int, _f32, _vp, _vp]
+_lib.afc_correlate.argtypes = [C.POINTER(Dims), C.c_int, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.afc_calibrate_workspace_bytes.argtypes = [_i32, _i32]
+_lib.afc_calibrate_workspace_bytes.restype = _sz
+_lib.afc_calibrate_grad.argtypes = [_i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.afc_plan_create.argtypes = [C.POINTER(Dims), _vp, _vp, C.c_char_p, C.POINTER(_vp)]
+_lib.afc_plan_workspace_bytes.argtypes = [_vp]
+_lib.afc_plan_workspace_bytes.restype = _sz
+_lib.afc_plan_launch.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.afc_plan_info.argtypes = [_vp, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)]
+_lib.afc_plan_destroy.argtypes = [_vp]
+_lib.afc_plan_destroy.restype = None
+
+EXPORTS = ["afc_channelised_bytes", "afc_visibility_bytes", "afc_channelise", "afc_correlate",
+           "afc_calibrate_workspace_bytes", "afc_calibrate_grad", "afc_plan_create",
+           "afc_plan_workspace_bytes", "afc_plan_launch", "afc_plan_info", "afc_plan_destroy",
+           "afc_last_error"]
+
+
+class AfcError(RuntimeError):
+    pass
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise AfcError(f"{what} failed ({rc}): {_lib.afc_last_error().decode()}")
+
+
+def dims(n_antennas: int, n_subbands: int, n_spectra: int, n_channels: int = N_CHANNELS,
+         n_taps: int = N_TAPS) -> Dims:
+    return Dims(n_antennas, 2, n_subbands, n_channels, n_taps, n_spectra)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(device):
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t) -> Optional[C.c_void_p]:
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _require(t, dtype, name):
+    torch = _torch()
+    if not t.is_cuda:
+        raise AfcError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise AfcError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise AfcError(f"{name} must be contiguous")
+    del torch
+
+
+_TORCH_OF = {"f32": "float32", "f16": "float16", "i8": "int8"}
+
+
+def channelised_shape(n_subbands, n_spectra, n_inputs):
+    sb = (n_spectra + SPECTRUM_BLOCK - 1) // SPECTRUM_BLOCK
+    return (n_subbands, N_CHANNELS, sb, n_inputs, SPECTRUM_BLOCK, 2)
+
+
+def channelise(x, taps, n_spectra: int, out_dtype: str = "f32", gain: float = 1.0, out=None):
+    """x int16 [B][L][Na][2][2] (or [B][L][N][2]) -> z [B][P][Sb][N][8][2]."""
+    torch = _torch()
+    _require(x, torch.int16, "x")
+    _require(taps, torch.float32, "taps")
+    B, L = x.shape[0], x.shape[1]
+    N = x[0, 0].numel() // 2
+    Na = N // 2
+    d = dims(Na, B, n_spectra)
+    if L != (n_spectra + N_TAPS - 1) * N_CHANNELS:
+        raise AfcError(f"x has {L} rows, expected (S+T-1)*P = {(n_spectra + N_TAPS - 1) * N_CHANNELS}")
+    shape = channelised_shape(B, n_spectra, N)
+    tdt = getattr(torch, _TORCH_OF[out_dtype])
+    if out is None:
+        out = torch.empty(shape, dtype=tdt, device=x.device)
+    _require(out, tdt, "out")
+    if tuple(out.shape) != shape:
+        raise AfcError(f"out shape {tuple(out.shape)} != {shape}")
+    _check(_lib.afc_channelise(C.byref(d), _ptr(x), _ptr(taps), DTYPES[out_dtype], float(gain), _ptr(out),
+                               _stream(x.device)), "afc_channelise")
+    return out
+
+
+def visibility_shape(n_subbands, n_antennas):
+    return (n_subbands, N_CHANNELS, n_antennas * (n_antennas + 1) // 2, 2, 2, 2)
+
+
+def correlate(z, n_spectra: Optional[int] = None, n_spectra_per_sb: Optional[Sequence[int]] = None,
+              flags=None, want_weights: bool = True, out=None, weights=None):
+    """z [B][P][Sb][N][8][2] -> (vis [B][P][Nbl][2][2][2] float32 or int32, weights [B][Nbl] int32)."""
+    torch = _torch()
+    dt = {torch.float32: "f32", torch.float16: "f16", torch.int8: "i8"}[z.dtype]
+    _require(z, z.dtype, "z")
+    B, P, Sb, N = z.shape[0], z.shape[1], z.shape[2], z.shape[3]
+    if P != N_CHANNELS or z.shape[4] != SPECTRUM_BLOCK or z.shape[5] != 2:
+        raise AfcError(f"z shape {tuple(z.shape)} is not [B][64][Sb][N][8][2]")
+    S = n_spectra if n_spectra is not None else Sb * SPECTRUM_BLOCK
+    if (S + SPECTRUM_BLOCK - 1) // SPECTRUM_BLOCK != Sb:
+        raise AfcError("n_spectra does not match the number of spectrum blocks")
+    Na = N // 2
+    d = dims(Na, B, S)
+    vdt = torch.int32 if dt == "i8" else torch.float32
+    if out is None:
+        out = torch.empty(visibility_shape(B, Na), dtype=vdt, device=z.device)
+    _require(out, vdt, "out")
+    if want_weights and weights is None:
+        weights = torch.empty((B, Na * (Na + 1) // 2), dtype=torch.int32, device=z.device)
+    if weights is not None:
+        _require(weights, torch.int32, "weights")
+    if flags is not None:
+        _require(flags, torch.uint8, "flags")
+        if tuple(flags.shape) != (B, Na):
+            raise AfcError(f"flags shape {tuple(flags.shape)} != {(B, Na)}")
+    sp = None
+    if n_spectra_per_sb is not None:
+        arr = (C.c_int32 * B)(*[int(v) for v in n_spectra_per_sb])
+        sp = C.cast(arr, C.c_void_p)
+    _check(_lib.afc_correlate(C.byref(d), DTYPES[dt], _ptr(z), sp, _ptr(flags), _ptr(out), _ptr(weights),
+                              _stream(z.device)), "afc_correlate")
+    return out, weights
+
+
+def calibrate_grad(V, M, g, want_grad: bool = True, workspace=None):
+    """V, M float32 [P][Nbl][2][2][2]; g float32 [P][Na][2][2] -> (loss float64 [P][2], grad [P][Na][2][2])."""
+    torch = _torch()
+    for t, n in ((V, "V"), (M, "M"), (g, "g")):
+        _require(t, torch.float32, n)
+    P, Na = g.shape[0], g.shape[1]
+    nbl = Na * (Na + 1) // 2
+    if tuple(V.shape) != (P, nbl, 2, 2, 2) or tuple(M.shape) != tuple(V.shape) or tuple(g.shape) != (P, Na, 2, 2):
+        raise AfcError("calibrate_grad: V, M must be [P][Nbl][2][2][2] and g [P][Na][2][2]")
+    loss = torch.empty((P, 2), dtype=torch.float64, device=V.device)
+    grad = torch.empty_like(g) if want_grad else None
+    wsb = _lib.afc_calibrate_workspace_bytes(Na, P)
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=V.device)
+    _check(_lib.afc_calibrate_grad(Na, P, _ptr(V), _ptr(M), _ptr(g), _ptr(loss), _ptr(grad), _ptr(workspace),
+                                   _stream(V.device)), "afc_calibrate_grad")
+    return loss, grad
+
+
+def _make_cal_loss():
+    torch = _torch()
+
+    class CalLoss(torch.autograd.Function):
+        """L[k][pol] = ||V - G M G^H||_F^2 with the hand-written adjoint kernel.
+
+        g is complex64 [P][Na][2]; V, M float32 [P][Nbl][2][2][2].  The
+        forward kernel computes the gradient together with the loss; the
+        backward scales it by the incoming gradient of each (channel, pol).
+        """
+
+        @staticmethod
+        def forward(ctx, V, M, g):
+            gr = torch.view_as_real(g.contiguous())
+            loss, grad = calibrate_grad(V, M, gr, want_grad=True)
+            ctx.save_for_backward(torch.view_as_complex(grad))
+            return loss
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (grad,) = ctx.saved_tensors
+            gg = grad * grad_out.to(torch.float32)[:, None, :]
+            return None, None, gg
+
+    return CalLoss
+
+
+_cal_loss_cls = None
+
+
+def cal_loss(V, M, g):
+    """Differentiable calibration loss [P][2] (float64) with respect to complex g."""
+    global _cal_loss_cls
+    if _cal_loss_cls is None:
+        _cal_loss_cls = _make_cal_loss()
+    return _cal_loss_cls.apply(V, M, g)
+
+
+@dataclass
+class PlanInfo:
+    tile: int
+    n_workgroups: int
+    n_work_items: int
+
+
+class Plan:
+    """Batching form: one graph of one channeliser launch and one persistent correlator launch."""
+
+    def __init__(self, n_antennas: int, n_spectra_per_sb: Sequence[int], dtypes: Sequence[str],
+                 tune_cache: Optional[str] = None, n_spectra: Optional[int] = None):
+        """n_spectra: the row count of x is (n_spectra + 15) * 64 (default max of n_spectra_per_sb)."""
+        B = len(n_spectra_per_sb)
+        self.n_antennas = n_antennas
+        self.S = [int(s) for s in n_spectra_per_sb]
+        self.dtypes = list(dtypes)
+        self.dims = dims(n_antennas, B, max(self.S) if n_spectra is None else int(n_spectra))
+        dt = (C.c_int * B)(*[DTYPES[t] for t in self.dtypes])
+        sp = (C.c_int32 * B)(*self.S)
+        h = C.c_void_p()
+        _check(_lib.afc_plan_create(C.byref(self.dims), C.cast(dt, C.c_void_p), C.cast(sp, C.c_void_p),
+                                    tune_cache.encode() if tune_cache else None, C.byref(h)), "afc_plan_create")
+        self._h = h
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(_lib.afc_plan_workspace_bytes(self._h))
+
+    def info(self) -> PlanInfo:
+        a, b, c, d = _i32(), _i32(), _i32(), _i32()
+        _check(_lib.afc_plan_info(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)), "afc_plan_info")
+        return PlanInfo(a.value, c.value, d.value)
+
+    def launch(self, x, taps, gains, workspace, vis, flags=None, weights=None):
+        torch = _torch()
+        _require(x, torch.int16, "x")
+        _require(taps, torch.float32, "taps")
+        _require(workspace, torch.uint8, "workspace")
+        rows = (self.dims.n_spectra + N_TAPS - 1) * N_CHANNELS
+        if x.shape[0] != len(self.S) or x.shape[1] != rows:
+            raise AfcError(f"x must be [{len(self.S)}][{rows}][..]: got {tuple(x.shape)}")
+        if workspace.numel() < self.workspace_bytes:
+            raise AfcError("workspace too small")
+        B = len(self.S)
+        g = (C.c_float * B)(*[float(v) for v in gains])
+        _check(_lib.afc_plan_launch(self._h, _ptr(x), _ptr(taps), C.cast(g, C.c_void_p), _ptr(workspace),
+                                    _ptr(flags), _ptr(vis), _ptr(weights), _stream(x.device)), "afc_plan_launch")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.afc_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

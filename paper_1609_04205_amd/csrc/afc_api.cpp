@@ -1,0 +1,593 @@
+// C ABI of the FX-correlator library: argument checks, launch set-up, the
+// batching plan (host-balanced persistent work lists, HIP graph replay and
+// the tile tuner).  See include/afc.h for the contract of each entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <queue>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "afc_internal.h"
+
+using namespace afc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(AFC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int check_dims(const afc_dims* d) {
+    if (!d) return fail(AFC_ERR_INVALID, "dims is NULL");
+    if (d->n_antennas < 1) return fail(AFC_ERR_INVALID, "n_antennas = %d < 1", d->n_antennas);
+    if (d->n_pols != 2) return fail(AFC_ERR_UNSUPPORTED, "n_pols = %d (only 2 is built)", d->n_pols);
+    if (d->n_subbands < 1 || d->n_subbands > AFC_MAX_SUBBANDS)
+        return fail(AFC_ERR_INVALID, "n_subbands = %d outside 1..%d", d->n_subbands, AFC_MAX_SUBBANDS);
+    if (d->n_channels != kP) return fail(AFC_ERR_UNSUPPORTED, "n_channels = %d (only 64 is built)", d->n_channels);
+    if (d->n_taps != kT) return fail(AFC_ERR_UNSUPPORTED, "n_taps = %d (only 16 is built)", d->n_taps);
+    if (d->n_spectra < 1) return fail(AFC_ERR_INVALID, "n_spectra = %d < 1", d->n_spectra);
+    const int64_t N = 2LL * d->n_antennas;
+    const int64_t L = ((int64_t)d->n_spectra + kT - 1) * kP;
+    if (L * N * 2 >= (1LL << 31))
+        return fail(AFC_ERR_UNSUPPORTED, "one subband of input holds %lld int16 values (limit 2^31)",
+                    (long long)(L * N * 2));
+    if (N > 8192) return fail(AFC_ERR_UNSUPPORTED, "n_antennas = %d > 4096", d->n_antennas);
+    return AFC_OK;
+}
+
+bool dtype_ok(afc_dtype t) { return t == AFC_F32 || t == AFC_F16 || t == AFC_I8; }
+
+int64_t blocks_of(int64_t S) { return ceil_div(S, kSBlk); }
+
+// samples of one subband of z
+int64_t z_sb_samples(int64_t N, int64_t S) { return (int64_t)kP * blocks_of(S) * N * kSBlk; }
+
+int64_t nbl_of(int64_t Na) { return Na * (Na + 1) / 2; }
+
+}  // namespace
+
+extern "C" {
+
+AFC_API const char* afc_last_error(void) { return g_err.c_str(); }
+
+AFC_API size_t afc_channelised_bytes(const afc_dims* d, afc_dtype dt) {
+    if (check_dims(d) != AFC_OK || !dtype_ok(dt)) return 0;
+    return (size_t)d->n_subbands * z_sb_samples(2LL * d->n_antennas, d->n_spectra) * sample_bytes(dt);
+}
+
+AFC_API size_t afc_visibility_bytes(const afc_dims* d) {
+    if (check_dims(d) != AFC_OK) return 0;
+    return (size_t)d->n_subbands * kP * nbl_of(d->n_antennas) * 4 * 8;
+}
+
+AFC_API int afc_channelise(const afc_dims* d, const int16_t* x, const float* taps, afc_dtype out_dtype,
+                           float requant_gain, void* out, hipStream_t stream) {
+    g_err.clear();
+    int rc = check_dims(d);
+    if (rc != AFC_OK) return rc;
+    if (!x || !taps || !out) return fail(AFC_ERR_INVALID, "NULL pointer (x, taps or out)");
+    if (!dtype_ok(out_dtype)) return fail(AFC_ERR_INVALID, "unknown out_dtype %d", (int)out_dtype);
+    if (out_dtype == AFC_I8 && !(std::isfinite(requant_gain) && requant_gain > 0.0f))
+        return fail(AFC_ERR_INVALID, "requant_gain must be finite and > 0 for AFC_I8");
+    const int64_t N = 2LL * d->n_antennas;
+    const int64_t z_sb = z_sb_samples(N, d->n_spectra);
+    if (z_sb * sample_bytes(out_dtype) >= (1LL << 40)) return fail(AFC_ERR_UNSUPPORTED, "output too large");
+    PpfLaunch a{};
+    a.x = x;
+    a.taps = taps;
+    a.z = out;
+    a.x_sb_stride = ((int64_t)d->n_spectra + kT - 1) * kP * N * 2;
+    a.z_sb_stride = z_sb;
+    a.N = (int)N;
+    a.S = d->n_spectra;
+    a.Sb = (int)blocks_of(d->n_spectra);
+    a.B = d->n_subbands;
+    a.gain = requant_gain;
+    a.dt = out_dtype;
+    hipError_t e = launch_ppf(a, stream);
+    if (e != hipSuccess) return hip_fail(e, "channeliser launch");
+    return AFC_OK;
+}
+
+AFC_API int afc_correlate(const afc_dims* d, afc_dtype in_dtype, const void* z, const int32_t* n_spectra_per_sb,
+                          const uint8_t* flags, void* vis, int32_t* weights, hipStream_t stream) {
+    g_err.clear();
+    int rc = check_dims(d);
+    if (rc != AFC_OK) return rc;
+    if (!z || !vis) return fail(AFC_ERR_INVALID, "NULL pointer (z or vis)");
+    if (!dtype_ok(in_dtype)) return fail(AFC_ERR_INVALID, "unknown in_dtype %d", (int)in_dtype);
+    std::vector<int32_t> S(d->n_subbands, d->n_spectra);
+    if (n_spectra_per_sb) {
+        for (int b = 0; b < d->n_subbands; ++b) {
+            if (n_spectra_per_sb[b] < 1 || n_spectra_per_sb[b] > d->n_spectra)
+                return fail(AFC_ERR_INVALID, "n_spectra_per_sb[%d] = %d outside 1..%d", b, n_spectra_per_sb[b],
+                            d->n_spectra);
+            S[b] = n_spectra_per_sb[b];
+        }
+    }
+    if (in_dtype == AFC_I8) {
+        for (int b = 0; b < d->n_subbands; ++b)
+            if (2LL * 127 * 127 * S[b] >= (1LL << 31))
+                return fail(AFC_ERR_UNSUPPORTED, "int8 sums over %d spectra may overflow int32", S[b]);
+    }
+    const int64_t N = 2LL * d->n_antennas;
+    XLaunch a{};
+    a.z = z;
+    a.vis = vis;
+    a.weights = weights;
+    a.flags = flags;
+    a.Sb = (int)blocks_of(d->n_spectra);
+    a.z_ch_stride = (int64_t)a.Sb * N * kSBlk;
+    a.z_sb_stride = a.z_ch_stride * kP;
+    a.N = (int)N;
+    a.Na = d->n_antennas;
+    a.B = d->n_subbands;
+    a.S_host = S.data();
+    a.dt = in_dtype;
+    hipError_t e = launch_xengine(a, stream);
+    if (e != hipSuccess) return hip_fail(e, "correlator launch");
+    return AFC_OK;
+}
+
+AFC_API size_t afc_calibrate_workspace_bytes(int32_t n_antennas, int32_t n_channels) {
+    if (n_antennas < 1 || n_antennas > 4096 || n_channels < 1) return 0;
+    return cal_workspace_bytes(n_antennas, n_channels);
+}
+
+AFC_API int afc_calibrate_grad(int32_t n_antennas, int32_t n_channels, const void* V, const void* M, const void* g,
+                               double* loss, void* grad, void* workspace, hipStream_t stream) {
+    g_err.clear();
+    if (n_antennas < 1 || n_antennas > 4096) return fail(AFC_ERR_INVALID, "n_antennas = %d outside 1..4096", n_antennas);
+    if (n_channels < 1 || n_channels > 65535) return fail(AFC_ERR_INVALID, "n_channels = %d outside 1..65535", n_channels);
+    if (!V || !M || !g || !loss) return fail(AFC_ERR_INVALID, "NULL pointer (V, M, g or loss)");
+    if (!workspace) return fail(AFC_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)",
+                                cal_workspace_bytes(n_antennas, n_channels));
+    hipError_t e = launch_calibrate(n_antennas, n_channels, reinterpret_cast<const float2*>(V),
+                                    reinterpret_cast<const float2*>(M), reinterpret_cast<const float2*>(g), loss,
+                                    reinterpret_cast<float2*>(grad), workspace, stream);
+    if (e != hipSuccess) return hip_fail(e, "calibration launch");
+    return AFC_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batching plan
+// ---------------------------------------------------------------------------
+struct afc_plan {
+    afc_dims d{};
+    std::vector<int32_t> dt, S;
+    std::vector<int64_t> z_off;
+    size_t ws_bytes = 0;
+    int N = 0, Na = 0;
+    int64_t L = 0;
+    // device tables
+    PpfItem* d_items = nullptr;
+    XSubband* d_sbs = nullptr;
+    struct Mode {
+        bool used = false;
+        int tile = 128;
+        int n_wg = 0;
+        int n_items = 0;
+        XWork* d_work = nullptr;
+        int32_t* d_begin = nullptr;
+    } mode[2];
+    std::vector<PpfItem> items;
+    // graph
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<const void*> key_ptrs;
+    std::vector<float> key_gains;
+};
+
+namespace {
+
+int num_cus() {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return 256;
+    return std::max(1, p.multiProcessorCount);
+}
+
+// Cost of one tile item in MFMA cycles per spectrum (per SIMD), from the
+// instruction rates: int8 32x32x32 and fp16 32x32x16 take the same cycles,
+// int8 covers twice the spectra; fp32 32x32x2 covers one spectrum per pair.
+double tile_cost(int dt, int tile, int S, bool diag) {
+    const double blocks = (tile / 32.0) * (tile / 32.0) * (diag ? 10.0 / 16.0 : 1.0);
+    const double per_spec = dt == AFC_I8 ? 4.0 : dt == AFC_F16 ? 8.0 : 128.0;   // cycles per 32x32 block-spectrum
+    return blocks * per_spec * S + 2000.0;                                      // + fixed cost (epilogue)
+}
+
+// Build a balanced work list for one mode: groups (subband, channel) are
+// spread over the XCDs, then the tiles of each group over the workgroups of
+// its XCD, longest-processing-time first, in group order.
+void build_work(const afc_plan& p, int m, int tile, int n_wg, std::vector<XWork>& work_out,
+                std::vector<int32_t>& begin_out) {
+    const int nT = (int)ceil_div(p.N, tile);
+    struct G {
+        int sb, ch;
+        double cost;
+    };
+    std::vector<G> groups;
+    for (int b = 0; b < p.d.n_subbands; ++b) {
+        const bool in_mode = m == 0 ? (p.dt[b] == AFC_I8 || p.dt[b] == AFC_F16) : p.dt[b] == AFC_F32;
+        if (!in_mode) continue;
+        double c = 0;
+        for (int ti = 0; ti < nT; ++ti)
+            for (int tj = 0; tj <= ti; ++tj) c += tile_cost(p.dt[b], tile, p.S[b], ti == tj);
+        for (int ch = 0; ch < kP; ++ch) groups.push_back({b, ch, c});
+    }
+    const int n_xcd = 8;
+    std::vector<double> xload(n_xcd, 0.0);
+    std::vector<std::vector<int>> xgroups(n_xcd);
+    std::vector<int> order(groups.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return groups[a].cost > groups[b].cost; });
+    for (int gi : order) {
+        int best = (int)(std::min_element(xload.begin(), xload.end()) - xload.begin());
+        xload[best] += groups[gi].cost;
+        xgroups[best].push_back(gi);
+    }
+    std::vector<std::vector<XWork>> per_wg(n_wg);
+    for (int x = 0; x < n_xcd; ++x) {
+        std::vector<int> wgs;
+        for (int w = x; w < n_wg; w += n_xcd) wgs.push_back(w);
+        if (wgs.empty()) continue;
+        using E = std::pair<double, int>;
+        std::priority_queue<E, std::vector<E>, std::greater<E>> heap;
+        for (int w : wgs) heap.push({0.0, w});
+        for (int gi : xgroups[x]) {
+            const G& g = groups[gi];
+            std::vector<std::pair<double, XWork>> tiles;
+            for (int ti = 0; ti < nT; ++ti)
+                for (int tj = 0; tj <= ti; ++tj)
+                    tiles.push_back({tile_cost(p.dt[g.sb], tile, p.S[g.sb], ti == tj), XWork{g.sb, g.ch, ti, tj}});
+            std::stable_sort(tiles.begin(), tiles.end(),
+                             [](const auto& a, const auto& b) { return a.first > b.first; });
+            for (auto& t : tiles) {
+                E e = heap.top();
+                heap.pop();
+                per_wg[e.second].push_back(t.second);
+                heap.push({e.first + t.first, e.second});
+            }
+        }
+    }
+    work_out.clear();
+    begin_out.assign(n_wg + 1, 0);
+    for (int w = 0; w < n_wg; ++w) {
+        begin_out[w] = (int32_t)work_out.size();
+        work_out.insert(work_out.end(), per_wg[w].begin(), per_wg[w].end());
+    }
+    begin_out[n_wg] = (int32_t)work_out.size();
+}
+
+int upload_mode(afc_plan* p, int m, int tile, int n_wg) {
+    afc_plan::Mode& md = p->mode[m];
+    std::vector<XWork> work;
+    std::vector<int32_t> begin;
+    build_work(*p, m, tile, n_wg, work, begin);
+    if (md.d_work) hipFree(md.d_work);
+    if (md.d_begin) hipFree(md.d_begin);
+    md.d_work = nullptr;
+    md.d_begin = nullptr;
+    md.used = !work.empty();
+    md.tile = tile;
+    md.n_wg = n_wg;
+    md.n_items = (int)work.size();
+    if (!md.used) return AFC_OK;
+    hipError_t e = hipMalloc(&md.d_work, work.size() * sizeof(XWork));
+    if (e == hipSuccess) e = hipMalloc(&md.d_begin, begin.size() * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemcpy(md.d_work, work.data(), work.size() * sizeof(XWork), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(md.d_begin, begin.data(), begin.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "plan work upload");
+    return AFC_OK;
+}
+
+std::string tune_key(const afc_plan& p) {
+    int n8 = 0, n16 = 0, n32 = 0;
+    int smin = 1 << 30, smax = 0;
+    for (int b = 0; b < p.d.n_subbands; ++b) {
+        n8 += p.dt[b] == AFC_I8;
+        n16 += p.dt[b] == AFC_F16;
+        n32 += p.dt[b] == AFC_F32;
+        smin = std::min(smin, p.S[b]);
+        smax = std::max(smax, p.S[b]);
+    }
+    std::ostringstream o;
+    o << "N" << p.N << "_i8x" << n8 << "_f16x" << n16 << "_f32x" << n32 << "_S" << smin << "-" << smax;
+    return o.str();
+}
+
+// The tune cache is a flat JSON object {"key": [tile, wg_per_cu], ...}.
+std::map<std::string, std::pair<int, int>> read_cache(const char* path) {
+    std::map<std::string, std::pair<int, int>> m;
+    std::ifstream f(path);
+    if (!f) return m;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string s = ss.str();
+    size_t i = 0;
+    while ((i = s.find('"', i)) != std::string::npos) {
+        const size_t j = s.find('"', i + 1);
+        if (j == std::string::npos) break;
+        const std::string key = s.substr(i + 1, j - i - 1);
+        const size_t lb = s.find('[', j), rb = s.find(']', j);
+        if (lb == std::string::npos || rb == std::string::npos) break;
+        int a = 0, b = 0;
+        if (sscanf(s.c_str() + lb, "[%d,%d]", &a, &b) == 2 || sscanf(s.c_str() + lb, "[ %d , %d ]", &a, &b) == 2)
+            m[key] = {a, b};
+        i = rb + 1;
+    }
+    return m;
+}
+
+void write_cache(const char* path, const std::map<std::string, std::pair<int, int>>& m) {
+    std::ofstream f(path);
+    f << "{\n";
+    size_t k = 0;
+    for (const auto& kv : m) {
+        f << "  \"" << kv.first << "\": [" << kv.second.first << ", " << kv.second.second << "]"
+          << (++k < m.size() ? ",\n" : "\n");
+    }
+    f << "}\n";
+}
+
+// Time the int8/fp16 persistent correlator of the plan's own work for each
+// candidate (tile, workgroups per CU) on scratch buffers; returns the best.
+int tune_mode0(afc_plan* p, int& tile_out, int& wg_per_cu_out) {
+    const int cus = num_cus();
+    const int cands[][2] = {{128, 2}, {128, 1}, {64, 2}, {64, 4}};
+    size_t vis_bytes = (size_t)p->d.n_subbands * kP * nbl_of(p->Na) * 32;
+    void* z = nullptr;
+    void* vis = nullptr;
+    hipError_t e = hipMalloc(&z, std::max<size_t>(p->ws_bytes, 256));
+    if (e == hipSuccess) e = hipMalloc(&vis, vis_bytes);
+    if (e != hipSuccess) {
+        if (z) hipFree(z);
+        return hip_fail(e, "tuner scratch allocation");
+    }
+    hipMemset(z, 0, p->ws_bytes);
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    float best = 1e30f;
+    tile_out = 128;
+    wg_per_cu_out = 2;
+    for (const auto& c : cands) {
+        int rc = upload_mode(p, 0, c[0], cus * c[1]);
+        if (rc != AFC_OK) break;
+        const afc_plan::Mode& md = p->mode[0];
+        float tmin = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            hipEventRecord(e0, nullptr);
+            launch_xengine_persistent(z, vis, nullptr, nullptr, p->d_sbs, md.d_work, md.d_begin, md.n_wg, p->N, p->Na,
+                                      0, md.tile, nullptr);
+            hipEventRecord(e1, nullptr);
+            hipEventSynchronize(e1);
+            float ms = 0;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) tmin = std::min(tmin, ms);
+        }
+        if (tmin < best) {
+            best = tmin;
+            tile_out = c[0];
+            wg_per_cu_out = c[1];
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(z);
+    hipFree(vis);
+    return AFC_OK;
+}
+
+void plan_free_graph(afc_plan* p) {
+    if (p->exec) hipGraphExecDestroy(p->exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+AFC_API int afc_plan_create(const afc_dims* d, const afc_dtype* dtype_per_sb, const int32_t* n_spectra_per_sb,
+                            const char* tune_cache_path, afc_plan** out) {
+    g_err.clear();
+    if (!out) return fail(AFC_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    int rc = check_dims(d);
+    if (rc != AFC_OK) return rc;
+    if (!dtype_per_sb || !n_spectra_per_sb) return fail(AFC_ERR_INVALID, "dtype_per_sb and n_spectra_per_sb are required");
+    afc_plan* p = new afc_plan();
+    p->d = *d;
+    p->N = 2 * d->n_antennas;
+    p->Na = d->n_antennas;
+    p->L = ((int64_t)d->n_spectra + kT - 1) * kP;
+    const int B = d->n_subbands;
+    p->dt.resize(B);
+    p->S.resize(B);
+    p->z_off.resize(B);
+    int64_t off = 0;
+    for (int b = 0; b < B; ++b) {
+        if (!dtype_ok(dtype_per_sb[b])) {
+            delete p;
+            return fail(AFC_ERR_INVALID, "dtype_per_sb[%d] = %d unknown", b, (int)dtype_per_sb[b]);
+        }
+        if (n_spectra_per_sb[b] < 1 || n_spectra_per_sb[b] > d->n_spectra) {
+            delete p;
+            return fail(AFC_ERR_INVALID, "n_spectra_per_sb[%d] = %d outside 1..%d", b, n_spectra_per_sb[b], d->n_spectra);
+        }
+        if (dtype_per_sb[b] == AFC_I8 && 2LL * 127 * 127 * n_spectra_per_sb[b] >= (1LL << 31)) {
+            delete p;
+            return fail(AFC_ERR_UNSUPPORTED, "int8 sums over %d spectra may overflow int32", n_spectra_per_sb[b]);
+        }
+        p->dt[b] = dtype_per_sb[b];
+        p->S[b] = n_spectra_per_sb[b];
+        p->z_off[b] = off;
+        off += z_sb_samples(p->N, p->S[b]) * sample_bytes((afc_dtype)p->dt[b]);
+        off = (off + 255) / 256 * 256;
+    }
+    p->ws_bytes = (size_t)off;
+    // per-subband tables
+    std::vector<XSubband> sbs(B);
+    p->items.resize(B);
+    const int64_t nbl = nbl_of(p->Na);
+    for (int b = 0; b < B; ++b) {
+        sbs[b] = XSubband{p->z_off[b], (int64_t)b * kP * nbl * 32, p->S[b], (int32_t)blocks_of(p->S[b]), p->dt[b], 0};
+        p->items[b] = PpfItem{(int64_t)b * p->L * p->N * 2, p->z_off[b], p->S[b], (int32_t)blocks_of(p->S[b]),
+                              p->dt[b], 1.0f};
+    }
+    hipError_t e = hipMalloc(&p->d_sbs, B * sizeof(XSubband));
+    if (e == hipSuccess) e = hipMalloc(&p->d_items, B * sizeof(PpfItem));
+    if (e == hipSuccess) e = hipMemcpy(p->d_sbs, sbs.data(), B * sizeof(XSubband), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_items, p->items.data(), B * sizeof(PpfItem), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        afc_plan_destroy(p);
+        return hip_fail(e, "plan allocation");
+    }
+    const int cus = num_cus();
+    // int8 / fp16 subbands: tile choice from the tune cache or the tuner
+    bool any0 = false, any1 = false;
+    for (int b = 0; b < B; ++b) {
+        any0 |= p->dt[b] != AFC_F32;
+        any1 |= p->dt[b] == AFC_F32;
+    }
+    if (any0) {
+        int tile = 128, wpc = 2;
+        if (tune_cache_path && *tune_cache_path) {
+            auto cache = read_cache(tune_cache_path);
+            const std::string key = tune_key(*p);
+            auto it = cache.find(key);
+            if (it != cache.end() && (it->second.first == 64 || it->second.first == 128) && it->second.second >= 1 &&
+                it->second.second <= 8) {
+                tile = it->second.first;
+                wpc = it->second.second;
+            } else {
+                rc = tune_mode0(p, tile, wpc);
+                if (rc != AFC_OK) {
+                    afc_plan_destroy(p);
+                    return rc;
+                }
+                cache[key] = {tile, wpc};
+                write_cache(tune_cache_path, cache);
+            }
+        }
+        rc = upload_mode(p, 0, tile, cus * wpc);
+        if (rc != AFC_OK) {
+            afc_plan_destroy(p);
+            return rc;
+        }
+    }
+    if (any1) {
+        rc = upload_mode(p, 1, 64, cus * 2);
+        if (rc != AFC_OK) {
+            afc_plan_destroy(p);
+            return rc;
+        }
+    }
+    *out = p;
+    return AFC_OK;
+}
+
+AFC_API size_t afc_plan_workspace_bytes(const afc_plan* p) { return p ? p->ws_bytes : 0; }
+
+AFC_API int afc_plan_info(const afc_plan* p, int32_t* tile_rows, int32_t* tile_cols, int32_t* n_workgroups,
+                          int32_t* n_work_items) {
+    if (!p) return fail(AFC_ERR_INVALID, "plan is NULL");
+    const afc_plan::Mode& md = p->mode[0].used ? p->mode[0] : p->mode[1];
+    if (tile_rows) *tile_rows = md.tile;
+    if (tile_cols) *tile_cols = md.tile;
+    if (n_workgroups) *n_workgroups = md.n_wg;
+    if (n_work_items) *n_work_items = p->mode[0].n_items + p->mode[1].n_items;
+    return AFC_OK;
+}
+
+AFC_API int afc_plan_launch(afc_plan* p, const int16_t* x, const float* taps, const float* gain_per_sb,
+                            void* z_workspace, const uint8_t* flags, void* vis, int32_t* weights, hipStream_t stream) {
+    g_err.clear();
+    if (!p) return fail(AFC_ERR_INVALID, "plan is NULL");
+    if (!x || !taps || !z_workspace || !vis) return fail(AFC_ERR_INVALID, "NULL pointer (x, taps, workspace or vis)");
+    const int B = p->d.n_subbands;
+    std::vector<float> gains(B, 1.0f);
+    for (int b = 0; b < B; ++b) {
+        if (p->dt[b] == AFC_I8) {
+            if (!gain_per_sb) return fail(AFC_ERR_INVALID, "gain_per_sb is required with int8 subbands");
+            if (!(std::isfinite(gain_per_sb[b]) && gain_per_sb[b] > 0.0f))
+                return fail(AFC_ERR_INVALID, "gain_per_sb[%d] must be finite and > 0", b);
+            gains[b] = gain_per_sb[b];
+        }
+    }
+    const std::vector<const void*> key = {x, taps, z_workspace, flags, vis, weights};
+    const bool same = p->exec && key == p->key_ptrs && gains == p->key_gains;
+    hipError_t e;
+    if (!same) {
+        plan_free_graph(p);
+        for (int b = 0; b < B; ++b) p->items[b].gain = gains[b];
+        e = hipMemcpy(p->d_items, p->items.data(), B * sizeof(PpfItem), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "plan gain upload");
+        e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "graph capture begin");
+        hipError_t le = launch_ppf_batched(x, taps, z_workspace, p->d_items, B, p->N, p->d.n_spectra, p->cap_stream);
+        for (int m = 0; m < 2 && le == hipSuccess; ++m) {
+            const afc_plan::Mode& md = p->mode[m];
+            if (!md.used) continue;
+            le = launch_xengine_persistent(z_workspace, vis, weights, flags, p->d_sbs, md.d_work, md.d_begin, md.n_wg,
+                                           p->N, p->Na, m, md.tile, p->cap_stream);
+        }
+        e = hipStreamEndCapture(p->cap_stream, &p->graph);
+        if (le != hipSuccess) {
+            plan_free_graph(p);
+            return hip_fail(le, "plan kernel launch during capture");
+        }
+        if (e != hipSuccess) return hip_fail(e, "graph capture end");
+        e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            plan_free_graph(p);
+            return hip_fail(e, "graph instantiate");
+        }
+        p->key_ptrs = key;
+        p->key_gains = gains;
+    }
+    e = hipGraphLaunch(p->exec, stream);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    return AFC_OK;
+}
+
+AFC_API void afc_plan_destroy(afc_plan* p) {
+    if (!p) return;
+    plan_free_graph(p);
+    for (auto& md : p->mode) {
+        if (md.d_work) hipFree(md.d_work);
+        if (md.d_begin) hipFree(md.d_begin);
+    }
+    if (p->d_items) hipFree(p->d_items);
+    if (p->d_sbs) hipFree(p->d_sbs);
+    if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+    delete p;
+}
+
+}  // extern "C"

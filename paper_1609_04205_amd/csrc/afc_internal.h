@@ -1,0 +1,86 @@
+// Internal declarations shared by the kernels and the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "afc.h"
+
+namespace afc {
+
+constexpr int kP = 64;                 // channels
+constexpr int kT = 16;                 // taps per branch
+constexpr int kSBlk = AFC_SPECTRUM_BLOCK;
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int sample_bytes(afc_dtype t) { return t == AFC_F32 ? 8 : t == AFC_F16 ? 4 : 2; }
+
+// ---------------------------------------------------------------- PPF
+struct PpfLaunch {
+    const int16_t* x;       // subband 0 base
+    const float* taps;      // [T*P]
+    void* z;                // subband 0 base of the channelised output
+    int64_t x_sb_stride;    // int16 elements between subbands
+    int64_t z_sb_stride;    // samples between subbands (complex elements)
+    int N;                  // receivers
+    int S;                  // spectra (per subband, same for all in one launch)
+    int Sb;                 // blocks allocated per channel
+    int B;                  // subbands
+    float gain;
+    afc_dtype dt;
+};
+hipError_t launch_ppf(const PpfLaunch& a, hipStream_t stream);
+
+// Per-subband descriptor for the batched channeliser.
+struct PpfItem {
+    int64_t x_off;          // int16 elements from x base to this subband
+    int64_t z_off;          // bytes from workspace base to this subband
+    int32_t S;              // spectra
+    int32_t Sb;             // blocks allocated
+    int32_t dt;             // afc_dtype
+    float gain;
+};
+hipError_t launch_ppf_batched(const int16_t* x, const float* taps, void* z_ws, const PpfItem* items_dev,
+                              int n_items, int N, int max_S, hipStream_t stream);
+
+// ---------------------------------------------------------------- X-engine
+struct XLaunch {
+    const void* z;          // subband 0 base
+    void* vis;              // subband 0 base
+    int32_t* weights;       // or nullptr
+    const uint8_t* flags;   // [B][Na] or nullptr
+    int64_t z_ch_stride;    // samples between channels
+    int64_t z_sb_stride;    // samples between subbands
+    int N, Na, Sb, B;
+    const int32_t* S_host;  // [B] host
+    afc_dtype dt;
+};
+hipError_t launch_xengine(const XLaunch& a, hipStream_t stream);
+
+// Batched persistent X-engine work item (one lower-triangle tile of one
+// channel of one subband).
+struct XWork {
+    int32_t sb;             // subband index
+    int32_t ch;             // channel
+    int32_t ti, tj;         // tile row / column (ti >= tj)
+};
+struct XSubband {
+    int64_t z_off;          // bytes from workspace base
+    int64_t vis_off;        // bytes from vis base
+    int32_t S;
+    int32_t Sb;
+    int32_t dt;
+    int32_t pad;
+};
+hipError_t launch_xengine_persistent(const void* z_ws, void* vis, int32_t* weights,
+                                     const uint8_t* flags, const XSubband* sbs_dev,
+                                     const XWork* work_dev, const int32_t* wg_begin_dev,
+                                     int n_wg, int N, int Na, int mode, int tile, hipStream_t stream);
+int xengine_tile(afc_dtype dt);
+
+// ---------------------------------------------------------------- calibration
+size_t cal_workspace_bytes(int Na, int P);
+hipError_t launch_calibrate(int Na, int P, const float2* V, const float2* M, const float2* g,
+                            double* loss, float2* grad, void* ws, hipStream_t stream);
+
+}  // namespace afc

@@ -1,0 +1,218 @@
+// Gain-calibration loss and its gradient with respect to the complex gains.
+// Sec. "Calibration Pipeline": per-channel amplitude and phase calibration of
+// the XX and YY visibilities against a point-source sky model; read here as
+// the least-squares loss
+//
+//   R_ab = V_ab - g_a M_ab conj(g_b),   L = sum_{a,b} |R_ab|^2
+//   grad_a = dL/dRe g_a + i dL/dIm g_a = -2 sum_b [R_ab conj(M_ab) + conj(R_ba) M_ba] g_b
+//
+// With V and M stored as lower triangles (upper = conjugate), R is Hermitian
+// off the diagonal and, for t_ab = R_ab conj(M_ab),
+//   grad_a = -4 [ sum_{b<a} t_ab g_b + sum_{c>a} conj(t_ca) g_c + Re(t_aa) g_a ].
+// Every stored element therefore feeds one row sum (antenna a) and one
+// column sum (antenna b).
+//
+// Pass 1: one workgroup per 64 x 64 antenna tile of the lower triangle, per
+// channel and polarisation.  Each thread owns one column antenna and 16 rows;
+// the residual is formed in float32 with error-free product and sum
+// transformations, so that R keeps full float32 relative accuracy even when
+// V and G M G^H cancel to a few percent.  Row sums (wave reduction) and
+// column sums (LDS reduction) are accumulated in float64 and written to the
+// workspace; the tile's loss is a float32 tree sum.
+// Pass 2: one thread per antenna adds its row and column partials over the
+// tiles in a fixed order (float64) and writes -4 x the sum; the first block
+// of each (channel, polarisation) adds the tile losses in a fixed order.
+// No atomics: the result is bitwise reproducible.
+#include "afc_internal.h"
+
+// The error-free transformations below need every product and sum rounded
+// on its own: this file is compiled with -ffp-contract=off (the fma in
+// two_prod is explicit), and the pragma keeps the intent visible.
+#pragma clang fp contract(off)
+
+namespace afc {
+namespace {
+
+constexpr int kTileA = 64;      // antennas per tile side
+constexpr int kThreads = 256;   // 4 waves: rows r, r+4, ...
+
+struct ff {
+    float hi, lo;
+};
+__device__ __forceinline__ ff two_prod(float a, float b) {
+    const float p = __fmul_rn(a, b);
+    return {p, fmaf(a, b, -p)};
+}
+__device__ __forceinline__ ff two_sum(float a, float b) {
+    const float s = __fadd_rn(a, b);
+    const float bb = __fsub_rn(s, a);
+    const float e = __fadd_rn(__fsub_rn(a, __fsub_rn(s, bb)), __fsub_rn(b, bb));
+    return {s, e};
+}
+// a*b + c*d as hi + lo
+__device__ __forceinline__ ff dot2(float a, float b, float c, float d) {
+    const ff p = two_prod(a, b), q = two_prod(c, d);
+    const ff s = two_sum(p.hi, q.hi);
+    return {s.hi, __fadd_rn(s.lo, __fadd_rn(p.lo, q.lo))};
+}
+
+// R = V - g_a M conj(g_b), each component rounded once to float32.
+__device__ __forceinline__ float2 residual(float2 v, float2 m, float2 ga, float2 gb) {
+    // q = g_a conj(g_b)
+    const ff qr = dot2(ga.x, gb.x, ga.y, gb.y);
+    const ff qi = dot2(ga.y, gb.x, -ga.x, gb.y);
+    // w = q M
+    ff wr = dot2(qr.hi, m.x, -qi.hi, m.y);
+    ff wi = dot2(qr.hi, m.y, qi.hi, m.x);
+    wr.lo = __fadd_rn(wr.lo, __fsub_rn(__fmul_rn(qr.lo, m.x), __fmul_rn(qi.lo, m.y)));
+    wi.lo = __fadd_rn(wi.lo, __fadd_rn(__fmul_rn(qr.lo, m.y), __fmul_rn(qi.lo, m.x)));
+    // R = V - w
+    const ff rr = two_sum(v.x, -wr.hi);
+    const ff ri = two_sum(v.y, -wi.hi);
+    return make_float2(__fadd_rn(rr.hi, __fsub_rn(rr.lo, wr.lo)), __fadd_rn(ri.hi, __fsub_rn(ri.lo, wi.lo)));
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ float wave_sumf(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ void tile_rc(int t, int& ti, int& tj) {
+    int r = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while (r * (r + 1) / 2 > t) --r;
+    while ((r + 1) * (r + 2) / 2 <= t) ++r;
+    ti = r;
+    tj = t - r * (r + 1) / 2;
+}
+
+// workspace layout: rowpart, colpart double2 [P][2][n_tiles][64]; loss float [P][2][n_tiles]
+__global__ __launch_bounds__(kThreads) void cal_tiles_kernel(int Na, int P, int n_tiles, const float2* __restrict__ V,
+                                                             const float2* __restrict__ M, const float2* __restrict__ g,
+                                                             double2* __restrict__ rowpart, double2* __restrict__ colpart,
+                                                             float* __restrict__ losspart) {
+    __shared__ double2 col_lds[4][kTileA];
+    __shared__ float loss_lds[4];
+    const int t = blockIdx.x, ch = blockIdx.y, pol = blockIdx.z;
+    int ti, tj;
+    tile_rc(t, ti, tj);
+    const int tid = threadIdx.x, cb = tid & 63, rg = tid >> 6;
+    const int b = tj * kTileA + cb;
+    const int64_t nbl = (int64_t)Na * (Na + 1) / 2;
+    const float2* Vc = V + (int64_t)ch * nbl * 4 + pol * 3;   // [bl][2][2]: XX at 0, YY at 3
+    const float2* Mc = M + (int64_t)ch * nbl * 4 + pol * 3;
+    const float2* gc = g + (int64_t)ch * Na * 2 + pol;        // [a][2]
+    const float2 gb = b < Na ? gc[(int64_t)b * 2] : make_float2(0.0f, 0.0f);
+
+    double cre = 0.0, cim = 0.0;
+    float lsum = 0.0f;
+    const int64_t slot = ((int64_t)(ch * 2 + pol) * n_tiles + t) * kTileA;
+#pragma unroll 4
+    for (int m = 0; m < kTileA / 4; ++m) {
+        const int r = rg + 4 * m;
+        const int a = ti * kTileA + r;                            // wave-uniform
+        double rre = 0.0, rim = 0.0;
+        if (a < Na) {
+            const float2 ga = gc[(int64_t)a * 2];
+            if (b < Na && b <= a) {
+                const int64_t e = ((int64_t)a * (a + 1) / 2 + b) * 4;
+                const float2 v = Vc[e], mm = Mc[e];
+                const float2 R = residual(v, mm, ga, gb);
+                const float r2 = R.x * R.x + R.y * R.y;
+                lsum += a == b ? r2 : 2.0f * r2;
+                // t = R conj(M)
+                float tr = R.x * mm.x + R.y * mm.y;
+                float tm = R.y * mm.x - R.x * mm.y;
+                if (a == b) tm = 0.0f;                         // diagonal: Re(t) only
+                // row a: t g_b
+                rre = (double)(tr * gb.x - tm * gb.y);
+                rim = (double)(tr * gb.y + tm * gb.x);
+                if (a != b) {                                  // column b: conj(t) g_a
+                    cre += (double)(tr * ga.x + tm * ga.y);
+                    cim += (double)(tr * ga.y - tm * ga.x);
+                }
+            }
+        }
+        rre = wave_sum(rre);
+        rim = wave_sum(rim);
+        if (cb == 0) rowpart[slot + r] = make_double2(rre, rim);
+    }
+    col_lds[rg][cb] = make_double2(cre, cim);
+    lsum = wave_sumf(lsum);
+    if (cb == 0) loss_lds[rg] = lsum;
+    __syncthreads();
+    if (tid < kTileA) {
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            sr += col_lds[w][tid].x;
+            si += col_lds[w][tid].y;
+        }
+        colpart[slot + tid] = make_double2(sr, si);
+    }
+    if (tid == 0) losspart[(int64_t)(ch * 2 + pol) * n_tiles + t] = (loss_lds[0] + loss_lds[1]) + (loss_lds[2] + loss_lds[3]);
+}
+
+__global__ __launch_bounds__(256) void cal_reduce_kernel(int Na, int P, int nT, int n_tiles,
+                                                         const double2* __restrict__ rowpart,
+                                                         const double2* __restrict__ colpart,
+                                                         const float* __restrict__ losspart, double* __restrict__ loss,
+                                                         float2* __restrict__ grad) {
+    const int ch = blockIdx.y, pol = blockIdx.z;
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t base = (int64_t)(ch * 2 + pol) * n_tiles;
+    if (grad && a < Na) {
+        const int ta = a / kTileA, ra = a % kTileA;
+        double sr = 0.0, si = 0.0;
+        for (int tj = 0; tj <= ta; ++tj) {                   // row a: tiles (ta, tj)
+            const double2 v = rowpart[(base + ta * (ta + 1) / 2 + tj) * kTileA + ra];
+            sr += v.x;
+            si += v.y;
+        }
+        for (int ti = ta; ti < nT; ++ti) {                   // column a: tiles (ti, ta)
+            const double2 v = colpart[(base + ti * (ti + 1) / 2 + ta) * kTileA + ra];
+            sr += v.x;
+            si += v.y;
+        }
+        grad[((int64_t)ch * Na + a) * 2 + pol] = make_float2((float)(-4.0 * sr), (float)(-4.0 * si));
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        float s = 0.0f;
+        for (int t = 0; t < n_tiles; ++t) s += losspart[base + t];
+        loss[ch * 2 + pol] = (double)s;
+    }
+}
+
+int n_tiles_side(int Na) { return (int)ceil_div(Na, kTileA); }
+
+}  // namespace
+
+size_t cal_workspace_bytes(int Na, int P) {
+    const int nT = n_tiles_side(Na);
+    const size_t n_tiles = (size_t)nT * (nT + 1) / 2;
+    return (size_t)P * 2 * n_tiles * (2 * kTileA * sizeof(double2) + sizeof(float)) + 256;
+}
+
+hipError_t launch_calibrate(int Na, int P, const float2* V, const float2* M, const float2* g, double* loss,
+                            float2* grad, void* ws, hipStream_t stream) {
+    const int nT = n_tiles_side(Na);
+    const int n_tiles = nT * (nT + 1) / 2;
+    char* w = reinterpret_cast<char*>(ws);
+    double2* rowpart = reinterpret_cast<double2*>(w);
+    double2* colpart = rowpart + (size_t)P * 2 * n_tiles * kTileA;
+    float* losspart = reinterpret_cast<float*>(colpart + (size_t)P * 2 * n_tiles * kTileA);
+    hipLaunchKernelGGL(cal_tiles_kernel, dim3(n_tiles, P, 2), dim3(kThreads), 0, stream, Na, P, n_tiles, V, M, g,
+                       rowpart, colpart, losspart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(cal_reduce_kernel, dim3((unsigned)ceil_div(Na, 256), P, 2), dim3(256), 0, stream, Na, P, nT,
+                       n_tiles, rowpart, colpart, losspart, loss, grad);
+    return hipGetLastError();
+}
+
+}  // namespace afc

@@ -1,0 +1,342 @@
+// Polyphase filter bank (FIR + 64-point FFT) with the corner turn fused into
+// the store.  Sec. "Polyphase Filterbank" (a bank of 16-tap FIR filters per
+// receiver subband stream, then a complex FFT of the filter outputs) and
+// Sec. "Delay, Bandpass Compensation and Transpose Kernel" (exchange of the
+// parallel axis from channels to receivers).
+//
+//   u[s][p] = sum_{t<16} h[t*64 + p] x[(s+t)*64 + p]
+//   y[s][k] = sum_{p<64} u[s][p] exp(-2 pi i k p / 64)
+//
+// Mapping (one workgroup = 16 receivers x a run of spectra, 16 waves):
+//  * FIR phase: wave w owns the four branches p = w + 16 j (j = 0..3).  Lane
+//    (il, jh, c) owns real component c of receiver i0 + il for the two
+//    branches j = 2 jh, 2 jh + 1.  The 16-deep window of each branch lives in
+//    registers and slides by one sample per spectrum; loads are coalesced
+//    rows of the time-major input.
+//  * The first radix-4 stage of the FFT (over j) runs in registers after two
+//    DPP exchanges inside each lane quad (partner component, partner branch
+//    pair); each quad lane then owns one k1 and applies the twiddle
+//    exp(-2 pi i p1 k1 / 64).  Results go to LDS as [spectrum][k1][p1][il]
+//    for 16 spectra.
+//  * FFT phase: a lane owns (receiver, spectrum, k1) and does the remaining
+//    16-point FFT over p1 in registers (radix-4 x radix-4), producing
+//    channels k = k1 + 4 k2.  Lanes are ordered so that each store writes
+//    8 receivers x 8 spectra contiguously in the [k][block][receiver][slot]
+//    output layout.
+#include <hip/hip_fp16.h>
+
+#include "afc_internal.h"
+
+namespace afc {
+namespace {
+
+constexpr int kNi = 16;                      // receivers per workgroup
+constexpr int kThreads = 1024;               // 16 waves
+constexpr int kKStride = 16 * 16 + 8;        // float2 per k1 row (+64 B: k1 rows start 16 banks apart)
+constexpr int kSStride = 4 * kKStride + 4;   // float2 per spectrum (+32 B: spectra start 8 banks apart)
+constexpr int kSpectraPerPhase = 16;
+constexpr int kChunk = 768;                  // spectra per workgroup, a multiple of 16
+
+struct Tw64 {
+    float2 w[64];                            // exp(-2 pi i m / 64), rounded from double on the host
+};
+
+__device__ __forceinline__ float2 operator+(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 operator-(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// 4-point DFT in place, natural order: X_k = sum_n x_n (-i)^{nk}.
+__device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2& x3) {
+    const float2 t0 = x0 + x2, t1 = x0 - x2, t2 = x1 + x3, t3 = x1 - x3;
+    x0 = t0 + t2;
+    x2 = t0 - t2;
+    x1 = make_float2(t1.x + t3.y, t1.y - t3.x);   // t1 - i t3
+    x3 = make_float2(t1.x - t3.y, t1.y + t3.x);   // t1 + i t3
+}
+
+// 16-point DFT, Y[k] = sum_n a[n] exp(-2 pi i n k / 16), as 4 x 4 with
+// n = al + 4 be, k = ga + 4 de.  On return Y[ga + 4 de] is in a[4 ga + de].
+__device__ __forceinline__ void dft16(float2 (&a)[16]) {
+    constexpr float c8 = 0.92387953251128675613f;   // cos(pi/8)
+    constexpr float s8 = 0.38268343236508977173f;   // sin(pi/8)
+    constexpr float r2 = 0.70710678118654752440f;   // sqrt(1/2)
+#pragma unroll
+    for (int al = 0; al < 4; ++al) dft4(a[al], a[al + 4], a[al + 8], a[al + 12]);
+    // twiddles exp(-2 pi i al ga / 16) on a[al + 4 ga]
+    a[1 + 4] = cmul(a[1 + 4], make_float2(c8, -s8));    // 1
+    a[1 + 8] = cmul(a[1 + 8], make_float2(r2, -r2));    // 2
+    a[1 + 12] = cmul(a[1 + 12], make_float2(s8, -c8));  // 3
+    a[2 + 4] = cmul(a[2 + 4], make_float2(r2, -r2));    // 2
+    a[2 + 8] = make_float2(a[2 + 8].y, -a[2 + 8].x);    // 4: -i
+    a[2 + 12] = cmul(a[2 + 12], make_float2(-r2, -r2)); // 6
+    a[3 + 4] = cmul(a[3 + 4], make_float2(s8, -c8));    // 3
+    a[3 + 8] = cmul(a[3 + 8], make_float2(-r2, -r2));   // 6
+    a[3 + 12] = cmul(a[3 + 12], make_float2(-c8, s8));  // 9
+#pragma unroll
+    for (int ga = 0; ga < 4; ++ga) dft4(a[4 * ga], a[4 * ga + 1], a[4 * ga + 2], a[4 * ga + 3]);
+}
+
+__device__ __forceinline__ float swap_comp(float v) {
+    // quad_perm(1,0,3,2): exchange with the neighbouring lane (other component)
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float swap_pair(float v) {
+    // quad_perm(2,3,0,1): exchange with the lane two away (other branch pair)
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ int requant1(float y, float gain) {
+    float v = y * gain;                       // one float32 product
+    float r = rintf(v);                       // nearest, ties to even
+    r = fminf(fmaxf(r, -127.0f), 127.0f);
+    return (int)r;
+}
+
+// store at sample index base + off (base wave-uniform, off per lane)
+template <int DT>
+__device__ __forceinline__ void store_sample(void* zs, int64_t base, int off, float2 y, float gain) {
+    if constexpr (DT == AFC_F32) {
+        (reinterpret_cast<float2*>(zs) + base)[off] = y;
+    } else if constexpr (DT == AFC_F16) {
+        (reinterpret_cast<__half2*>(zs) + base)[off] = __floats2half2_rn(y.x, y.y);
+    } else {
+        const int qr = requant1(y.x, gain), qi = requant1(y.y, gain);
+        (reinterpret_cast<uint16_t*>(zs) + base)[off] = (uint16_t)((qr & 0xFF) | ((qi & 0xFF) << 8));
+    }
+}
+
+
+// One workgroup: receivers [i0, i0+16) of one subband, spectra [s_begin, s_end).
+template <int DT>
+__device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const float* __restrict__ taps,
+                                         void* __restrict__ zs, const Tw64& tw, int N, int S, int Sb,
+                                         int i0, int s_begin, int s_end, float gain, float2* lds,
+                                         float* ltaps) {
+    const int tid = threadIdx.x;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+
+    // ---- FIR-phase roles: lane = il * 4 + jh * 2 + comp
+    const int comp = lane & 1, jh = (lane >> 1) & 1, il = lane >> 2;
+    const int rcv = i0 + il;
+    const bool rcv_ok = rcv < N;
+    const int p1 = wv;
+    const int row_stride = N * 2;
+    const int lane_off = (p1 + 32 * jh) * row_stride + rcv * 2 + comp;   // branch p1 + 16 (2 jh) at row 0
+    const int64_t spec_stride = (int64_t)kP * row_stride;               // int16 elements per spectrum row
+
+    // taps staged in LDS as [branch][t]; each FIR phase reloads its 32 taps,
+    // so they do not occupy registers during the FFT phase
+    for (int e = tid; e < kT * kP; e += kThreads) {
+        const int t = e / kP, p = e % kP;
+        ltaps[p * kT + t] = taps[e];
+    }
+    __syncthreads();
+    const float4* tp0 = reinterpret_cast<const float4*>(ltaps + (p1 + 32 * jh) * kT);
+    const float4* tp1 = reinterpret_cast<const float4*>(ltaps + (p1 + 32 * jh + 16) * kT);
+
+    // this quad lane produces k1 = comp + 2 jh
+    const int k1o = comp + 2 * jh;
+    // (uniform loads of the four candidates, then a per-lane select)
+    const float2 tw1 = tw.w[p1 & 63], tw2 = tw.w[(2 * p1) & 63], tw3 = tw.w[(3 * p1) & 63];
+    const float2 tw_o = k1o == 0 ? make_float2(1.0f, 0.0f) : k1o == 1 ? tw1 : k1o == 2 ? tw2 : tw3;
+    const float sgn = (k1o & 1) ? -1.0f : 1.0f;
+
+    // sample x_p[m] of branch p1 + 16 (2 jh + jj) at spectrum-row m
+    // (wave-uniform 64-bit row pointer + 32-bit lane offset)
+    auto ld = [&](int m, int jj) -> float {
+        const int16_t* rowp = xs + (int64_t)m * spec_stride;
+        return rcv_ok ? (float)rowp[jj * (16 * row_stride) + lane_off] : 0.0f;
+    };
+
+    // history: window slot m % 16 holds x_p[m]; s_begin is a multiple of 16
+    float win[2][16];
+#pragma unroll
+    for (int m = 0; m < 15; ++m)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) win[jj][m] = ld(s_begin + m, jj);
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) win[jj][15] = 0.0f;
+
+    // ---- FFT-phase roles
+    const int k1 = wv & 3, rh = (wv >> 2) & 1, bh = wv >> 3;
+    const int sl = lane & 7, ii = lane >> 3;
+    const int ilf = rh * 8 + ii;
+    const int rf = i0 + ilf;
+
+    // two-deep software pipeline of the per-spectrum loads
+    float pf[2][2];
+    auto fetch = [&](int s, float (&dst)[2]) {
+        if (s < S) {
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj) dst[jj] = ld(s + 15, jj);
+        } else {
+            dst[0] = dst[1] = 0.0f;
+        }
+    };
+    fetch(s_begin, pf[0]);
+    fetch(s_begin + 1, pf[1]);
+
+    for (int sg = s_begin; sg < s_end; sg += kSpectraPerPhase) {
+        float h[2][16];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const float4 a0 = tp0[v], a1 = tp1[v];
+            h[0][4 * v] = a0.x; h[0][4 * v + 1] = a0.y; h[0][4 * v + 2] = a0.z; h[0][4 * v + 3] = a0.w;
+            h[1][4 * v] = a1.x; h[1][4 * v + 1] = a1.y; h[1][4 * v + 2] = a1.z; h[1][4 * v + 3] = a1.w;
+        }
+#pragma unroll
+        for (int q = 0; q < kSpectraPerPhase; ++q) {
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj) win[jj][(q + 15) & 15] = pf[q & 1][jj];
+            fetch(sg + q + 2, pf[q & 1]);
+            float u[2];
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int t = 0; t < 16; ++t) acc = fmaf(h[jj][t], win[jj][(q + t) & 15], acc);
+                u[jj] = acc;
+            }
+            // complex FIR outputs of this lane's branch pair, then of the other pair
+            float2 U[2], O[2];
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj) {
+                const float o = swap_comp(u[jj]);
+                U[jj] = comp ? make_float2(o, u[jj]) : make_float2(u[jj], o);
+                O[jj] = make_float2(swap_pair(U[jj].x), swap_pair(U[jj].y));
+            }
+            // u_j for j = 0..3
+            const float2 u0 = jh ? O[0] : U[0], u1 = jh ? O[1] : U[1];
+            const float2 u2 = jh ? U[0] : O[0], u3 = jh ? U[1] : O[1];
+            // A[k1] = E + (-i)^k1 Od,  E = u0 + (-1)^k1 u2,  Od = u1 + (-1)^k1 u3
+            const float2 E = make_float2(u0.x + sgn * u2.x, u0.y + sgn * u2.y);
+            const float2 Od = make_float2(u1.x + sgn * u3.x, u1.y + sgn * u3.y);
+            float2 R;
+            if (k1o == 0) R = Od;
+            else if (k1o == 1) R = make_float2(Od.y, -Od.x);
+            else if (k1o == 2) R = make_float2(-Od.x, -Od.y);
+            else R = make_float2(-Od.y, Od.x);
+            lds[q * kSStride + k1o * kKStride + p1 * 16 + il] = cmul(E + R, tw_o);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        __syncthreads();
+        {
+            float2 a[16];
+            const float2* src = lds + (8 * bh + sl) * kSStride + k1 * kKStride + ilf;
+#pragma unroll
+            for (int p = 0; p < 16; ++p) a[p] = src[p * 16];
+            dft16(a);
+            const int s = sg + 8 * bh + sl;
+            const int blk = (sg >> 3) + bh;
+            if (rf < N && blk < Sb) {
+                const bool live = s < S;
+                const int lane_zoff = (blk * N + rf) * kSBlk + sl;          // samples within a channel
+                const int64_t ch_stride = (int64_t)Sb * N * kSBlk;          // samples per channel
+#pragma unroll
+                for (int ga = 0; ga < 4; ++ga)
+#pragma unroll
+                    for (int de = 0; de < 4; ++de) {
+                        const int k = k1 + 4 * (ga + 4 * de);
+                        float2 y = a[4 * ga + de];
+                        if (!live) y = make_float2(0.0f, 0.0f);
+                        store_sample<DT>(zs, (int64_t)k * ch_stride, lane_zoff, y, gain);
+                    }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int DT>
+__global__ __launch_bounds__(kThreads) void ppf_kernel(const int16_t* __restrict__ x, const float* __restrict__ taps,
+                                                       void* __restrict__ z, Tw64 tw, int64_t x_sb_stride,
+                                                       int64_t z_sb_bytes, int N, int S, int Sb, int n_groups,
+                                                       int n_chunks, float gain) {
+    __shared__ float2 lds[kSpectraPerPhase * kSStride];
+    __shared__ __attribute__((aligned(16))) float ltaps[kT * kP];
+    int bid = blockIdx.x;
+    const int chunk = bid % n_chunks;
+    bid /= n_chunks;
+    const int grp = bid % n_groups;
+    const int sb = bid / n_groups;
+    const int s_begin = chunk * kChunk;
+    const int s_end = min(S, s_begin + kChunk);
+    ppf_body<DT>(x + sb * x_sb_stride, taps, reinterpret_cast<char*>(z) + sb * z_sb_bytes, tw, N, S, Sb,
+                 grp * kNi, s_begin, s_end, gain, lds, ltaps);
+}
+
+// Batched form: one launch over per-subband jobs with their own S, type and gain.
+__global__ __launch_bounds__(kThreads) void ppf_batched_kernel(const int16_t* __restrict__ x,
+                                                              const float* __restrict__ taps, void* __restrict__ z,
+                                                              Tw64 tw, const PpfItem* __restrict__ items,
+                                                              int N, int n_groups, int n_chunks) {
+    __shared__ float2 lds[kSpectraPerPhase * kSStride];
+    __shared__ __attribute__((aligned(16))) float ltaps[kT * kP];
+    int bid = blockIdx.x;
+    const int chunk = bid % n_chunks;
+    bid /= n_chunks;
+    const int grp = bid % n_groups;
+    const int it = bid / n_groups;
+    const PpfItem item = items[it];
+    const int s_begin = chunk * kChunk;
+    if (s_begin >= item.S) return;                       // uniform over the workgroup
+    const int s_end = min(item.S, s_begin + kChunk);
+    const int16_t* xs = x + item.x_off;
+    void* zs = reinterpret_cast<char*>(z) + item.z_off;
+    if (item.dt == AFC_F32)
+        ppf_body<AFC_F32>(xs, taps, zs, tw, N, item.S, item.Sb, grp * kNi, s_begin, s_end, item.gain, lds, ltaps);
+    else if (item.dt == AFC_F16)
+        ppf_body<AFC_F16>(xs, taps, zs, tw, N, item.S, item.Sb, grp * kNi, s_begin, s_end, item.gain, lds, ltaps);
+    else
+        ppf_body<AFC_I8>(xs, taps, zs, tw, N, item.S, item.Sb, grp * kNi, s_begin, s_end, item.gain, lds, ltaps);
+}
+
+Tw64 make_twiddles() {
+    Tw64 t;
+    for (int m = 0; m < 64; ++m) {
+        const double ang = -2.0 * 3.14159265358979323846 * m / 64.0;
+        t.w[m] = make_float2((float)cos(ang), (float)sin(ang));
+    }
+    return t;
+}
+
+}  // namespace
+
+hipError_t launch_ppf(const PpfLaunch& a, hipStream_t stream) {
+    static const Tw64 tw = make_twiddles();
+    const int n_groups = (int)ceil_div(a.N, kNi);
+    const int n_chunks = (int)ceil_div(a.S, kChunk);
+    const dim3 grid((unsigned)((int64_t)a.B * n_groups * n_chunks));
+    const int64_t z_sb_bytes = a.z_sb_stride * sample_bytes(a.dt);
+    switch (a.dt) {
+        case AFC_F32:
+            hipLaunchKernelGGL(ppf_kernel<AFC_F32>, grid, dim3(kThreads), 0, stream, a.x, a.taps, a.z, tw,
+                               a.x_sb_stride, z_sb_bytes, a.N, a.S, a.Sb, n_groups, n_chunks, a.gain);
+            break;
+        case AFC_F16:
+            hipLaunchKernelGGL(ppf_kernel<AFC_F16>, grid, dim3(kThreads), 0, stream, a.x, a.taps, a.z, tw,
+                               a.x_sb_stride, z_sb_bytes, a.N, a.S, a.Sb, n_groups, n_chunks, a.gain);
+            break;
+        default:
+            hipLaunchKernelGGL(ppf_kernel<AFC_I8>, grid, dim3(kThreads), 0, stream, a.x, a.taps, a.z, tw,
+                               a.x_sb_stride, z_sb_bytes, a.N, a.S, a.Sb, n_groups, n_chunks, a.gain);
+            break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ppf_batched(const int16_t* x, const float* taps, void* z_ws, const PpfItem* items_dev,
+                              int n_items, int N, int max_S, hipStream_t stream) {
+    static const Tw64 tw = make_twiddles();
+    const int n_groups = (int)ceil_div(N, kNi);
+    const int n_chunks = (int)ceil_div(max_S, kChunk);
+    const dim3 grid((unsigned)((int64_t)n_items * n_groups * n_chunks));
+    hipLaunchKernelGGL(ppf_batched_kernel, grid, dim3(kThreads), 0, stream, x, taps, z_ws, tw, items_dev, N,
+                       n_groups, n_chunks);
+    return hipGetLastError();
+}
+
+}  // namespace afc

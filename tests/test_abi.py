@@ -1,0 +1,74 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/afc.h, sizes its buffers correctly and rejects invalid
+arguments on the host before anything is launched."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "afc.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"AFC_API\s+[\w\s\*]+?\b(afc_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def afc():
+    import paper_1609_04205_amd as afc
+    return afc
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for n in ["afc_channelise", "afc_correlate", "afc_calibrate_grad", "afc_plan_create", "afc_plan_launch",
+              "afc_plan_destroy", "afc_last_error"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(afc):
+    lib = C.CDLL(afc.LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(afc.EXPORTS) == _declared()
+
+
+def test_sizes(afc):
+    d = afc.dims(576, 16, 3051)
+    Sb = (3051 + 7) // 8
+    assert afc._lib.afc_channelised_bytes(C.byref(d), afc.AFC_I8) == 16 * 64 * Sb * 1152 * 8 * 2
+    assert afc._lib.afc_channelised_bytes(C.byref(d), afc.AFC_F32) == 16 * 64 * Sb * 1152 * 8 * 8
+    assert afc._lib.afc_visibility_bytes(C.byref(d)) == 16 * 64 * (576 * 577 // 2) * 32
+    bad = afc.dims(576, 16, 3051, n_channels=256)
+    assert afc._lib.afc_channelised_bytes(C.byref(bad), afc.AFC_I8) == 0
+    assert afc._lib.afc_calibrate_workspace_bytes(576, 64) > 0
+    assert afc._lib.afc_calibrate_workspace_bytes(0, 64) == 0
+
+
+def test_invalid_arguments_are_rejected_on_host(afc):
+    lib = afc._lib
+    d = afc.dims(48, 1, 1024)
+    dummy = C.c_void_p(0x1000)          # never dereferenced: validation fails first
+    assert lib.afc_channelise(None, dummy, dummy, afc.AFC_F32, 1.0, dummy, None) == -1
+    assert b"dims" in lib.afc_last_error()
+    assert lib.afc_channelise(C.byref(d), None, dummy, afc.AFC_F32, 1.0, dummy, None) == -1
+    assert lib.afc_channelise(C.byref(d), dummy, dummy, 7, 1.0, dummy, None) == -1
+    assert lib.afc_channelise(C.byref(d), dummy, dummy, afc.AFC_I8, 0.0, dummy, None) == -1
+    p256 = afc.dims(48, 1, 1024, n_channels=256)
+    assert lib.afc_channelise(C.byref(p256), dummy, dummy, afc.AFC_F32, 1.0, dummy, None) == -2
+    t8 = afc.dims(48, 1, 1024, n_taps=8)
+    assert lib.afc_correlate(C.byref(t8), afc.AFC_F32, dummy, None, None, dummy, None, None) == -2
+    pol1 = afc.Dims(48, 1, 1, 64, 16, 1024)
+    assert lib.afc_correlate(C.byref(pol1), afc.AFC_F32, dummy, None, None, dummy, None, None) == -2
+    s_bad = (C.c_int32 * 1)(2000)
+    assert lib.afc_correlate(C.byref(d), afc.AFC_F32, dummy, C.cast(s_bad, C.c_void_p), None, dummy, None, None) == -1
+    big = afc.dims(48, 1, 70000)       # int8 sums could overflow int32
+    assert lib.afc_correlate(C.byref(big), afc.AFC_I8, dummy, None, None, dummy, None, None) == -2
+    assert lib.afc_calibrate_grad(48, 4, dummy, dummy, dummy, dummy, None, None, None) == -4
+    assert lib.afc_calibrate_grad(0, 4, dummy, dummy, dummy, dummy, None, dummy, None) == -1
+    out = C.c_void_p()
+    assert lib.afc_plan_create(C.byref(d), None, None, None, C.byref(out)) == -1
+    assert not out.value

@@ -1,0 +1,105 @@
+"""GPU parity of the calibration loss and adjoint (afc_calibrate_grad, CalLoss)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_util import log
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def afc():
+    import paper_1609_04205_amd as afc
+    return afc
+
+
+def _cplx(a):
+    return a[..., 0].astype(np.float64) + 1j * a[..., 1]
+
+
+def _check(afc, dev, V, M, g, chans=None, tol_g=1e-6, tol_l=1e-5):
+    Vt, Mt, gt = (torch.from_numpy(a).to(dev) for a in (V, M, g))
+    loss, grad = afc.calibrate_grad(Vt, Mt, gt)
+    torch.cuda.synchronize()
+    loss = loss.cpu().numpy()
+    grad = _cplx(grad.cpu().numpy())
+    chans = range(g.shape[0]) if chans is None else list(chans)
+    sel = np.array(chans)
+    lref, gref = oracle.cal_loss_grad(V[sel], M[sel], g[sel])
+    worst_g = worst_l = 0.0
+    for k, ch in enumerate(chans):
+        for pol in range(2):
+            rl = abs(loss[ch, pol] - lref[k, pol]) / abs(lref[k, pol])
+            gn = np.linalg.norm(gref[k, :, pol])
+            rg = np.linalg.norm(grad[ch, :, pol] - gref[k, :, pol]) / gn if gn > 0 else 0.0
+            worst_g, worst_l = max(worst_g, rg), max(worst_l, rl)
+    log(f"  loss rel err {worst_l:.2e}, grad rel err {worst_g:.2e}")
+    assert worst_l <= tol_l
+    assert worst_g <= tol_g
+
+
+def test_small_random(afc, dev):
+    rng = np.random.default_rng(1)
+    Na, P = 70, 3                       # 70 antennas: ragged against the 64-antenna tiles
+    nbl = Na * (Na + 1) // 2
+    V = rng.standard_normal((P, nbl, 2, 2, 2)).astype(np.float32)
+    M = rng.standard_normal((P, nbl, 2, 2, 2)).astype(np.float32)
+    d = np.array([a * (a + 1) // 2 + a for a in range(Na)])
+    for arr in (V, M):
+        arr[:, d, 0, 0, 1] = 0
+        arr[:, d, 1, 1, 1] = 0
+    g = rng.standard_normal((P, Na, 2, 2)).astype(np.float32)
+    _check(afc, dev, V, M, g)
+
+
+@pytest.mark.parametrize("at", ["true", "unit"])
+def test_cfg5_small(afc, dev, at):
+    V, M, g = W.make_calibration(Na=48, P=4, seed=15)
+    if at == "unit":
+        g = np.zeros_like(g)
+        g[..., 0] = 1.0
+    _check(afc, dev, V, M, g)
+
+
+@pytest.mark.parametrize("at", ["true", "unit"])
+def test_cfg5_full_size(afc, dev, at):
+    """576 antennas x 64 channels at SNR 20, at the true gains (residual ~ 5% of V) and at g = 1."""
+    log(f"calibration full size at {at}")
+    V, M, g = W.make_calibration(Na=576, P=64, seed=5)
+    if at == "unit":
+        g = np.zeros_like(g)
+        g[..., 0] = 1.0
+    _check(afc, dev, V, M, g, chans=[0, 17, 40, 63])
+
+
+def test_autograd_matches_torch(afc, dev):
+    """CalLoss backward equals torch autograd of the same loss in float64."""
+    V, M, g = W.make_calibration(Na=24, P=2, seed=21)
+    Vt, Mt = torch.from_numpy(V).to(dev), torch.from_numpy(M).to(dev)
+    gc = torch.view_as_complex(torch.from_numpy(g).to(dev)).clone().requires_grad_(True)
+    L = afc.cal_loss(Vt, Mt, gc)
+    w = torch.tensor([[1.0, 0.5], [2.0, -1.0]], dtype=torch.float64, device=dev)
+    (L * w).sum().backward()
+    # reference: full Hermitian matrices in float64 on the CPU
+    Na = 24
+    a, b = np.tril_indices(Na)
+    ref_grad = np.zeros((2, Na, 2), np.complex128)
+    for k in range(2):
+        for pol in range(2):
+            Vf = np.zeros((Na, Na), np.complex128)
+            Mf = np.zeros((Na, Na), np.complex128)
+            Vf[a, b] = _cplx(V[k, :, pol, pol])
+            Vf[b, a] = np.conj(Vf[a, b])
+            Mf[a, b] = _cplx(M[k, :, pol, pol])
+            Mf[b, a] = np.conj(Mf[a, b])
+            gt = torch.tensor(_cplx(g[k, :, pol]), requires_grad=True)
+            R = torch.tensor(Vf) - gt[:, None] * torch.tensor(Mf) * gt.conj()[None, :]
+            ((R.abs() ** 2).sum() * float(w[k, pol])).backward()
+            ref_grad[k, :, pol] = gt.grad.numpy()
+    got = gc.grad.cpu().numpy()
+    rel = np.linalg.norm(got - ref_grad) / np.linalg.norm(ref_grad)
+    assert rel <= 1e-6

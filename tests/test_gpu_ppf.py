@@ -1,0 +1,128 @@
+"""GPU parity of the channeliser (afc_channelise) against the CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_util import log
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def afc():
+    import paper_1609_04205_amd as afc
+    return afc
+
+
+def _run(afc, dev, cfg, dtype, gain=1.0, n_rows=None):
+    x = W.make_voltages(cfg, device=dev, n_rows=n_rows)
+    taps_np = W.prototype_taps()
+    taps = torch.from_numpy(taps_np).to(dev)
+    z = afc.channelise(x, taps, cfg.n_spectra, dtype, gain)
+    torch.cuda.synchronize()
+    return x, taps_np, z
+
+
+def _natural(z, S):
+    """[B][P][Sb][N][8][2] -> numpy complex [B][P][S][N] plus the pad slots."""
+    zn = z.float().cpu().numpy()
+    B, P, Sb, N = zn.shape[:4]
+    full = zn.transpose(0, 1, 2, 4, 3, 5).reshape(B, P, Sb * 8, N, 2)
+    c = full[..., 0].astype(np.float64) + 1j * full[..., 1]
+    return c[:, :, :S], c[:, :, S:]
+
+
+def test_f32_cfg1_all_outputs(afc, dev):
+    cfg = W.CONFIGS[1]
+    log("ppf f32 cfg1: Na=48 S=1024")
+    x, taps, z = _run(afc, dev, cfg, "f32")
+    y, pad = _natural(z, cfg.n_spectra)
+    ref = oracle.ppf_subband(x[0].cpu().numpy(), taps, 64, 16, cfg.n_spectra)      # [P][S][N]
+    sigma = np.sqrt(np.mean(np.abs(ref) ** 2) / 2)
+    err = np.abs(y[0] - ref).max() / sigma
+    log(f"  max |dy|/sigma_y = {err:.3e}")
+    assert err <= 1e-5
+    assert pad.size == 0 or np.all(pad == 0)
+
+
+@pytest.mark.parametrize("Na,S,B", [(5, 37, 2), (1, 1, 1), (24, 130, 1)])
+def test_f32_ragged(afc, dev, Na, S, B):
+    """Receivers not a multiple of the workgroup's 16, spectra not a multiple of 8 or 16."""
+    cfg = W.Config("ragged", Na, B, n_spectra=S, sigma_n=500.0, source_sigmas=(100.0,), seed=7)
+    log(f"ppf f32 ragged: Na={Na} S={S} B={B}")
+    x, taps, z = _run(afc, dev, cfg, "f32")
+    y, pad = _natural(z, S)
+    xs = x.cpu().numpy()
+    for b in range(B):
+        ref = oracle.ppf_subband(xs[b], taps, 64, 16, S)
+        sigma = np.sqrt(np.mean(np.abs(ref) ** 2) / 2)
+        assert np.abs(y[b] - ref).max() / sigma <= 1e-5
+    assert np.all(pad == 0)
+
+
+def test_f16_cfg1(afc, dev):
+    cfg = W.CONFIGS[1]
+    log("ppf f16 cfg1")
+    x, taps, z = _run(afc, dev, cfg, "f16")
+    y, _ = _natural(z, cfg.n_spectra)
+    ref = oracle.ppf_subband(x[0].cpu().numpy(), taps, 64, 16, cfg.n_spectra)
+    sigma = np.sqrt(np.mean(np.abs(ref) ** 2) / 2)
+    # each component: fp16 rounding (half an ulp, 2^-11 relative) + float32 error
+    for comp in (np.real, np.imag):
+        d = np.abs(comp(y[0]) - comp(ref))
+        assert np.all(d <= 2.0 ** -11 * np.abs(comp(ref)) * 1.0001 + 2e-5 * sigma)
+
+
+def test_i8_requant_cfg1(afc, dev):
+    cfg = W.CONFIGS[1]
+    taps = W.prototype_taps()
+    gain = W.requant_gain(cfg, taps)
+    log(f"ppf i8 cfg1 gain={gain}")
+    x = W.make_voltages(cfg, device=dev)
+    tt = torch.from_numpy(taps).to(dev)
+    z8 = afc.channelise(x, tt, cfg.n_spectra, "i8", gain)
+    z32 = afc.channelise(x, tt, cfg.n_spectra, "f32")
+    torch.cuda.synchronize()
+    q = z8.cpu().numpy()
+    y32 = z32.cpu().numpy()
+    # property: the int8 output is the requantised float32 output of the same kernel
+    ref_q = np.clip(np.rint(y32 * np.float32(gain)), -127, 127).astype(np.int8)
+    assert (y32 * np.float32(gain)).dtype == np.float32
+    np.testing.assert_array_equal(q, ref_q)
+    assert q.min() >= -127
+    # against the float64 oracle: at most one step, and only next to a rounding boundary
+    yq, _ = _natural(z8.float(), cfg.n_spectra)
+    ref = oracle.ppf_subband(x[0].cpu().numpy(), taps, 64, 16, cfg.n_spectra)
+    for comp in (np.real, np.imag):
+        v = comp(ref) * gain
+        r = np.clip(np.rint(v), -127, 127)
+        d = np.abs(comp(yq[0]) - r)
+        assert d.max() <= 1
+        near = np.abs(np.abs(v - np.floor(v)) - 0.5)
+        sigma = np.sqrt(np.mean(np.abs(ref) ** 2) / 2)
+        assert np.all(near[d == 1] <= 1e-5 * sigma * gain)
+        log(f"  off-by-one fraction {np.mean(d == 1):.2e}")
+
+
+def test_f32_full_size_sampled(afc, dev):
+    """AARTFAAC-12 shape (1152 receivers, 16 subbands, 3051 spectra): sampled receivers."""
+    cfg = W.CONFIGS[3]
+    log("ppf f32 cfg3 full size")
+    x, taps, z = _run(afc, dev, cfg, "f32")
+    rng = np.random.default_rng(0)
+    for sb in (0, 7, 15):
+        inputs = sorted(rng.choice(cfg.n_inputs, size=3, replace=False).tolist()) + [cfg.n_inputs - 1]
+        xs = x[sb].cpu().numpy()
+        ref = oracle.ppf_subband(xs, taps, 64, 16, cfg.n_spectra, inputs=inputs)
+        zz = z[sb].index_select(2, torch.tensor(inputs, device=dev))          # [P][Sb][R][8][2]
+        got = zz.permute(0, 1, 3, 2, 4).reshape(64, -1, len(inputs), 2)[:, :cfg.n_spectra].cpu().numpy()
+        got = got[..., 0].astype(np.float64) + 1j * got[..., 1]
+        sigma = np.sqrt(np.mean(np.abs(ref) ** 2) / 2)
+        err = np.abs(got - ref).max() / sigma
+        log(f"  sb={sb} inputs={inputs} max err {err:.3e}")
+        assert err <= 1e-5
+    del x, z
+    torch.cuda.empty_cache()

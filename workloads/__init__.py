@@ -127,13 +127,13 @@ def antenna_positions(cfg: Config) -> np.ndarray:
     if cfg.layout == "disc":
         return _disc(rng, cfg.n_antennas, 30.0)
     n_st = {"stations6": 6, "stations12": 12}[cfg.layout]
-    per = cfg.n_antennas // n_st
+    counts = [cfg.n_antennas // n_st + (1 if k < cfg.n_antennas % n_st else 0) for k in range(n_st)]
     centres = []
     for k in range(n_st):
         ring = 150.0 if k < 6 else 588.0
         ang = 2.0 * np.pi * (k % 6) / 6.0 + (0.0 if k < 6 else np.pi / 6.0)
         centres.append((ring * np.cos(ang), ring * np.sin(ang)))
-    pos = [np.asarray(c)[None, :] + _disc(rng, per, 30.0) for c in centres]
+    pos = [np.asarray(c)[None, :] + _disc(rng, n, 30.0) for c, n in zip(centres, counts)]
     return np.concatenate(pos, axis=0)
 
 
