@@ -1,0 +1,278 @@
+"""Benchmark of the FX-correlator hot path on one MI355X.
+
+One step = one pass of the hot path over one integration of the AARTFAAC-12
+shaped workload (576 dual-polarised antennas = 1152 receivers, 16 subbands,
+64 channels, 3051 spectra ~ 1 s): afc_channelise (16-tap PPF, requantised to
+int8) followed by afc_correlate (int8 MFMA X-engine, lower triangle).
+Inputs are synthetic, seeded, and resident in HBM before timing starts.
+
+Prints ONE JSON line.  `value` is the whole step's useful complex
+multiply-accumulates per second (TCMAC/s).  Beside it: per-kernel times from
+HIP events on the launch stream, the X-engine's fraction of the int8 MFMA
+peak, the PPF's algorithmic GB/s, the real-time factor, the fp32 path for the
+int8-vs-fp32 comparison, the batching plan (32 subbands, ragged, flagged,
+mixed fp16/int8) and the calibration gradient, and the CPU oracle timed on
+a bounded sample on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "X-engine TCMAC/s and % MFMA peak, int8 vs fp32, 576 ant; PPF GB/s; real-time factor"
+PEAK_HBM_GBS = 8000.0
+PEAK_INT8_TOPS = 5000.0
+PEAK_FP16_TFLOPS = 2500.0
+PEAK_FP32_MFMA_TFLOPS = 157.3
+# non-packed fp32 vector peak: 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+PEAK_FP32_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="time only the int8 step")
+    ap.add_argument("--cpu-sample-spectra", type=int, default=512)
+    return ap.parse_args()
+
+
+class Timer:
+    """Average kernel durations from HIP events recorded on the launch stream."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.pairs = {}
+
+    def rec(self, name):
+        torch = self.torch
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(torch.cuda.current_stream())
+        self.pairs.setdefault(name, []).append((e0, e1))
+        return e1
+
+    def ms(self, name):
+        ps = self.pairs.get(name, [])
+        return sum(a.elapsed_time(b) for a, b in ps) / max(1, len(ps))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1609_04205_amd as afc
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    cfg = W.CONFIGS[3]
+    B, Na, S, P = cfg.n_subbands, cfg.n_antennas, cfg.n_spectra, 64
+    N = 2 * Na
+    nbl = Na * (Na + 1) // 2
+    Sb = (S + 7) // 8
+    L = cfg.n_rows
+    log(f"workload {cfg.name}: B={B} Na={Na} N={N} S={S}")
+    x = W.make_voltages(cfg, device=dev)
+    taps_np = W.prototype_taps()
+    taps = torch.from_numpy(taps_np).to(dev)
+    gain = W.requant_gain(cfg, taps_np)
+    z8 = torch.empty(afc.channelised_shape(B, S, N), dtype=torch.int8, device=dev)
+    vis = torch.empty(afc.visibility_shape(B, Na), dtype=torch.int32, device=dev)
+    wts = torch.empty((B, nbl), dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    timer = Timer(torch)
+
+    def step(tm=None):
+        if tm:
+            e = tm.rec("ppf")
+        afc.channelise(x, taps, S, "i8", gain, out=z8)
+        if tm:
+            e.record(torch.cuda.current_stream())
+            e = tm.rec("xengine")
+        afc.correlate(z8, n_spectra=S, out=vis, weights=wts)
+        if tm:
+            e.record(torch.cuda.current_stream())
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(timer)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    ppf_ms, xe_ms = timer.ms("ppf"), timer.ms("xengine")
+
+    cmac = float(B) * P * (N * (N + 1) // 2) * S             # useful complex MACs per step
+    data_s = S * P / W.F_SUBBAND                              # seconds of data per step
+    ppf_bytes = float(B) * L * N * 4 + float(B) * P * S * N * 2 + 4 * 16 * 64
+    # FIR 16 taps x 4 flop per complex point + FFT 5 log2(64) flop per point
+    ppf_flops = float(B) * N * S * 64 * (16 * 4 + 5 * 6)
+    xe_tops = 8.0 * cmac / (xe_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": round(cmac / (ms_step * 1e-3) / 1e12, 4),
+        "unit": "TCMAC/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i8",
+        "data": "synthetic",
+        "config": {"workload": "a12-576ant-16sb-3051spectra", "n_antennas": Na, "n_receivers": N,
+                   "n_subbands": B, "n_channels": P, "n_taps": 16, "n_spectra": S,
+                   "step": "channelise(int16 -> int8) + correlate(int8 MFMA, int32)"},
+        "roofline": None,
+        "real_time_factor": round(data_s / (ms_step * 1e-3), 2),
+        "xengine_ms": round(xe_ms, 4),
+        "xengine_tcmacs": round(cmac / (xe_ms * 1e-3) / 1e12, 3),
+        "xengine_int8_mfma_frac": round(xe_tops / PEAK_INT8_TOPS, 4),
+        "ppf_ms": round(ppf_ms, 4),
+        "ppf_gbs": round(ppf_bytes / (ppf_ms * 1e-3) / 1e9, 1),
+        "ppf_hbm_frac": round(ppf_bytes / (ppf_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+        "ppf_valu_frac": round(ppf_flops / (ppf_ms * 1e-3) / 1e12 / PEAK_FP32_VALU_TFLOPS, 4),
+    }
+    ppf_roof = {"bound": "hbm", "achieved": round(ppf_bytes / (ppf_ms * 1e-3) / 1e9, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(ppf_bytes / (ppf_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4), "traffic": None}
+    xe_roof = {"bound": "mfma", "achieved": round(xe_tops, 2), "peak": PEAK_INT8_TOPS, "unit": "TFLOP/s",
+               "frac": round(xe_tops / PEAK_INT8_TOPS, 4), "traffic": None}
+    out["roofline"] = xe_roof if xe_ms >= ppf_ms else ppf_roof
+    out["roofline_other"] = ppf_roof if xe_ms >= ppf_ms else xe_roof
+    log(f"int8 step {ms_step:.3f} ms (ppf {ppf_ms:.3f}, xengine {xe_ms:.3f})")
+
+    if not args.no_extras:
+        # ---- fp32 path on the same input: int8 vs fp32
+        del z8
+        z32 = torch.empty(afc.channelised_shape(B, S, N), dtype=torch.float32, device=dev)
+        vis32 = torch.empty(afc.visibility_shape(B, Na), dtype=torch.float32, device=dev)
+        t32 = Timer(torch)
+        for it in range(3):
+            tm = t32 if it > 0 else None
+            if tm:
+                e = tm.rec("ppf")
+            afc.channelise(x, taps, S, "f32", out=z32)
+            if tm:
+                e.record(torch.cuda.current_stream())
+                e = tm.rec("xengine")
+            afc.correlate(z32, n_spectra=S, out=vis32, weights=wts)
+            if tm:
+                e.record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        f32_xe = t32.ms("xengine")
+        f32_tf = 8.0 * cmac / (f32_xe * 1e-3) / 1e12
+        out["fp32"] = {"xengine_ms": round(f32_xe, 3), "xengine_tcmacs": round(cmac / (f32_xe * 1e-3) / 1e12, 3),
+                       "xengine_fp32_mfma_frac": round(f32_tf / PEAK_FP32_MFMA_TFLOPS, 4),
+                       "ppf_ms": round(t32.ms("ppf"), 3),
+                       "ppf_gbs": round((float(B) * L * N * 4 + float(B) * P * S * N * 8) / (t32.ms("ppf") * 1e-3) / 1e9, 1),
+                       "real_time_factor": round(data_s / ((f32_xe + t32.ms("ppf")) * 1e-3), 2)}
+        out["int8_speedup_over_fp32_xengine"] = round(f32_xe / xe_ms, 2)
+        log(f"fp32 xengine {f32_xe:.3f} ms")
+        del z32, vis32, x, vis
+        torch.cuda.empty_cache()
+
+        # ---- batching form: 32 subbands, ragged S, flags, mixed fp16/int8, one graph
+        cfg4 = W.CONFIGS[4]
+        bp = W.batch_params(cfg4)
+        dts = ["f16" if d == 1 else "i8" for d in bp.dtypes]
+        x4 = W.make_voltages(cfg4, device=dev)
+        plan = afc.Plan(Na, bp.n_spectra.tolist(), dts, n_spectra=cfg4.n_spectra,
+                        tune_cache=os.path.join(ROOT, "paper_1609_04205_amd", "tune_cache.json"))
+        ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+        vis4 = torch.empty(afc.visibility_shape(cfg4.n_subbands, Na), dtype=torch.int32, device=dev)
+        w4 = torch.empty((cfg4.n_subbands, nbl), dtype=torch.int32, device=dev)
+        fl = torch.from_numpy(bp.flags).to(dev)
+        g4 = [W.requant_gain(cfg4, taps_np)] * cfg4.n_subbands
+        plan.launch(x4, taps, g4, ws, vis4, flags=fl, weights=w4)
+        torch.cuda.synchronize()
+        tp = Timer(torch)
+        for _ in range(3):
+            e = tp.rec("plan")
+            plan.launch(x4, taps, g4, ws, vis4, flags=fl, weights=w4)
+            e.record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        nprime = [2 * (Na - int(bp.flags[b].sum())) for b in range(cfg4.n_subbands)]
+        cm4 = sum(P * n * (n + 1) // 2 * int(bp.n_spectra[b]) for b, n in enumerate(nprime))
+        plan_ms = tp.ms("plan")
+        info = plan.info()
+        out["batching"] = {"workload": cfg4.name, "graph_ms": round(plan_ms, 3),
+                           "useful_tcmacs": round(cm4 / (plan_ms * 1e-3) / 1e12, 3),
+                           "real_time_factor": round(max(bp.n_spectra) * P / W.F_SUBBAND / (plan_ms * 1e-3), 2),
+                           "tile": info.tile, "workgroups": info.n_workgroups, "work_items": info.n_work_items}
+        log(f"plan {plan_ms:.3f} ms")
+        plan.close()
+        del x4, ws, vis4, w4
+        torch.cuda.empty_cache()
+
+        # ---- calibration adjoint, 576 antennas x 64 channels
+        Vc, Mc, gc = W.make_calibration(Na=576, P=64, seed=5)
+        Vt, Mt, gt = (torch.from_numpy(a).to(dev) for a in (Vc, Mc, gc))
+        afc.calibrate_grad(Vt, Mt, gt)
+        torch.cuda.synchronize()
+        tc = Timer(torch)
+        for _ in range(5):
+            e = tc.rec("cal")
+            afc.calibrate_grad(Vt, Mt, gt)
+            e.record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        cal_ms = tc.ms("cal")
+        cal_bytes = 2.0 * 64 * nbl * 2 * 8          # XX and YY of V and M
+        out["calibration"] = {"ms": round(cal_ms, 4), "algorithmic_gbs": round(cal_bytes / (cal_ms * 1e-3) / 1e9, 1)}
+        log(f"calibration {cal_ms:.3f} ms")
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_spectra)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(S_s):
+    """Oracle chain (float64 PPF -> requant -> exact int correlator) on a bounded sample:
+    subband 0 of the same workload, all 1152 receivers, the first S_s spectra, all 64
+    channels; TCMAC/s = useful CMACs of the sample / oracle wall time."""
+    import numpy as np
+
+    import oracle
+    import workloads as W
+
+    cfg = W.CONFIGS[3]
+    N = cfg.n_inputs
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    os.environ["OMP_NUM_THREADS"] = str(threads)
+    x = W.make_voltages(cfg, subbands=[0], n_rows=(S_s + 15) * 64).numpy()[0]
+    taps = W.prototype_taps()
+    gain = W.requant_gain(cfg, taps)
+    t0 = time.perf_counter()
+    y = oracle.ppf_subband(x, taps, 64, 16, S_s)                          # [P][S][N]
+    t1 = time.perf_counter()
+    q = oracle.requant(np.stack([y.real, y.imag], -1).astype(np.float32), gain)
+    t2 = time.perf_counter()
+    for ch in range(64):
+        oracle.xcorr_int(np.ascontiguousarray(q[ch]))
+    t3 = time.perf_counter()
+    cmac = 64.0 * (N * (N + 1) // 2) * S_s
+    return {"value": round(cmac / (t3 - t0) / 1e12, 6), "unit": "TCMAC/s", "cores": threads, "kind": "oracle",
+            "sample": f"subband 0 of the same workload, all {N} receivers, first {S_s} of 3051 spectra, 64 channels: "
+                      f"float64 PPF {t1 - t0:.1f} s + requant {t2 - t1:.1f} s + exact-int correlator {t3 - t2:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()
