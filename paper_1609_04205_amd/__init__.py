@@ -14,7 +14,7 @@ from dataclasses import dataclass
 from typing import Optional, Sequence, Tuple
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libafc.so")
+LIB_PATH = os.environ.get("AFC_LIBRARY", os.path.join(HERE, "libafc.so"))
 
 AFC_F32, AFC_F16, AFC_I8 = 0, 1, 2
 DTYPES = {"f32": AFC_F32, "f16": AFC_F16, "i8": AFC_I8}

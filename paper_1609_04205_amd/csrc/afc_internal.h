@@ -84,3 +84,14 @@ hipError_t launch_calibrate(int Na, int P, const float2* V, const float2* M, con
                             double* loss, float2* grad, void* ws, hipStream_t stream);
 
 }  // namespace afc
+
+namespace afc {
+// Workgroup barrier that orders LDS only: waits for this wave's LDS
+// operations, then s_barrier.  Unlike __syncthreads() it does not wait for
+// outstanding global loads and stores, so prefetches stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+}  // namespace afc

@@ -36,6 +36,7 @@ constexpr int kKStride = 16 * 16 + 8;        // float2 per k1 row (+64 B: k1 row
 constexpr int kSStride = 4 * kKStride + 4;   // float2 per spectrum (+32 B: spectra start 8 banks apart)
 constexpr int kSpectraPerPhase = 16;
 constexpr int kChunk = 768;                  // spectra per workgroup, a multiple of 16
+constexpr int kDepth = 4;                    // spectra of loads in flight per lane (divides 16)
 
 struct Tw64 {
     float2 w[64];                            // exp(-2 pi i m / 64), rounded from double on the host
@@ -78,20 +79,20 @@ __device__ __forceinline__ void dft16(float2 (&a)[16]) {
     for (int ga = 0; ga < 4; ++ga) dft4(a[4 * ga], a[4 * ga + 1], a[4 * ga + 2], a[4 * ga + 3]);
 }
 
-__device__ __forceinline__ float swap_comp(float v) {
-    // quad_perm(1,0,3,2): exchange with the neighbouring lane (other component)
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float swap_pair(float v) {
-    // quad_perm(2,3,0,1): exchange with the lane two away (other branch pair)
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+// value of lane L of this lane's quad (DPP quad_perm(L,L,L,L))
+template <int L>
+__device__ __forceinline__ float quad_bcast(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), L * 0x55, 0xF, 0xF, false));
 }
 
-__device__ __forceinline__ int requant1(float y, float gain) {
-    float v = y * gain;                       // one float32 product
-    float r = rintf(v);                       // nearest, ties to even
-    r = fminf(fmaxf(r, -127.0f), 127.0f);
-    return (int)r;
+// clamp(rint(fp32(y * gain)), -127, 127) as a two's-complement byte in the
+// low 8 bits.  Clamping before rounding gives the same value (the bounds are
+// integers); adding 1.5 * 2^23 rounds to an integer with ties to even and
+// leaves it in the low mantissa bits.
+__device__ __forceinline__ unsigned requant_bits(float y, float gain) {
+    const float v = __fmul_rn(y, gain);                        // one float32 product
+    const float c = __builtin_amdgcn_fmed3f(v, -127.0f, 127.0f);
+    return __float_as_uint(__fadd_rn(c, 12582912.0f));
 }
 
 // store at sample index base + off (base wave-uniform, off per lane)
@@ -102,8 +103,9 @@ __device__ __forceinline__ void store_sample(void* zs, int64_t base, int off, fl
     } else if constexpr (DT == AFC_F16) {
         (reinterpret_cast<__half2*>(zs) + base)[off] = __floats2half2_rn(y.x, y.y);
     } else {
-        const int qr = requant1(y.x, gain), qi = requant1(y.y, gain);
-        (reinterpret_cast<uint16_t*>(zs) + base)[off] = (uint16_t)((qr & 0xFF) | ((qi & 0xFF) << 8));
+        const unsigned qr = requant_bits(y.x, gain), qi = requant_bits(y.y, gain);
+        // bytes: low = real, high = imaginary
+        (reinterpret_cast<uint16_t*>(zs) + base)[off] = (uint16_t)__builtin_amdgcn_perm(qi, qr, 0x0c0c0400u);
     }
 }
 
@@ -120,8 +122,10 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
 
     // ---- FIR-phase roles: lane = il * 4 + jh * 2 + comp
     const int comp = lane & 1, jh = (lane >> 1) & 1, il = lane >> 2;
-    const int rcv = i0 + il;
-    const bool rcv_ok = rcv < N;
+    // Receivers beyond N read receiver N-1 and spectra beyond S read the last
+    // valid samples: every load is in bounds and unconditional (no load waits
+    // on another); such lanes and spectra are never stored.
+    const int rcv = min(i0 + il, N - 1);
     const int p1 = wv;
     const int row_stride = N * 2;
     const int lane_off = (p1 + 32 * jh) * row_stride + rcv * 2 + comp;   // branch p1 + 16 (2 jh) at row 0
@@ -133,7 +137,7 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
         const int t = e / kP, p = e % kP;
         ltaps[p * kT + t] = taps[e];
     }
-    __syncthreads();
+    lds_barrier();
     const float4* tp0 = reinterpret_cast<const float4*>(ltaps + (p1 + 32 * jh) * kT);
     const float4* tp1 = reinterpret_cast<const float4*>(ltaps + (p1 + 32 * jh + 16) * kT);
 
@@ -142,13 +146,18 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
     // (uniform loads of the four candidates, then a per-lane select)
     const float2 tw1 = tw.w[p1 & 63], tw2 = tw.w[(2 * p1) & 63], tw3 = tw.w[(3 * p1) & 63];
     const float2 tw_o = k1o == 0 ? make_float2(1.0f, 0.0f) : k1o == 1 ? tw1 : k1o == 2 ? tw2 : tw3;
+    // (-i)^k1 tw
+    const float2 rtw_o = k1o == 0 ? tw_o : k1o == 1 ? make_float2(tw_o.y, -tw_o.x)
+                       : k1o == 2 ? make_float2(-tw_o.x, -tw_o.y) : make_float2(-tw_o.y, tw_o.x);
     const float sgn = (k1o & 1) ? -1.0f : 1.0f;
 
     // sample x_p[m] of branch p1 + 16 (2 jh + jj) at spectrum-row m
     // (wave-uniform 64-bit row pointer + 32-bit lane offset)
-    auto ld = [&](int m, int jj) -> float {
-        const int16_t* rowp = xs + (int64_t)m * spec_stride;
-        return rcv_ok ? (float)rowp[jj * (16 * row_stride) + lane_off] : 0.0f;
+    // raw int16 sample; converted to float only where it enters the window,
+    // so that a load in flight is not waited on before it is needed
+    auto ld = [&](int m, int jj) -> int {
+        const int16_t* rowp = xs + (int64_t)min(m, S + kT - 2) * spec_stride;
+        return rowp[jj * (16 * row_stride) + lane_off];
     };
 
     // history: window slot m % 16 holds x_p[m]; s_begin is a multiple of 16
@@ -156,7 +165,7 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
 #pragma unroll
     for (int m = 0; m < 15; ++m)
 #pragma unroll
-        for (int jj = 0; jj < 2; ++jj) win[jj][m] = ld(s_begin + m, jj);
+        for (int jj = 0; jj < 2; ++jj) win[jj][m] = (float)ld(s_begin + m, jj);
 #pragma unroll
     for (int jj = 0; jj < 2; ++jj) win[jj][15] = 0.0f;
 
@@ -166,18 +175,14 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
     const int ilf = rh * 8 + ii;
     const int rf = i0 + ilf;
 
-    // two-deep software pipeline of the per-spectrum loads
-    float pf[2][2];
-    auto fetch = [&](int s, float (&dst)[2]) {
-        if (s < S) {
+    // software pipeline of the per-spectrum loads, kDepth spectra ahead
+    int pf[kDepth][2];
+    auto fetch = [&](int s, int (&dst)[2]) {
 #pragma unroll
-            for (int jj = 0; jj < 2; ++jj) dst[jj] = ld(s + 15, jj);
-        } else {
-            dst[0] = dst[1] = 0.0f;
-        }
+        for (int jj = 0; jj < 2; ++jj) dst[jj] = ld(s + 15, jj);
     };
-    fetch(s_begin, pf[0]);
-    fetch(s_begin + 1, pf[1]);
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d) fetch(s_begin + d, pf[d]);
 
     for (int sg = s_begin; sg < s_end; sg += kSpectraPerPhase) {
         float h[2][16];
@@ -190,8 +195,8 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
 #pragma unroll
         for (int q = 0; q < kSpectraPerPhase; ++q) {
 #pragma unroll
-            for (int jj = 0; jj < 2; ++jj) win[jj][(q + 15) & 15] = pf[q & 1][jj];
-            fetch(sg + q + 2, pf[q & 1]);
+            for (int jj = 0; jj < 2; ++jj) win[jj][(q + 15) & 15] = (float)pf[q % kDepth][jj];
+            fetch(sg + q + kDepth, pf[q % kDepth]);
             float u[2];
 #pragma unroll
             for (int jj = 0; jj < 2; ++jj) {
@@ -200,29 +205,23 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
                 for (int t = 0; t < 16; ++t) acc = fmaf(h[jj][t], win[jj][(q + t) & 15], acc);
                 u[jj] = acc;
             }
-            // complex FIR outputs of this lane's branch pair, then of the other pair
-            float2 U[2], O[2];
-#pragma unroll
-            for (int jj = 0; jj < 2; ++jj) {
-                const float o = swap_comp(u[jj]);
-                U[jj] = comp ? make_float2(o, u[jj]) : make_float2(u[jj], o);
-                O[jj] = make_float2(swap_pair(U[jj].x), swap_pair(U[jj].y));
-            }
-            // u_j for j = 0..3
-            const float2 u0 = jh ? O[0] : U[0], u1 = jh ? O[1] : U[1];
-            const float2 u2 = jh ? U[0] : O[0], u3 = jh ? U[1] : O[1];
-            // A[k1] = E + (-i)^k1 Od,  E = u0 + (-1)^k1 u2,  Od = u1 + (-1)^k1 u3
-            const float2 E = make_float2(u0.x + sgn * u2.x, u0.y + sgn * u2.y);
-            const float2 Od = make_float2(u1.x + sgn * u3.x, u1.y + sgn * u3.y);
-            float2 R;
-            if (k1o == 0) R = Od;
-            else if (k1o == 1) R = make_float2(Od.y, -Od.x);
-            else if (k1o == 2) R = make_float2(-Od.x, -Od.y);
-            else R = make_float2(-Od.y, Od.x);
-            lds[q * kSStride + k1o * kKStride + p1 * 16 + il] = cmul(E + R, tw_o);
+            // u_j (j = 0..3) of this receiver, complex, gathered from the quad:
+            // lane (comp, jh) holds component comp of branches j = 2 jh + jj
+            const float2 u0 = make_float2(quad_bcast<0>(u[0]), quad_bcast<1>(u[0]));
+            const float2 u1 = make_float2(quad_bcast<0>(u[1]), quad_bcast<1>(u[1]));
+            const float2 u2 = make_float2(quad_bcast<2>(u[0]), quad_bcast<3>(u[0]));
+            const float2 u3 = make_float2(quad_bcast<2>(u[1]), quad_bcast<3>(u[1]));
+            // A[k1] = E + (-i)^k1 Od,  E = u0 + (-1)^k1 u2,  Od = u1 + (-1)^k1 u3;
+            // the output A[k1] tw = E tw + Od ((-i)^k1 tw)
+            const float2 E = make_float2(fmaf(sgn, u2.x, u0.x), fmaf(sgn, u2.y, u0.y));
+            const float2 Od = make_float2(fmaf(sgn, u3.x, u1.x), fmaf(sgn, u3.y, u1.y));
+            float2 o = cmul(E, tw_o);
+            o.x = fmaf(Od.x, rtw_o.x, fmaf(-Od.y, rtw_o.y, o.x));
+            o.y = fmaf(Od.x, rtw_o.y, fmaf(Od.y, rtw_o.x, o.y));
+            lds[q * kSStride + k1o * kKStride + p1 * 16 + il] = o;
             __builtin_amdgcn_sched_barrier(0);
         }
-        __syncthreads();
+        lds_barrier();
         {
             float2 a[16];
             const float2* src = lds + (8 * bh + sl) * kSStride + k1 * kKStride + ilf;
@@ -246,7 +245,7 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
                     }
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -254,14 +253,17 @@ template <int DT>
 __global__ __launch_bounds__(kThreads) void ppf_kernel(const int16_t* __restrict__ x, const float* __restrict__ taps,
                                                        void* __restrict__ z, Tw64 tw, int64_t x_sb_stride,
                                                        int64_t z_sb_bytes, int N, int S, int Sb, int n_groups,
-                                                       int n_chunks, float gain) {
+                                                       int n_chunks, int total, int per_xcd, float gain) {
     __shared__ float2 lds[kSpectraPerPhase * kSStride];
     __shared__ __attribute__((aligned(16))) float ltaps[kT * kP];
-    int bid = blockIdx.x;
-    const int chunk = bid % n_chunks;
-    bid /= n_chunks;
-    const int grp = bid % n_groups;
-    const int sb = bid / n_groups;
+    // workgroups go round-robin over the 8 XCDs: give each XCD a contiguous
+    // range with neighbouring receiver groups (which share 128-byte lines of
+    // the input rows) adjacent in time
+    const int w = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (w >= total) return;
+    const int grp = w % n_groups;
+    const int chunk = (w / n_groups) % n_chunks;
+    const int sb = w / (n_groups * n_chunks);
     const int s_begin = chunk * kChunk;
     const int s_end = min(S, s_begin + kChunk);
     ppf_body<DT>(x + sb * x_sb_stride, taps, reinterpret_cast<char*>(z) + sb * z_sb_bytes, tw, N, S, Sb,
@@ -309,20 +311,22 @@ hipError_t launch_ppf(const PpfLaunch& a, hipStream_t stream) {
     static const Tw64 tw = make_twiddles();
     const int n_groups = (int)ceil_div(a.N, kNi);
     const int n_chunks = (int)ceil_div(a.S, kChunk);
-    const dim3 grid((unsigned)((int64_t)a.B * n_groups * n_chunks));
+    const int total = (int)((int64_t)a.B * n_groups * n_chunks);
+    const int per_xcd = (int)ceil_div(total, 8);
+    const dim3 grid((unsigned)(per_xcd * 8));
     const int64_t z_sb_bytes = a.z_sb_stride * sample_bytes(a.dt);
     switch (a.dt) {
         case AFC_F32:
             hipLaunchKernelGGL(ppf_kernel<AFC_F32>, grid, dim3(kThreads), 0, stream, a.x, a.taps, a.z, tw,
-                               a.x_sb_stride, z_sb_bytes, a.N, a.S, a.Sb, n_groups, n_chunks, a.gain);
+                               a.x_sb_stride, z_sb_bytes, a.N, a.S, a.Sb, n_groups, n_chunks, total, per_xcd, a.gain);
             break;
         case AFC_F16:
             hipLaunchKernelGGL(ppf_kernel<AFC_F16>, grid, dim3(kThreads), 0, stream, a.x, a.taps, a.z, tw,
-                               a.x_sb_stride, z_sb_bytes, a.N, a.S, a.Sb, n_groups, n_chunks, a.gain);
+                               a.x_sb_stride, z_sb_bytes, a.N, a.S, a.Sb, n_groups, n_chunks, total, per_xcd, a.gain);
             break;
         default:
             hipLaunchKernelGGL(ppf_kernel<AFC_I8>, grid, dim3(kThreads), 0, stream, a.x, a.taps, a.z, tw,
-                               a.x_sb_stride, z_sb_bytes, a.N, a.S, a.Sb, n_groups, n_chunks, a.gain);
+                               a.x_sb_stride, z_sb_bytes, a.N, a.S, a.Sb, n_groups, n_chunks, total, per_xcd, a.gain);
             break;
     }
     return hipGetLastError();

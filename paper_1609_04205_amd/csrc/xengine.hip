@@ -26,6 +26,8 @@
 //   fp32  v_mfma_f32_32x32x2_f32  ( 2 spectra per K-step), fp32 sums, summed
 //         in two levels (blocks of 64 spectra into a second accumulator) to
 //         keep the rounding error of 3051-term sums near 1e-7 relative
+#include <type_traits>
+
 #include "afc_internal.h"
 
 namespace afc {
@@ -54,10 +56,54 @@ template <> struct XT<AFC_F32> {
     using acc_t = v16f;
 };
 // spectrum blocks per LDS stage (fp16 at 128 keeps its prefetch registers down)
+#ifndef AFC_I8_STAGE_BLOCKS
+#define AFC_I8_STAGE_BLOCKS 4
+#endif
 template <int DT, int TILE>
-constexpr int stage_blocks() { return (DT == AFC_F16 && TILE == 128) ? 2 : 4; }
+constexpr int stage_blocks() {
+    return (DT == AFC_F16 && TILE == 128) ? 2 : (DT == AFC_I8 && TILE == 128) ? AFC_I8_STAGE_BLOCKS : 4;
+}
+#ifndef AFC_PREFETCH_DEPTH
+#define AFC_PREFETCH_DEPTH 2
+#endif
 template <int DT, int TILE>
-constexpr int lds_bytes() { return 2 * 2 * stage_blocks<DT, TILE>() * TILE * XT<DT>::RB; }
+constexpr int prefetch_depth() { return (DT == AFC_F16 && TILE == 128) ? 1 : AFC_PREFETCH_DEPTH; }
+// int8 and fp16 stage through direct global-to-LDS loads (three buffers);
+// fp32 through registers (two buffers)
+template <int DT>
+constexpr bool uses_dma() { return DT != AFC_F32; }
+#ifndef AFC_DMA_DEPTH
+#define AFC_DMA_DEPTH 2
+#endif
+constexpr int kDmaDepth = AFC_DMA_DEPTH;      // stages of global-to-LDS loads in flight
+template <int DT, int TILE>
+constexpr int lds_bytes() {
+    return (uses_dma<DT>() ? kDmaDepth + 1 : 2) * 2 * stage_blocks<DT, TILE>() * TILE * XT<DT>::RB;
+}
+
+
+// Workgroup barrier for the DMA pipeline: no memory fence (which would wait
+// for every outstanding global-to-LDS load); a compiler-level memory clobber
+// keeps LDS accesses on their side of it.
+__device__ __forceinline__ void dma_barrier() {
+    __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// s_waitcnt vmcnt(N) with the other counters left at their maximum
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt");
+    __builtin_amdgcn_s_waitcnt((N & 15) | (((N >> 4) & 3) << 14) | 0x0F70);
+}
+
+// s_waitcnt vmcnt(PER * k) for a runtime k in [0, kDmaDepth - 1] (uniform)
+template <int PER>
+__device__ __forceinline__ void wait_vmcnt_runtime(int k) {
+    if (k <= 0) wait_vmcnt<0>();
+    else if (k == 1 || kDmaDepth <= 2) wait_vmcnt<PER>();
+    else if (k == 2 || kDmaDepth <= 3) wait_vmcnt<(2 * PER < 63 ? 2 * PER : 63)>();
+    else wait_vmcnt<(3 * PER < 63 ? 3 * PER : 63)>();
+}
 
 // 16-byte chunk q of receiver row r lives at chunk slot q ^ swz(r)
 template <int RB, int PLANES>
@@ -66,11 +112,16 @@ __device__ __forceinline__ int swz(int r) {
     else return (r / (256 / RB)) % PLANES;
 }
 
-// (re, im) -> (-im, re) on packed int8 pairs
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// (re, im) -> (-im, re) on packed int8 pairs: swap the bytes of each pair,
+// negate each pair as a 16-bit number (its low byte becomes -im mod 256),
+// keep the low bytes of that and the high bytes (re) of the swapped word.
 __device__ __forceinline__ int jswap_i8(int w) {
-    const unsigned u = (unsigned)w;
-    const unsigned t = ((u & 0x00FF00FFu) << 8) | ((u >> 8) & 0x00FF00FFu);   // (im, re) per pair
-    return (int)((t & 0xFF00FF00u) | ((0x01000100u - (t & 0x00FF00FFu)) & 0x00FF00FFu));
+    const unsigned t = __builtin_amdgcn_perm((unsigned)w, (unsigned)w, 0x02030001u);   // (im, re) per pair
+    const u16x2 n = (u16x2)0 - __builtin_bit_cast(u16x2, t);
+    const unsigned nb = __builtin_bit_cast(unsigned, n);
+    return (int)((nb & 0x00FF00FFu) | (t & 0xFF00FF00u));
 }
 // (re, im) -> (-im, re) on packed fp16 pairs
 __device__ __forceinline__ int jswap_f16(int w) {
@@ -130,6 +181,7 @@ __device__ __forceinline__ void xtile(const char* __restrict__ z, char* __restri
     constexpr int PANEL = kStg * TILE * RB;                  // bytes of one panel in one stage
     constexpr int CHUNKS = kStg * TILE * PLANES;             // 16-byte chunks per panel per stage
     constexpr int CPT = CHUNKS / kThreads;
+    constexpr bool kDma = uses_dma<DT>();
     using acc_t = typename Tr::acc_t;
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -154,8 +206,15 @@ __device__ __forceinline__ void xtile(const char* __restrict__ z, char* __restri
             outI[m][n] = acc_t{};
         }
 
-    uint4 pre[2][CPT];
-    auto load_stage = [&](int st) {
+    // Loads are issued unconditionally from clamped addresses (always in
+    // bounds) so that none of them waits on another; rows beyond N, blocks
+    // beyond the subband's spectra and the tail spectra of the last block are
+    // zeroed when the staged registers are written to LDS, after the compute
+    // of the current stage has hidden the load latency.
+    constexpr int DEPTH = prefetch_depth<DT, TILE>();   // stages of loads in flight
+    uint4 pre[DEPTH][2][CPT];
+    auto load_stage = [&](int st, auto slot_tag) {
+        constexpr int slot = decltype(slot_tag)::value;
 #pragma unroll
         for (int pn = 0; pn < 2; ++pn) {
             if (pn == 1 && diag) break;
@@ -166,21 +225,23 @@ __device__ __forceinline__ void xtile(const char* __restrict__ z, char* __restri
                 const int bl = chunk / (TILE * PLANES);
                 const int rem = chunk % (TILE * PLANES);
                 const int row = rem / PLANES, q = rem % PLANES;
-                const int blk = st * kStg + bl;
-                const int rg = r0 + row;
-                uint4 v = make_uint4(0u, 0u, 0u, 0u);
-                if (blk < nb && rg < N) {
-                    v = *reinterpret_cast<const uint4*>(z + ((int64_t)blk * N + rg) * RB + q * 16);
-                    if (blk == nb - 1 && tail_valid < kSBlk) v = mask_tail<DT>(v, q, tail_valid);
-                }
-                pre[pn][c] = v;
+                const int blk = min(st * kStg + bl, nb - 1);
+                const int rg = min(r0 + row, N - 1);
+                pre[slot][pn][c] = *reinterpret_cast<const uint4*>(z + ((int64_t)blk * N + rg) * RB + q * 16);
             }
         }
     };
-    auto store_stage = [&](int buf) {
+    // a stage needs no masking when all its blocks are whole and in range and
+    // both panels' rows are below N (uniform over the workgroup)
+    const bool rows_full = i0 + TILE <= N && j0 + TILE <= N;
+    const int full_blocks = tail_valid < kSBlk ? nb - 1 : nb;
+    auto store_stage = [&](int st, int buf, auto slot_tag) {
+        constexpr int slot = decltype(slot_tag)::value;
+        const bool clean = rows_full && (st + 1) * kStg <= full_blocks;
 #pragma unroll
         for (int pn = 0; pn < 2; ++pn) {
             if (pn == 1 && diag) break;
+            const int r0 = pn == 0 ? i0 : j0;
             char* base = lds_raw + (buf * 2 + pn) * PANEL;
 #pragma unroll
             for (int c = 0; c < CPT; ++c) {
@@ -188,8 +249,13 @@ __device__ __forceinline__ void xtile(const char* __restrict__ z, char* __restri
                 const int bl = chunk / (TILE * PLANES);
                 const int rem = chunk % (TILE * PLANES);
                 const int row = rem / PLANES, q = rem % PLANES;
-                *reinterpret_cast<uint4*>(base + bl * TILE * RB + row * RB + ((q ^ swz<RB, PLANES>(row)) * 16)) =
-                    pre[pn][c];
+                const int blk = st * kStg + bl;
+                uint4 v = pre[slot][pn][c];
+                if (!clean) {
+                    if (blk >= nb || r0 + row >= N) v = make_uint4(0u, 0u, 0u, 0u);
+                    else if (blk == nb - 1 && tail_valid < kSBlk) v = mask_tail<DT>(v, q, tail_valid);
+                }
+                *reinterpret_cast<uint4*>(base + bl * TILE * RB + row * RB + ((q ^ swz<RB, PLANES>(row)) * 16)) = v;
             }
         }
     };
@@ -200,14 +266,8 @@ __device__ __forceinline__ void xtile(const char* __restrict__ z, char* __restri
     const int lr = lane & 31, lh = lane >> 5;
     int fold = 0;
 
-    load_stage(0);
-    store_stage(0);
-    __syncthreads();
-    for (int st = 0; st < n_stages; ++st) {
-        const int buf = st & 1;
-        if (st + 1 < n_stages) load_stage(st + 1);
-        const char* PA = lds_raw + (buf * 2 + 0) * PANEL;
-        const char* PB = lds_raw + (buf * 2 + (diag ? 0 : 1)) * PANEL;
+    // MFMAs of one stage from the panels PA (rows) and PB (columns)
+    auto compute = [&](const char* PA, const char* PB) {
         if (wave_on) {
             if constexpr (DT == AFC_I8) {
 #pragma unroll
@@ -297,10 +357,92 @@ __device__ __forceinline__ void xtile(const char* __restrict__ z, char* __restri
                 }
             }
         }
-        __syncthreads();
-        if (st + 1 < n_stages) {
-            store_stage(buf ^ 1);
-            __syncthreads();
+    };
+
+    if constexpr (kDma) {
+        // Stages made of whole blocks go straight from global memory to LDS
+        // (global_load_lds: lane L of a wave writes 16 bytes at M0 + 16 L),
+        // kDmaDepth stages ahead, in a ring of kDmaDepth + 1 buffers.  Rows
+        // beyond N read row N-1: they only feed outputs that are never
+        // stored.  The remaining (partial) stage goes through registers with
+        // masking.
+        constexpr int NB = kDmaDepth + 1;
+        const int n_clean = full_blocks / kStg;
+        auto issue = [&](int st) {
+            const int bq = st % NB;
+#pragma unroll
+            for (int pn = 0; pn < 2; ++pn) {
+                if (pn == 1 && diag) break;
+                const int r0 = pn == 0 ? i0 : j0;
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) {
+                    const int chunk = tid + c * kThreads;
+                    const int bl = chunk / (TILE * PLANES);
+                    const int rem = chunk % (TILE * PLANES);
+                    const int row = rem / PLANES, sl = rem % PLANES;
+                    const int q = sl ^ swz<RB, PLANES>(row);
+                    const int blk = st * kStg + bl;
+                    const char* src = z + ((int64_t)blk * N + min(r0 + row, N - 1)) * RB + q * 16;
+                    char* dst = lds_raw + (bq * 2 + pn) * PANEL + (c * kThreads + wid * 64) * 16;
+                    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+                }
+            }
+        };
+#pragma unroll
+        for (int d = 0; d < kDmaDepth; ++d)
+            if (d < n_clean) issue(d);
+        for (int st = 0; st < n_clean; ++st) {
+            // this wave's loads of stage st have landed once at most the
+            // later stages already issued (up to kDmaDepth - 1) are outstanding
+            const int later = min(n_clean - 1 - st, kDmaDepth - 1);
+            if (diag) wait_vmcnt_runtime<CPT>(later);
+            else wait_vmcnt_runtime<2 * CPT>(later);
+            // plain s_barrier: the explicit wait above already covers the
+            // LDS written by this wave's DMA loads (an LDS fence here would
+            // also wait for the stages still in flight)
+            dma_barrier();
+            if (st + kDmaDepth < n_clean) issue(st + kDmaDepth);
+            const int bq = st % NB;
+            compute(lds_raw + (bq * 2) * PANEL, lds_raw + (bq * 2 + (diag ? 0 : 1)) * PANEL);
+        }
+        using S0 = std::integral_constant<int, 0>;
+        for (int st = n_clean; st < n_stages; ++st) {
+            load_stage(st, S0{});
+            lds_barrier();
+            store_stage(st, 0, S0{});
+            lds_barrier();
+            compute(lds_raw, lds_raw + (diag ? 0 : 1) * PANEL);
+        }
+        lds_barrier();
+    } else {
+        // Register staging with one barrier per stage: at stage st the
+        // registers hold the samples of the next DEPTH stages; stage st+1 goes
+        // to the other LDS buffer first, its register slot is refilled with
+        // stage st+1+DEPTH, then stage st is multiplied from its buffer.  The
+        // barrier at the end of the stage orders both the buffer just written
+        // (read at st+1) and the buffer just read (written at st+1).  Stage k
+        // lives in register slot k % DEPTH; the loop is unrolled by DEPTH so
+        // that every slot index is a constant.
+        using S0 = std::integral_constant<int, 0>;
+        using S1 = std::integral_constant<int, (DEPTH > 1 ? 1 : 0)>;
+        load_stage(0, S0{});
+        store_stage(0, 0, S0{});
+        if (n_stages > 1) load_stage(1, S1{});
+        if (DEPTH > 1 && n_stages > 2) load_stage(2, S0{});
+        lds_barrier();
+        auto step = [&](int st, auto slot_tag) {
+            const int buf = st & 1;
+            if (st + 1 < n_stages) {
+                store_stage(st + 1, buf ^ 1, slot_tag);
+                if (st + 1 + DEPTH < n_stages) load_stage(st + 1 + DEPTH, slot_tag);
+            }
+            compute(lds_raw + (buf * 2 + 0) * PANEL, lds_raw + (buf * 2 + (diag ? 0 : 1)) * PANEL);
+            lds_barrier();
+        };
+        // stage st consumes slot (st + 1) % DEPTH
+        for (int st = 0; st < n_stages; st += 2) {
+            step(st, S1{});
+            if (st + 1 < n_stages) step(st + 1, S0{});
         }
     }
     if constexpr (DT == AFC_F32) {
@@ -317,6 +459,31 @@ __device__ __forceinline__ void xtile(const char* __restrict__ z, char* __restri
     // ---- epilogue: 2x2 polarisation blocks of antennas a >= b
     const int64_t nbl = (int64_t)Na * (Na + 1) / 2;
     (void)nbl;
+    // flags of this lane's row antennas (8 per 32-row block) and column
+    // antennas, fetched together before the stores
+    bool frow[MB][8], fcol[MB];
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+        fcol[m] = false;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) frow[m][k] = false;
+    }
+    if (fl_sb) {
+        uint8_t fc[MB], fr[MB][8];
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+            fc[m] = fl_sb[min(j0 + wc * WT + m * 32 + lr, N - 1) >> 1];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                fr[m][k] = fl_sb[min(i0 + wr * WT + m * 32 + 8 * (k >> 1) + 4 * lh + 2 * (k & 1), N - 1) >> 1];
+        }
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+            fcol[m] = fc[m] != 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) frow[m][k] = fr[m][k] != 0;
+        }
+    }
 #pragma unroll
     for (int m = 0; m < MB; ++m)
 #pragma unroll
@@ -325,14 +492,14 @@ __device__ __forceinline__ void xtile(const char* __restrict__ z, char* __restri
             const int J = j0 + wc * WT + n * 32 + lr;
             if (J >= N) continue;
             const int b = J >> 1, qq = J & 1;
-            const bool fb = fl_sb ? fl_sb[b] != 0 : false;
+            const bool fb = fcol[n];
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int I = i0 + wr * WT + m * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
                 if (I >= N) continue;
                 const int a = I >> 1, p = I & 1;
                 if (a < b) continue;
-                const bool flagged = fb || (fl_sb ? fl_sb[a] != 0 : false);
+                const bool flagged = fb || frow[m][((r >> 2) << 1) | ((r >> 1) & 1)];
                 const int64_t bl = (int64_t)a * (a + 1) / 2 + b;
                 const int64_t e = bl * 4 + p * 2 + qq;
                 if constexpr (DT == AFC_I8) {
@@ -358,7 +525,11 @@ __global__ __launch_bounds__(kThreads, 2) void xengine_kernel(XArgs a) {
     // XCDs; give each XCD a contiguous range of work so that the tiles of one
     // channel share that XCD's L2.
     const int bid = blockIdx.x;
+#ifdef AFC_NO_XCD_ORDER
+    const int w = bid;
+#else
     const int w = (bid & 7) * a.per_xcd + (bid >> 3);
+#endif
     if (w >= a.total) return;
     const int t = w % a.n_tiles;
     const int rest = w / a.n_tiles;
@@ -409,7 +580,7 @@ __global__ __launch_bounds__(kThreads, WPC) void xengine_persistent_kernel(
             const char* z = z_ws + sd.z_off + (int64_t)wk.ch * sd.Sb * N * kSBlk * 8;
             xtile<AFC_F32, TILE>(z, vis_ch, wsb, fl, N, Na, sd.S, wk.ti, wk.tj, ww, lds);
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
