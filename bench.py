@@ -36,6 +36,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel_key):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by a plain 1 GiB copy), or
+    None when the kernel's source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        d = json.load(open(path))
+        k = d["kernels"][kernel_key]
+        src = os.path.join(ROOT, "paper_1609_04205_amd", "csrc", k["source"])
+        if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != k["source_sha256_16"]:
+            return None
+        return round(k["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -44,6 +61,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="time only the int8 step")
     ap.add_argument("--cpu-sample-spectra", type=int, default=512)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (three times), to scale HBM byte counters")
     return ap.parse_args()
 
 
@@ -75,6 +94,15 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        a = torch.ones((1 << 30) // 4, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 1 << 30, "copies": 3}), flush=True)
+        return
 
     import paper_1609_04205_amd as afc
     import workloads as W
@@ -153,9 +181,10 @@ def main():
         "ppf_valu_frac": round(ppf_flops / (ppf_ms * 1e-3) / 1e12 / PEAK_FP32_VALU_TFLOPS, 4),
     }
     ppf_roof = {"bound": "hbm", "achieved": round(ppf_bytes / (ppf_ms * 1e-3) / 1e9, 1), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": round(ppf_bytes / (ppf_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4), "traffic": None}
+                "unit": "GB/s", "frac": round(ppf_bytes / (ppf_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                "traffic": measured_traffic("ppf_kernel<int8>")}
     xe_roof = {"bound": "mfma", "achieved": round(xe_tops, 2), "peak": PEAK_INT8_TOPS, "unit": "TFLOP/s",
-               "frac": round(xe_tops / PEAK_INT8_TOPS, 4), "traffic": None}
+               "frac": round(xe_tops / PEAK_INT8_TOPS, 4), "traffic": measured_traffic("xengine_kernel<int8,128>")}
     out["roofline"] = xe_roof if xe_ms >= ppf_ms else ppf_roof
     out["roofline_other"] = ppf_roof if xe_ms >= ppf_ms else xe_roof
     log(f"int8 step {ms_step:.3f} ms (ppf {ppf_ms:.3f}, xengine {xe_ms:.3f})")
