@@ -203,12 +203,7 @@ struct afc_plan {
 
 namespace {
 
-int num_cus() {
-    int dev = 0;
-    hipDeviceProp_t p;
-    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return 256;
-    return std::max(1, p.multiProcessorCount);
-}
+int num_cus() { return device_cu_count(); }
 
 // Cost of one tile item in MFMA cycles per spectrum (per SIMD), from the
 // instruction rates: int8 32x32x32 and fp16 32x32x16 take the same cycles,

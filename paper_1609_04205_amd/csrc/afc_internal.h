@@ -14,6 +14,8 @@ constexpr int kSBlk = AFC_SPECTRUM_BLOCK;
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int sample_bytes(afc_dtype t) { return t == AFC_F32 ? 8 : t == AFC_F16 ? 4 : 2; }
+// compute units of the current device (cached per device)
+int device_cu_count();
 
 // ---------------------------------------------------------------- PPF
 struct PpfLaunch {

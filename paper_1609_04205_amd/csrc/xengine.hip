@@ -26,6 +26,7 @@
 //   fp32  v_mfma_f32_32x32x2_f32  ( 2 spectra per K-step), fp32 sums, summed
 //         in two levels (blocks of 64 spectra into a second accumulator) to
 //         keep the rounding error of 3051-term sums near 1e-7 relative
+#include <algorithm>
 #include <type_traits>
 
 #include "afc_internal.h"
@@ -55,38 +56,51 @@ template <> struct XT<AFC_F32> {
     static constexpr int RB = 64, PLANES = 4;
     using acc_t = v16f;
 };
-// spectrum blocks per LDS stage (fp16 at 128 keeps its prefetch registers down)
+// spectrum blocks per LDS stage
 #ifndef AFC_I8_STAGE_BLOCKS
 #define AFC_I8_STAGE_BLOCKS 4
 #endif
-template <int DT, int TILE>
-constexpr int stage_blocks() {
-    return (DT == AFC_F16 && TILE == 128) ? 2 : (DT == AFC_I8 && TILE == 128) ? AFC_I8_STAGE_BLOCKS : 4;
-}
-#ifndef AFC_PREFETCH_DEPTH
-#define AFC_PREFETCH_DEPTH 2
+#ifndef AFC_F16_STAGE_BLOCKS
+#define AFC_F16_STAGE_BLOCKS 2
 #endif
 template <int DT, int TILE>
-constexpr int prefetch_depth() { return (DT == AFC_F16 && TILE == 128) ? 1 : AFC_PREFETCH_DEPTH; }
-// int8 and fp16 stage through direct global-to-LDS loads (three buffers);
-// fp32 through registers (two buffers)
+constexpr int stage_blocks() {
+    return DT == AFC_F32 ? 4 : TILE != 128 ? (DT == AFC_I8 ? 4 : 2)
+                                           : DT == AFC_I8 ? AFC_I8_STAGE_BLOCKS : AFC_F16_STAGE_BLOCKS;
+}
+// fp32: stages of register-staged loads in flight
+template <int DT, int TILE>
+constexpr int prefetch_depth() { return 2; }
+// int8 and fp16 stage through direct global-to-LDS loads, fp32 through registers
 template <int DT>
 constexpr bool uses_dma() { return DT != AFC_F32; }
 #ifndef AFC_DMA_DEPTH
 #define AFC_DMA_DEPTH 2
 #endif
 constexpr int kDmaDepth = AFC_DMA_DEPTH;      // stages of global-to-LDS loads in flight
+// DMA ring: the stage being multiplied, the next one (already landed when
+// its first operands are read) and kDmaDepth - 1 further stages in flight,
+// plus the buffer being refilled
+constexpr int kDmaBuffers = kDmaDepth + 2;
 template <int DT, int TILE>
 constexpr int lds_bytes() {
-    return (uses_dma<DT>() ? kDmaDepth + 1 : 2) * 2 * stage_blocks<DT, TILE>() * TILE * XT<DT>::RB;
+    return (uses_dma<DT>() ? kDmaBuffers : 2) * 2 * stage_blocks<DT, TILE>() * TILE * XT<DT>::RB;
 }
-
 
 // Workgroup barrier for the DMA pipeline: no memory fence (which would wait
 // for every outstanding global-to-LDS load); a compiler-level memory clobber
 // keeps LDS accesses on their side of it.
 __device__ __forceinline__ void dma_barrier() {
     __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// 16 bytes per lane from base + voff + soff (a raw buffer of `bytes` bytes)
+// into LDS: lane L of the wave writes dst + 16 L (dst wave-uniform)
+__device__ __forceinline__ void buffer_load_lds16(const char* base, int bytes, char* dst, int voff, int soff) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, bytes, 0x00020000);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)dst, 16, voff, soff, 0, 0);
+#endif
 }
 
 // s_waitcnt vmcnt(N) with the other counters left at their maximum
@@ -181,6 +195,7 @@ __device__ __forceinline__ void xtile(const char* __restrict__ z, char* __restri
     constexpr int PANEL = kStg * TILE * RB;                  // bytes of one panel in one stage
     constexpr int CHUNKS = kStg * TILE * PLANES;             // 16-byte chunks per panel per stage
     constexpr int CPT = CHUNKS / kThreads;
+    static_assert(CHUNKS % kThreads == 0, "a stage must split evenly over the threads");
     constexpr bool kDma = uses_dma<DT>();
     using acc_t = typename Tr::acc_t;
 
@@ -266,52 +281,77 @@ __device__ __forceinline__ void xtile(const char* __restrict__ z, char* __restri
     const int lr = lane & 31, lh = lane >> 5;
     int fold = 0;
 
+    // Operands of one k-step (int8: 16 spectra, fp16: 8 spectra) of this
+    // wave: row blocks m of panel PA and column blocks n of panel PB.
+    constexpr int NKK = DT == AFC_I8 ? kStg / 2 : kStg;
+    // (unconditional, also in waves that skip their MFMAs, so that the LDS
+    // wait counts stay exact across the branches)
+    auto load_ops = [&](const char* PA, const char* PB, int kk, uint4 (&oa)[MB], uint4 (&ob)[MB]) {
+        const int bl = DT == AFC_I8 ? 2 * kk + lh : kk;
+        const int q = DT == AFC_I8 ? 0 : lh;
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+            oa[m] = rd(PA, bl, wr * WT + m * 32 + lr, q);
+            ob[m] = rd(PB, bl, wc * WT + m * 32 + lr, q);
+        }
+    };
+    // MFMAs of one k-step.  `mid` runs after the first block's two MFMAs
+    // have been issued (the scheduler may not move work across it): loads
+    // of the next operands issued there overlap the remaining MFMAs.
+    auto mma = [&](const uint4 (&oa)[MB], const uint4 (&ob)[MB], auto&& mid) {
+        using V = std::conditional_t<DT == AFC_I8, v4i, v8h>;
+        auto cvt = [](uint4 u) -> V {
+            if constexpr (DT == AFC_I8) return v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
+            else return __builtin_bit_cast(v8h, u);
+        };
+        auto jsw = [](uint4 u) -> V {
+            if constexpr (DT == AFC_I8)
+                return v4i{jswap_i8((int)u.x), jswap_i8((int)u.y), jswap_i8((int)u.z), jswap_i8((int)u.w)};
+            else
+                return __builtin_bit_cast(v8h, make_uint4((unsigned)jswap_f16((int)u.x), (unsigned)jswap_f16((int)u.y),
+                                                          (unsigned)jswap_f16((int)u.z), (unsigned)jswap_f16((int)u.w)));
+        };
+        auto op = [&](auto& acc, V x, V y) {
+            if constexpr (DT == AFC_I8) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(x, y, acc, 0, 0, 0);
+            else acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(x, y, acc, 0, 0, 0);
+        };
+        if (wave_on) {
+            const V a0 = cvt(oa[0]);
+            op(accR[0][0], a0, cvt(ob[0]));
+            op(accI[0][0], a0, jsw(ob[0]));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        mid();
+        __builtin_amdgcn_sched_barrier(0);
+        if (wave_on) {
+            V a[MB], b[MB], bj[MB];
+#pragma unroll
+            for (int m = 0; m < MB; ++m) {
+                a[m] = cvt(oa[m]);
+                b[m] = cvt(ob[m]);
+                bj[m] = jsw(ob[m]);
+            }
+#pragma unroll
+            for (int m = 0; m < MB; ++m)
+#pragma unroll
+                for (int n = 0; n < MB; ++n) {
+                    if ((m == 0 && n == 0) || (diag && wr == wc && m < n)) continue;
+                    op(accR[m][n], a[m], b[n]);
+                    op(accI[m][n], a[m], bj[n]);
+                }
+        }
+    };
+    auto nothing = [] {};
+
     // MFMAs of one stage from the panels PA (rows) and PB (columns)
     auto compute = [&](const char* PA, const char* PB) {
         if (wave_on) {
-            if constexpr (DT == AFC_I8) {
+            if constexpr (DT != AFC_F32) {
 #pragma unroll
-                for (int kk = 0; kk < kStg / 2; ++kk) {
-                    v4i a[MB], b[MB], bj[MB];
-#pragma unroll
-                    for (int m = 0; m < MB; ++m) {
-                        const uint4 u = rd(PA, 2 * kk + lh, wr * WT + m * 32 + lr, 0);
-                        a[m] = v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
-                        const uint4 w = rd(PB, 2 * kk + lh, wc * WT + m * 32 + lr, 0);
-                        b[m] = v4i{(int)w.x, (int)w.y, (int)w.z, (int)w.w};
-                        bj[m] = v4i{jswap_i8((int)w.x), jswap_i8((int)w.y), jswap_i8((int)w.z), jswap_i8((int)w.w)};
-                    }
-#pragma unroll
-                    for (int m = 0; m < MB; ++m)
-#pragma unroll
-                        for (int n = 0; n < MB; ++n) {
-                            if (diag && wr == wc && m < n) continue;
-                            accR[m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[m], b[n], accR[m][n], 0, 0, 0);
-                            accI[m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[m], bj[n], accI[m][n], 0, 0, 0);
-                        }
-                }
-            } else if constexpr (DT == AFC_F16) {
-#pragma unroll
-                for (int kk = 0; kk < kStg; ++kk) {
-                    v8h a[MB], b[MB], bj[MB];
-#pragma unroll
-                    for (int m = 0; m < MB; ++m) {
-                        const uint4 u = rd(PA, kk, wr * WT + m * 32 + lr, lh);
-                        a[m] = __builtin_bit_cast(v8h, u);
-                        const uint4 w = rd(PB, kk, wc * WT + m * 32 + lr, lh);
-                        b[m] = __builtin_bit_cast(v8h, w);
-                        const uint4 wj = make_uint4((unsigned)jswap_f16((int)w.x), (unsigned)jswap_f16((int)w.y),
-                                                    (unsigned)jswap_f16((int)w.z), (unsigned)jswap_f16((int)w.w));
-                        bj[m] = __builtin_bit_cast(v8h, wj);
-                    }
-#pragma unroll
-                    for (int m = 0; m < MB; ++m)
-#pragma unroll
-                        for (int n = 0; n < MB; ++n) {
-                            if (diag && wr == wc && m < n) continue;
-                            accR[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[m], b[n], accR[m][n], 0, 0, 0);
-                            accI[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[m], bj[n], accI[m][n], 0, 0, 0);
-                        }
+                for (int kk = 0; kk < NKK; ++kk) {
+                    uint4 oa[MB], ob[MB];
+                    load_ops(PA, PB, kk, oa, ob);
+                    mma(oa, ob, nothing);
                 }
             } else {
 #pragma unroll
@@ -361,57 +401,126 @@ __device__ __forceinline__ void xtile(const char* __restrict__ z, char* __restri
 
     if constexpr (kDma) {
         // Stages made of whole blocks go straight from global memory to LDS
-        // (global_load_lds: lane L of a wave writes 16 bytes at M0 + 16 L),
-        // kDmaDepth stages ahead, in a ring of kDmaDepth + 1 buffers.  Rows
-        // beyond N read row N-1: they only feed outputs that are never
-        // stored.  The remaining (partial) stage goes through registers with
-        // masking.
-        constexpr int NB = kDmaDepth + 1;
-        const int n_clean = full_blocks / kStg;
+        // (global_load_lds: lane L of a wave writes 16 bytes at M0 + 16 L)
+        // through a ring of kDmaBuffers buffers.  Rows beyond N read row N-1:
+        // they only feed outputs that are never stored.  In the last stage,
+        // blocks beyond the subband's data read the last block again and
+        // every operand of a block at or beyond the partial last block is
+        // masked in registers (spectra >= S become zero).
+        //
+        // Per stage st, one barrier, placed before its last k-step: by then
+        // stage st+1 has landed (each wave waits for its own loads first),
+        // every wave has finished stage st-1, so the loads of stage
+        // st+1+kDmaDepth can refill st-1's buffer, and the first operands of
+        // st+1 are read from LDS while the last MFMAs of st run.  Operands are
+        // double-buffered in registers one k-step ahead.
+        constexpr int NB = kDmaBuffers;
+        const int n_st = n_stages;
+        // Buffer loads (not global/flat ones, which the compiler must assume
+        // may also touch LDS, and would then wait for every LDS read at once).
+        // Byte offsets within the channel: voffset = this thread's chunk in
+        // stage 0, soffset = the stage (a channel of samples is far below
+        // 2 GiB: the entry points bound one subband of input to 2^31 values).
+        const int z_bytes = nb * N * RB;
+        int src_off[2][CPT];
+#pragma unroll
+        for (int pn = 0; pn < 2; ++pn)
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                const int chunk = tid + c * kThreads;
+                const int bl = chunk / (TILE * PLANES);
+                const int rem = chunk % (TILE * PLANES);
+                const int row = rem / PLANES, sl = rem % PLANES;
+                const int q = sl ^ swz<RB, PLANES>(row);
+                const int r0 = pn == 0 ? i0 : j0;
+                src_off[pn][c] = (bl * N + min(r0 + row, N - 1)) * RB + q * 16;
+            }
+        const int stage_bytes = kStg * N * RB;
         auto issue = [&](int st) {
             const int bq = st % NB;
+            const bool past_end = (st + 1) * kStg > nb;     // uniform
 #pragma unroll
             for (int pn = 0; pn < 2; ++pn) {
                 if (pn == 1 && diag) break;
-                const int r0 = pn == 0 ? i0 : j0;
 #pragma unroll
                 for (int c = 0; c < CPT; ++c) {
-                    const int chunk = tid + c * kThreads;
-                    const int bl = chunk / (TILE * PLANES);
-                    const int rem = chunk % (TILE * PLANES);
-                    const int row = rem / PLANES, sl = rem % PLANES;
-                    const int q = sl ^ swz<RB, PLANES>(row);
-                    const int blk = st * kStg + bl;
-                    const char* src = z + ((int64_t)blk * N + min(r0 + row, N - 1)) * RB + q * 16;
                     char* dst = lds_raw + (bq * 2 + pn) * PANEL + (c * kThreads + wid * 64) * 16;
-                    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+                    int voff = src_off[pn][c], soff = st * stage_bytes;
+                    if (past_end) {   // whole offset in voffset, block clamped to nb - 1
+                        const int bl = (tid + c * kThreads) / (TILE * PLANES);
+                        voff += (min(st * kStg + bl, nb - 1) - bl) * N * RB;
+                        soff = 0;
+                    }
+                    buffer_load_lds16(z, z_bytes, dst, voff, soff);
                 }
             }
         };
-#pragma unroll
-        for (int d = 0; d < kDmaDepth; ++d)
-            if (d < n_clean) issue(d);
-        for (int st = 0; st < n_clean; ++st) {
-            // this wave's loads of stage st have landed once at most the
-            // later stages already issued (up to kDmaDepth - 1) are outstanding
-            const int later = min(n_clean - 1 - st, kDmaDepth - 1);
+        // wait until this wave's loads of stage s have landed, given that
+        // the stages up to min(s + kDmaDepth - 1, n_st - 1) have been issued
+        auto wait_landed = [&](int s) {
+            const int later = min(n_st - 1 - s, kDmaDepth - 1);
             if (diag) wait_vmcnt_runtime<CPT>(later);
             else wait_vmcnt_runtime<2 * CPT>(later);
-            // plain s_barrier: the explicit wait above already covers the
-            // LDS written by this wave's DMA loads (an LDS fence here would
-            // also wait for the stages still in flight)
-            dma_barrier();
-            if (st + kDmaDepth < n_clean) issue(st + kDmaDepth);
+        };
+        auto panels = [&](int st, const char*& PA, const char*& PB) {
             const int bq = st % NB;
-            compute(lds_raw + (bq * 2) * PANEL, lds_raw + (bq * 2 + (diag ? 0 : 1)) * PANEL);
-        }
-        using S0 = std::integral_constant<int, 0>;
-        for (int st = n_clean; st < n_stages; ++st) {
-            load_stage(st, S0{});
-            lds_barrier();
-            store_stage(st, 0, S0{});
-            lds_barrier();
-            compute(lds_raw, lds_raw + (diag ? 0 : 1) * PANEL);
+            PA = lds_raw + (bq * 2) * PANEL;
+            PB = lds_raw + (bq * 2 + (diag ? 0 : 1)) * PANEL;
+        };
+        // Operand registers: set kk & 1 holds k-step kk of the current stage
+        // (NKK is even, so every stage starts in set 0).  The last stage is
+        // peeled off so that the loop body has no branch around LDS reads
+        // and the compiler's LDS wait counts stay exact.
+        static_assert(NKK % 2 == 0, "k-steps per stage must be even");
+        // zero the spectra >= S of this lane's operands of k-step kk of stage st
+        auto mask_tail_ops = [&](int st, int kk, uint4 (&a)[MB], uint4 (&b)[MB]) {
+            const int blk = st * kStg + (DT == AFC_I8 ? 2 * kk + lh : kk);
+            const int q = DT == AFC_I8 ? 0 : lh;
+            if (blk < nb - 1 || (blk == nb - 1 && tail_valid == kSBlk)) return;
+            const int valid = blk == nb - 1 ? tail_valid : 0;
+#pragma unroll
+            for (int m = 0; m < MB; ++m) {
+                a[m] = mask_tail<DT>(a[m], q, valid);
+                b[m] = mask_tail<DT>(b[m], q, valid);
+            }
+        };
+        uint4 oa[2][MB], ob[2][MB];
+        auto run_stage = [&](int st, auto has_next_tag) {
+            constexpr bool kNext = decltype(has_next_tag)::value;
+            const char *PA, *PB;
+            panels(st, PA, PB);
+#pragma unroll
+            for (int kk = 0; kk + 1 < NKK; ++kk) {
+                if constexpr (!kNext) mask_tail_ops(st, kk, oa[kk & 1], ob[kk & 1]);
+                mma(oa[kk & 1], ob[kk & 1], [&] { load_ops(PA, PB, kk + 1, oa[(kk + 1) & 1], ob[(kk + 1) & 1]); });
+            }
+            if constexpr (!kNext) mask_tail_ops(st, NKK - 1, oa[(NKK - 1) & 1], ob[(NKK - 1) & 1]);
+            mma(oa[(NKK - 1) & 1], ob[(NKK - 1) & 1], [&] {
+                if constexpr (kNext) {
+                    wait_landed(st + 1);
+                    dma_barrier();
+                    if (st + 1 + kDmaDepth < n_st) issue(st + 1 + kDmaDepth);
+                    const char *NA, *NBp;
+                    panels(st + 1, NA, NBp);
+                    load_ops(NA, NBp, 0, oa[0], ob[0]);
+                }
+            });
+        };
+        if (n_st > 0) {
+            // scalar loads still in flight would turn every LDS wait in the
+            // loop into lgkmcnt(0): settle them here
+            __builtin_amdgcn_s_waitcnt(0xC07F);
+#pragma unroll
+            for (int d = 0; d < kDmaDepth; ++d)
+                if (d < n_st) issue(d);
+            wait_landed(0);
+            dma_barrier();
+            if (kDmaDepth < n_st) issue(kDmaDepth);
+            const char *PA, *PB;
+            panels(0, PA, PB);
+            load_ops(PA, PB, 0, oa[0], ob[0]);
+            for (int st = 0; st + 1 < n_st; ++st) run_stage(st, std::true_type{});
+            run_stage(n_st - 1, std::false_type{});
         }
         lds_barrier();
     } else {
@@ -523,13 +632,11 @@ __global__ __launch_bounds__(kThreads, 2) void xengine_kernel(XArgs a) {
     __shared__ __attribute__((aligned(16))) char lds[lds_bytes<DT, TILE>()];
     // XCD-aware order: consecutive workgroup ids go round-robin over the 8
     // XCDs; give each XCD a contiguous range of work so that the tiles of one
-    // channel share that XCD's L2.
+    // channel share that XCD's L2.  (One tile per workgroup: the hardware
+    // dispatcher then keeps the tiles in flight on an XCD a contiguous
+    // window, which a static persistent schedule does not.)
     const int bid = blockIdx.x;
-#ifdef AFC_NO_XCD_ORDER
-    const int w = bid;
-#else
     const int w = (bid & 7) * a.per_xcd + (bid >> 3);
-#endif
     if (w >= a.total) return;
     const int t = w % a.n_tiles;
     const int rest = w / a.n_tiles;
@@ -585,6 +692,19 @@ __global__ __launch_bounds__(kThreads, WPC) void xengine_persistent_kernel(
 }
 
 }  // namespace
+
+int device_cu_count() {
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (dev < 0 || dev >= 64) dev = 0;
+    if (cache[dev] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v < 1) v = 256;
+        cache[dev] = v;
+    }
+    return cache[dev];
+}
 
 int xengine_tile(afc_dtype dt) { return dt == AFC_F32 ? 64 : 128; }
 
