@@ -183,9 +183,319 @@ __device__ __forceinline__ void tile_rc(int t, int& ti, int& tj) {
     tj = t - r * (r + 1) / 2;
 }
 
-// One tile of one (subband, channel).  `z` points at channel ch of subband sb.
+// Work of one wave in an int8 / fp16 tile: NP blocks of 32 x 32 outputs,
+// block p pairing row block am[IA[p]] of panel A with column block
+// bn[IB[p]] of panel B (am, bn hold NA and NB block indices).
+struct JobRows4 {      // off-diagonal 128-tile: every row block x this wave's column block
+    static constexpr int NA = 4, NB = 1, NP = 4;
+    static constexpr int IA[4] = {0, 1, 2, 3}, IB[4] = {0, 0, 0, 0};
+};
+// diagonal 128-tile: its ten lower-triangle blocks (m >= n) split 3/3/2/2
+struct JobDiag0 {      // (0,0) (1,0) (2,0)
+    static constexpr int NA = 3, NB = 1, NP = 3;
+    static constexpr int IA[4] = {0, 1, 2, 0}, IB[4] = {0, 0, 0, 0};
+    static constexpr int AM[4] = {0, 1, 2, 0}, BN[2] = {0, 0};
+};
+struct JobDiag1 {      // (3,0) (1,1) (2,1)
+    static constexpr int NA = 3, NB = 2, NP = 3;
+    static constexpr int IA[4] = {0, 1, 2, 0}, IB[4] = {0, 1, 1, 0};
+    static constexpr int AM[4] = {3, 1, 2, 0}, BN[2] = {0, 1};
+};
+struct JobDiag2 {      // (3,1) (2,2)
+    static constexpr int NA = 2, NB = 2, NP = 2;
+    static constexpr int IA[4] = {0, 1, 0, 0}, IB[4] = {0, 1, 0, 0};
+    static constexpr int AM[4] = {3, 2, 0, 0}, BN[2] = {1, 2};
+};
+struct JobDiag3 {      // (3,2) (3,3)
+    static constexpr int NA = 1, NB = 2, NP = 2;
+    static constexpr int IA[4] = {0, 0, 0, 0}, IB[4] = {0, 1, 0, 0};
+    static constexpr int AM[4] = {3, 0, 0, 0}, BN[2] = {2, 3};
+};
+struct JobOne {        // 64-tile: one block per wave
+    static constexpr int NA = 1, NB = 1, NP = 1;
+    static constexpr int IA[4] = {0, 0, 0, 0}, IB[4] = {0, 0, 0, 0};
+};
+struct JobIdle {       // 64-tile, the wave above the diagonal
+    static constexpr int NA = 1, NB = 1, NP = 0;
+    static constexpr int IA[4] = {0, 0, 0, 0}, IB[4] = {0, 0, 0, 0};
+};
+
+// One int8 / fp16 tile of one (subband, channel) for one wave's job.  All
+// waves of the workgroup stage the panels together; `z` points at channel ch
+// of subband sb.
+template <int DT, int TILE, class J>
+__device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __restrict__ vis_ch,
+                                         int32_t* __restrict__ w_sb, const uint8_t* __restrict__ fl_sb,
+                                         int N, int Na, int S, int ti, int tj, bool write_weights,
+                                         char* lds_raw, const int (&am)[4], const int (&bn)[2]) {
+    using Tr = XT<DT>;
+    using acc_t = typename Tr::acc_t;
+    using V = std::conditional_t<DT == AFC_I8, v4i, v8h>;
+    constexpr int RB = Tr::RB, PLANES = Tr::PLANES, kStg = stage_blocks<DT, TILE>();
+    constexpr int PANEL = kStg * TILE * RB;                  // bytes of one panel in one stage
+    constexpr int CHUNKS = kStg * TILE * PLANES;             // 16-byte chunks per panel per stage
+    constexpr int CPT = CHUNKS / kThreads;
+    static_assert(CHUNKS % kThreads == 0, "a stage must split evenly over the threads");
+    // k-steps per stage (int8: 16 spectra, fp16: 8 spectra each)
+    constexpr int NKK = DT == AFC_I8 ? kStg / 2 : kStg;
+    static_assert(NKK % 2 == 0, "k-steps per stage must be even");
+    constexpr int NA = J::NA, NBO = J::NB, NP = J::NP;
+    constexpr int NB = kDmaBuffers;
+
+    const int tid = threadIdx.x, lane = tid & 63, lr = lane & 31, lh = lane >> 5;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int i0 = ti * TILE, j0 = tj * TILE;
+    const bool diag = ti == tj;
+    const int nb = (S + kSBlk - 1) / kSBlk;
+    const int tail_valid = S - (nb - 1) * kSBlk;             // spectra in the last block
+    const int n_st = (nb + kStg - 1) / kStg;
+
+    acc_t accR[NP > 0 ? NP : 1], accI[NP > 0 ? NP : 1];
+#pragma unroll
+    for (int p = 0; p < (NP > 0 ? NP : 1); ++p) {
+        accR[p] = acc_t{};
+        accI[p] = acc_t{};
+    }
+
+    auto rd = [&](const char* panel, int bl, int row, int q) -> uint4 {
+        return *reinterpret_cast<const uint4*>(panel + bl * TILE * RB + row * RB + ((q ^ swz<RB, PLANES>(row)) * 16));
+    };
+    // this wave's operands of k-step kk (unconditional, so that the LDS
+    // wait counts stay exact across branches)
+    auto load_ops = [&](const char* PA, const char* PB, int kk, uint4 (&oa)[NA], uint4 (&ob)[NBO]) {
+        const int bl = DT == AFC_I8 ? 2 * kk + lh : kk;
+        const int q = DT == AFC_I8 ? 0 : lh;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) oa[i] = rd(PA, bl, am[i] * 32 + lr, q);
+#pragma unroll
+        for (int i = 0; i < NBO; ++i) ob[i] = rd(PB, bl, bn[i] * 32 + lr, q);
+    };
+    auto cvt = [](uint4 u) -> V {
+        if constexpr (DT == AFC_I8) return v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
+        else return __builtin_bit_cast(v8h, u);
+    };
+    auto jsw = [](uint4 u) -> V {
+        if constexpr (DT == AFC_I8)
+            return v4i{jswap_i8((int)u.x), jswap_i8((int)u.y), jswap_i8((int)u.z), jswap_i8((int)u.w)};
+        else
+            return __builtin_bit_cast(v8h, make_uint4((unsigned)jswap_f16((int)u.x), (unsigned)jswap_f16((int)u.y),
+                                                      (unsigned)jswap_f16((int)u.z), (unsigned)jswap_f16((int)u.w)));
+    };
+    auto op = [&](acc_t& acc, V x, V y) {
+        if constexpr (DT == AFC_I8) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(x, y, acc, 0, 0, 0);
+        else acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(x, y, acc, 0, 0, 0);
+    };
+    // MFMAs of one k-step.  `mid` runs after the first block's two MFMAs
+    // have been issued (the scheduler may not move work across it): loads
+    // of the next operands issued there overlap the remaining MFMAs.
+    auto mma = [&](const uint4 (&oa)[NA], const uint4 (&ob)[NBO], auto&& mid) {
+        V bv[NBO], bj[NBO];
+#pragma unroll
+        for (int i = 0; i < NBO; ++i) {
+            bv[i] = cvt(ob[i]);
+            bj[i] = jsw(ob[i]);
+        }
+        if constexpr (NP > 0) {
+            const V a0 = cvt(oa[J::IA[0]]);
+            op(accR[0], a0, bv[J::IB[0]]);
+            op(accI[0], a0, bj[J::IB[0]]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        mid();
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int p = 1; p < NP; ++p) {
+            const V a = cvt(oa[J::IA[p]]);
+            op(accR[p], a, bv[J::IB[p]]);
+            op(accI[p], a, bj[J::IB[p]]);
+        }
+        // keep the next k-step's J-swaps (which wait for its operand loads)
+        // behind these MFMAs
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    // zero the spectra >= S of this lane's operands of k-step kk of stage st
+    auto mask_tail_ops = [&](int st, int kk, uint4 (&a)[NA], uint4 (&b)[NBO]) {
+        const int blk = st * kStg + (DT == AFC_I8 ? 2 * kk + lh : kk);
+        const int q = DT == AFC_I8 ? 0 : lh;
+        if (blk < nb - 1 || (blk == nb - 1 && tail_valid == kSBlk)) return;
+        const int valid = blk == nb - 1 ? tail_valid : 0;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) a[i] = mask_tail<DT>(a[i], q, valid);
+#pragma unroll
+        for (int i = 0; i < NBO; ++i) b[i] = mask_tail<DT>(b[i], q, valid);
+    };
+
+    // Samples go straight from global memory to LDS (buffer loads with the
+    // LDS bit: lane L of a wave writes 16 bytes at M0 + 16 L) through a ring
+    // of NB stage buffers.  Buffer rather than global loads: the compiler
+    // must assume that global (flat) ones may also touch LDS and would then
+    // wait for every LDS read at once.  Rows beyond N read row N-1 (they only
+    // feed outputs that are never stored); in the last stage, blocks beyond
+    // the data read the last block again, and the operands of the partial
+    // last block are masked in registers.
+    //
+    // One barrier per stage st, placed before its last k-step: by then stage
+    // st+1 has landed (each wave waits for its own loads first) and every
+    // wave has finished stage st-1, so the loads of stage st+1+kDmaDepth
+    // refill st-1's buffer, and the first operands of st+1 are read while the
+    // last MFMAs of st run.  Operands are double-buffered one k-step ahead.
+    //
+    // Offsets within the channel: voffset = this thread's chunk in stage 0,
+    // soffset = the stage (a channel of samples is far below 2 GiB: the entry
+    // points bound one subband of input to 2^31 values).
+    const int z_bytes = nb * N * RB;
+    int src_off[2][CPT];
+#pragma unroll
+    for (int pn = 0; pn < 2; ++pn)
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int chunk = tid + c * kThreads;
+            const int bl = chunk / (TILE * PLANES);
+            const int rem = chunk % (TILE * PLANES);
+            const int row = rem / PLANES, sl = rem % PLANES;
+            const int q = sl ^ swz<RB, PLANES>(row);
+            const int r0 = pn == 0 ? i0 : j0;
+            src_off[pn][c] = (bl * N + min(r0 + row, N - 1)) * RB + q * 16;
+        }
+    const int stage_bytes = kStg * N * RB;
+    auto issue = [&](int st) {
+        const int bq = st % NB;
+        const bool past_end = (st + 1) * kStg > nb;          // uniform
+#pragma unroll
+        for (int pn = 0; pn < 2; ++pn) {
+            if (pn == 1 && diag) break;
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                char* dst = lds_raw + (bq * 2 + pn) * PANEL + (c * kThreads + wid * 64) * 16;
+                int voff = src_off[pn][c], soff = st * stage_bytes;
+                if (past_end) {   // whole offset in voffset, block clamped to nb - 1
+                    const int bl = (tid + c * kThreads) / (TILE * PLANES);
+                    voff += (min(st * kStg + bl, nb - 1) - bl) * N * RB;
+                    soff = 0;
+                }
+                buffer_load_lds16(z, z_bytes, dst, voff, soff);
+            }
+        }
+    };
+    // wait until this wave's loads of stage s have landed, given that the
+    // stages up to min(s + kDmaDepth - 1, n_st - 1) have been issued
+    auto wait_landed = [&](int s) {
+        const int later = min(n_st - 1 - s, kDmaDepth - 1);
+        if (diag) wait_vmcnt_runtime<CPT>(later);
+        else wait_vmcnt_runtime<2 * CPT>(later);
+    };
+    auto panels = [&](int st, const char*& PA, const char*& PB) {
+        const int bq = st % NB;
+        PA = lds_raw + (bq * 2) * PANEL;
+        PB = lds_raw + (bq * 2 + (diag ? 0 : 1)) * PANEL;
+    };
+    // operand set kk & 1 holds k-step kk of the current stage; the last
+    // stage is peeled off so that the loop body has no branch around LDS
+    // reads and the compiler's LDS wait counts stay exact
+    uint4 oa[2][NA], ob[2][NBO];
+    auto run_stage = [&](int st, auto has_next_tag) {
+        constexpr bool kNext = decltype(has_next_tag)::value;
+        const char *PA, *PB;
+        panels(st, PA, PB);
+#pragma unroll
+        for (int kk = 0; kk + 1 < NKK; ++kk) {
+            if constexpr (!kNext) mask_tail_ops(st, kk, oa[kk & 1], ob[kk & 1]);
+            mma(oa[kk & 1], ob[kk & 1], [&] { load_ops(PA, PB, kk + 1, oa[(kk + 1) & 1], ob[(kk + 1) & 1]); });
+        }
+        if constexpr (!kNext) mask_tail_ops(st, NKK - 1, oa[(NKK - 1) & 1], ob[(NKK - 1) & 1]);
+        mma(oa[(NKK - 1) & 1], ob[(NKK - 1) & 1], [&] {
+            if constexpr (kNext) {
+                wait_landed(st + 1);
+                dma_barrier();
+                if (st + 1 + kDmaDepth < n_st) issue(st + 1 + kDmaDepth);
+                const char *NA_, *NB_;
+                panels(st + 1, NA_, NB_);
+                load_ops(NA_, NB_, 0, oa[0], ob[0]);
+            }
+        });
+    };
+    // scalar loads still in flight would turn every LDS wait in the loop
+    // into lgkmcnt(0): settle them here
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+#pragma unroll
+    for (int d = 0; d < kDmaDepth; ++d)
+        if (d < n_st) issue(d);
+    wait_landed(0);
+    dma_barrier();
+    if (kDmaDepth < n_st) issue(kDmaDepth);
+    {
+        const char *PA, *PB;
+        panels(0, PA, PB);
+        load_ops(PA, PB, 0, oa[0], ob[0]);
+    }
+    for (int st = 0; st + 1 < n_st; ++st) run_stage(st, std::true_type{});
+    run_stage(n_st - 1, std::false_type{});
+    lds_barrier();
+
+    // ---- epilogue: 2x2 polarisation blocks of antennas a >= b
+    if constexpr (NP > 0) {
+        // flags of this lane's row antennas (8 per row block) and column
+        // antennas, fetched together before the stores
+        bool frow[NA][8], fcol[NBO];
+#pragma unroll
+        for (int i = 0; i < NBO; ++i) fcol[i] = false;
+#pragma unroll
+        for (int i = 0; i < NA; ++i)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) frow[i][k] = false;
+        if (fl_sb) {
+            uint8_t fc[NBO], fr[NA][8];
+#pragma unroll
+            for (int i = 0; i < NBO; ++i) fc[i] = fl_sb[min(j0 + bn[i] * 32 + lr, N - 1) >> 1];
+#pragma unroll
+            for (int i = 0; i < NA; ++i)
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    fr[i][k] = fl_sb[min(i0 + am[i] * 32 + 8 * (k >> 1) + 4 * lh + 2 * (k & 1), N - 1) >> 1];
+#pragma unroll
+            for (int i = 0; i < NBO; ++i) fcol[i] = fc[i] != 0;
+#pragma unroll
+            for (int i = 0; i < NA; ++i)
+#pragma unroll
+                for (int k = 0; k < 8; ++k) frow[i][k] = fr[i][k] != 0;
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int Jc = j0 + bn[J::IB[p]] * 32 + lr;
+            if (Jc >= N) continue;
+            const int b = Jc >> 1, qq = Jc & 1;
+            const bool fb = fcol[J::IB[p]];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int I = i0 + am[J::IA[p]] * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
+                if (I >= N) continue;
+                const int a = I >> 1, pp = I & 1;
+                if (a < b) continue;
+                const bool flagged = fb || frow[J::IA[p]][((r >> 2) << 1) | ((r >> 1) & 1)];
+                const int64_t bl = (int64_t)a * (a + 1) / 2 + b;
+                const int64_t e = bl * 4 + pp * 2 + qq;
+                if constexpr (DT == AFC_I8) {
+                    int re = accR[p][r], im = accI[p][r];
+                    if (I == Jc) im = 0;
+                    if (flagged) re = im = 0;
+                    reinterpret_cast<int2*>(vis_ch)[e] = make_int2(re, im);
+                } else {
+                    float re = accR[p][r], im = accI[p][r];
+                    if (I == Jc) im = 0.0f;
+                    if (flagged) re = im = 0.0f;
+                    reinterpret_cast<float2*>(vis_ch)[e] = make_float2(re, im);
+                }
+                if (write_weights && pp == 0 && qq == 0) w_sb[bl] = flagged ? 0 : S;
+            }
+        }
+    }
+}
+
+// One fp32 tile of one (subband, channel): 2 x 2 waves of one 32 x 32 block
+// each, samples staged through registers.  `z` points at channel ch of
+// subband sb.
 template <int DT, int TILE>
-__device__ __forceinline__ void xtile(const char* __restrict__ z, char* __restrict__ vis_ch,
+__device__ __forceinline__ void xtile_f32(const char* __restrict__ z, char* __restrict__ vis_ch,
                                       int32_t* __restrict__ w_sb, const uint8_t* __restrict__ fl_sb,
                                       int N, int Na, int S, int ti, int tj, bool write_weights,
                                       char* lds_raw) {
@@ -196,7 +506,7 @@ __device__ __forceinline__ void xtile(const char* __restrict__ z, char* __restri
     constexpr int CHUNKS = kStg * TILE * PLANES;             // 16-byte chunks per panel per stage
     constexpr int CPT = CHUNKS / kThreads;
     static_assert(CHUNKS % kThreads == 0, "a stage must split evenly over the threads");
-    constexpr bool kDma = uses_dma<DT>();
+    static_assert(DT == AFC_F32, "fp32 only");
     using acc_t = typename Tr::acc_t;
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -281,79 +591,10 @@ __device__ __forceinline__ void xtile(const char* __restrict__ z, char* __restri
     const int lr = lane & 31, lh = lane >> 5;
     int fold = 0;
 
-    // Operands of one k-step (int8: 16 spectra, fp16: 8 spectra) of this
-    // wave: row blocks m of panel PA and column blocks n of panel PB.
-    constexpr int NKK = DT == AFC_I8 ? kStg / 2 : kStg;
-    // (unconditional, also in waves that skip their MFMAs, so that the LDS
-    // wait counts stay exact across the branches)
-    auto load_ops = [&](const char* PA, const char* PB, int kk, uint4 (&oa)[MB], uint4 (&ob)[MB]) {
-        const int bl = DT == AFC_I8 ? 2 * kk + lh : kk;
-        const int q = DT == AFC_I8 ? 0 : lh;
-#pragma unroll
-        for (int m = 0; m < MB; ++m) {
-            oa[m] = rd(PA, bl, wr * WT + m * 32 + lr, q);
-            ob[m] = rd(PB, bl, wc * WT + m * 32 + lr, q);
-        }
-    };
-    // MFMAs of one k-step.  `mid` runs after the first block's two MFMAs
-    // have been issued (the scheduler may not move work across it): loads
-    // of the next operands issued there overlap the remaining MFMAs.
-    auto mma = [&](const uint4 (&oa)[MB], const uint4 (&ob)[MB], auto&& mid) {
-        using V = std::conditional_t<DT == AFC_I8, v4i, v8h>;
-        auto cvt = [](uint4 u) -> V {
-            if constexpr (DT == AFC_I8) return v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
-            else return __builtin_bit_cast(v8h, u);
-        };
-        auto jsw = [](uint4 u) -> V {
-            if constexpr (DT == AFC_I8)
-                return v4i{jswap_i8((int)u.x), jswap_i8((int)u.y), jswap_i8((int)u.z), jswap_i8((int)u.w)};
-            else
-                return __builtin_bit_cast(v8h, make_uint4((unsigned)jswap_f16((int)u.x), (unsigned)jswap_f16((int)u.y),
-                                                          (unsigned)jswap_f16((int)u.z), (unsigned)jswap_f16((int)u.w)));
-        };
-        auto op = [&](auto& acc, V x, V y) {
-            if constexpr (DT == AFC_I8) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(x, y, acc, 0, 0, 0);
-            else acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(x, y, acc, 0, 0, 0);
-        };
-        if (wave_on) {
-            const V a0 = cvt(oa[0]);
-            op(accR[0][0], a0, cvt(ob[0]));
-            op(accI[0][0], a0, jsw(ob[0]));
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        mid();
-        __builtin_amdgcn_sched_barrier(0);
-        if (wave_on) {
-            V a[MB], b[MB], bj[MB];
-#pragma unroll
-            for (int m = 0; m < MB; ++m) {
-                a[m] = cvt(oa[m]);
-                b[m] = cvt(ob[m]);
-                bj[m] = jsw(ob[m]);
-            }
-#pragma unroll
-            for (int m = 0; m < MB; ++m)
-#pragma unroll
-                for (int n = 0; n < MB; ++n) {
-                    if ((m == 0 && n == 0) || (diag && wr == wc && m < n)) continue;
-                    op(accR[m][n], a[m], b[n]);
-                    op(accI[m][n], a[m], bj[n]);
-                }
-        }
-    };
-    auto nothing = [] {};
-
     // MFMAs of one stage from the panels PA (rows) and PB (columns)
     auto compute = [&](const char* PA, const char* PB) {
         if (wave_on) {
-            if constexpr (DT != AFC_F32) {
-#pragma unroll
-                for (int kk = 0; kk < NKK; ++kk) {
-                    uint4 oa[MB], ob[MB];
-                    load_ops(PA, PB, kk, oa, ob);
-                    mma(oa, ob, nothing);
-                }
-            } else {
+            {
 #pragma unroll
                 for (int kk = 0; kk < kStg; ++kk) {
 #pragma unroll
@@ -399,131 +640,7 @@ __device__ __forceinline__ void xtile(const char* __restrict__ z, char* __restri
         }
     };
 
-    if constexpr (kDma) {
-        // Stages made of whole blocks go straight from global memory to LDS
-        // (global_load_lds: lane L of a wave writes 16 bytes at M0 + 16 L)
-        // through a ring of kDmaBuffers buffers.  Rows beyond N read row N-1:
-        // they only feed outputs that are never stored.  In the last stage,
-        // blocks beyond the subband's data read the last block again and
-        // every operand of a block at or beyond the partial last block is
-        // masked in registers (spectra >= S become zero).
-        //
-        // Per stage st, one barrier, placed before its last k-step: by then
-        // stage st+1 has landed (each wave waits for its own loads first),
-        // every wave has finished stage st-1, so the loads of stage
-        // st+1+kDmaDepth can refill st-1's buffer, and the first operands of
-        // st+1 are read from LDS while the last MFMAs of st run.  Operands are
-        // double-buffered in registers one k-step ahead.
-        constexpr int NB = kDmaBuffers;
-        const int n_st = n_stages;
-        // Buffer loads (not global/flat ones, which the compiler must assume
-        // may also touch LDS, and would then wait for every LDS read at once).
-        // Byte offsets within the channel: voffset = this thread's chunk in
-        // stage 0, soffset = the stage (a channel of samples is far below
-        // 2 GiB: the entry points bound one subband of input to 2^31 values).
-        const int z_bytes = nb * N * RB;
-        int src_off[2][CPT];
-#pragma unroll
-        for (int pn = 0; pn < 2; ++pn)
-#pragma unroll
-            for (int c = 0; c < CPT; ++c) {
-                const int chunk = tid + c * kThreads;
-                const int bl = chunk / (TILE * PLANES);
-                const int rem = chunk % (TILE * PLANES);
-                const int row = rem / PLANES, sl = rem % PLANES;
-                const int q = sl ^ swz<RB, PLANES>(row);
-                const int r0 = pn == 0 ? i0 : j0;
-                src_off[pn][c] = (bl * N + min(r0 + row, N - 1)) * RB + q * 16;
-            }
-        const int stage_bytes = kStg * N * RB;
-        auto issue = [&](int st) {
-            const int bq = st % NB;
-            const bool past_end = (st + 1) * kStg > nb;     // uniform
-#pragma unroll
-            for (int pn = 0; pn < 2; ++pn) {
-                if (pn == 1 && diag) break;
-#pragma unroll
-                for (int c = 0; c < CPT; ++c) {
-                    char* dst = lds_raw + (bq * 2 + pn) * PANEL + (c * kThreads + wid * 64) * 16;
-                    int voff = src_off[pn][c], soff = st * stage_bytes;
-                    if (past_end) {   // whole offset in voffset, block clamped to nb - 1
-                        const int bl = (tid + c * kThreads) / (TILE * PLANES);
-                        voff += (min(st * kStg + bl, nb - 1) - bl) * N * RB;
-                        soff = 0;
-                    }
-                    buffer_load_lds16(z, z_bytes, dst, voff, soff);
-                }
-            }
-        };
-        // wait until this wave's loads of stage s have landed, given that
-        // the stages up to min(s + kDmaDepth - 1, n_st - 1) have been issued
-        auto wait_landed = [&](int s) {
-            const int later = min(n_st - 1 - s, kDmaDepth - 1);
-            if (diag) wait_vmcnt_runtime<CPT>(later);
-            else wait_vmcnt_runtime<2 * CPT>(later);
-        };
-        auto panels = [&](int st, const char*& PA, const char*& PB) {
-            const int bq = st % NB;
-            PA = lds_raw + (bq * 2) * PANEL;
-            PB = lds_raw + (bq * 2 + (diag ? 0 : 1)) * PANEL;
-        };
-        // Operand registers: set kk & 1 holds k-step kk of the current stage
-        // (NKK is even, so every stage starts in set 0).  The last stage is
-        // peeled off so that the loop body has no branch around LDS reads
-        // and the compiler's LDS wait counts stay exact.
-        static_assert(NKK % 2 == 0, "k-steps per stage must be even");
-        // zero the spectra >= S of this lane's operands of k-step kk of stage st
-        auto mask_tail_ops = [&](int st, int kk, uint4 (&a)[MB], uint4 (&b)[MB]) {
-            const int blk = st * kStg + (DT == AFC_I8 ? 2 * kk + lh : kk);
-            const int q = DT == AFC_I8 ? 0 : lh;
-            if (blk < nb - 1 || (blk == nb - 1 && tail_valid == kSBlk)) return;
-            const int valid = blk == nb - 1 ? tail_valid : 0;
-#pragma unroll
-            for (int m = 0; m < MB; ++m) {
-                a[m] = mask_tail<DT>(a[m], q, valid);
-                b[m] = mask_tail<DT>(b[m], q, valid);
-            }
-        };
-        uint4 oa[2][MB], ob[2][MB];
-        auto run_stage = [&](int st, auto has_next_tag) {
-            constexpr bool kNext = decltype(has_next_tag)::value;
-            const char *PA, *PB;
-            panels(st, PA, PB);
-#pragma unroll
-            for (int kk = 0; kk + 1 < NKK; ++kk) {
-                if constexpr (!kNext) mask_tail_ops(st, kk, oa[kk & 1], ob[kk & 1]);
-                mma(oa[kk & 1], ob[kk & 1], [&] { load_ops(PA, PB, kk + 1, oa[(kk + 1) & 1], ob[(kk + 1) & 1]); });
-            }
-            if constexpr (!kNext) mask_tail_ops(st, NKK - 1, oa[(NKK - 1) & 1], ob[(NKK - 1) & 1]);
-            mma(oa[(NKK - 1) & 1], ob[(NKK - 1) & 1], [&] {
-                if constexpr (kNext) {
-                    wait_landed(st + 1);
-                    dma_barrier();
-                    if (st + 1 + kDmaDepth < n_st) issue(st + 1 + kDmaDepth);
-                    const char *NA, *NBp;
-                    panels(st + 1, NA, NBp);
-                    load_ops(NA, NBp, 0, oa[0], ob[0]);
-                }
-            });
-        };
-        if (n_st > 0) {
-            // scalar loads still in flight would turn every LDS wait in the
-            // loop into lgkmcnt(0): settle them here
-            __builtin_amdgcn_s_waitcnt(0xC07F);
-#pragma unroll
-            for (int d = 0; d < kDmaDepth; ++d)
-                if (d < n_st) issue(d);
-            wait_landed(0);
-            dma_barrier();
-            if (kDmaDepth < n_st) issue(kDmaDepth);
-            const char *PA, *PB;
-            panels(0, PA, PB);
-            load_ops(PA, PB, 0, oa[0], ob[0]);
-            for (int st = 0; st + 1 < n_st; ++st) run_stage(st, std::true_type{});
-            run_stage(n_st - 1, std::false_type{});
-        }
-        lds_barrier();
-    } else {
+    {
         // Register staging with one barrier per stage: at stage st the
         // registers hold the samples of the next DEPTH stages; stage st+1 goes
         // to the other LDS buffer first, its register slot is refilled with
@@ -554,20 +671,16 @@ __device__ __forceinline__ void xtile(const char* __restrict__ z, char* __restri
             if (st + 1 < n_stages) step(st + 1, S0{});
         }
     }
-    if constexpr (DT == AFC_F32) {
 #pragma unroll
-        for (int m = 0; m < MB; ++m)
+    for (int m = 0; m < MB; ++m)
 #pragma unroll
-            for (int n = 0; n < MB; ++n) {
-                accR[m][n] += outR[m][n];
-                accI[m][n] += outI[m][n];
-            }
-    }
+        for (int n = 0; n < MB; ++n) {
+            accR[m][n] += outR[m][n];
+            accI[m][n] += outI[m][n];
+        }
     if (!wave_on) return;
 
     // ---- epilogue: 2x2 polarisation blocks of antennas a >= b
-    const int64_t nbl = (int64_t)Na * (Na + 1) / 2;
-    (void)nbl;
     // flags of this lane's row antennas (8 per 32-row block) and column
     // antennas, fetched together before the stores
     bool frow[MB][8], fcol[MB];
@@ -611,20 +724,51 @@ __device__ __forceinline__ void xtile(const char* __restrict__ z, char* __restri
                 const bool flagged = fb || frow[m][((r >> 2) << 1) | ((r >> 1) & 1)];
                 const int64_t bl = (int64_t)a * (a + 1) / 2 + b;
                 const int64_t e = bl * 4 + p * 2 + qq;
-                if constexpr (DT == AFC_I8) {
-                    int re = accR[m][n][r], im = accI[m][n][r];
-                    if (I == J) im = 0;
-                    if (flagged) re = im = 0;
-                    reinterpret_cast<int2*>(vis_ch)[e] = make_int2(re, im);
-                } else {
-                    float re = accR[m][n][r], im = accI[m][n][r];
-                    if (I == J) im = 0.0f;
-                    if (flagged) re = im = 0.0f;
-                    reinterpret_cast<float2*>(vis_ch)[e] = make_float2(re, im);
-                }
+                float re = accR[m][n][r], im = accI[m][n][r];
+                if (I == J) im = 0.0f;
+                if (flagged) re = im = 0.0f;
+                reinterpret_cast<float2*>(vis_ch)[e] = make_float2(re, im);
                 if (write_weights && p == 0 && qq == 0) w_sb[bl] = flagged ? 0 : S;
             }
         }
+}
+
+// One tile of one (subband, channel).  int8 / fp16: each wave computes its
+// job of 32 x 32 blocks (diagonal tiles spread their lower-triangle blocks
+// over the waves); fp32: 2 x 2 waves of one block each.
+template <int DT, int TILE>
+__device__ __forceinline__ void xtile(const char* __restrict__ z, char* __restrict__ vis_ch,
+                                      int32_t* __restrict__ w_sb, const uint8_t* __restrict__ fl_sb,
+                                      int N, int Na, int S, int ti, int tj, bool write_weights, char* lds_raw) {
+    if constexpr (DT == AFC_F32) {
+        xtile_f32<DT, TILE>(z, vis_ch, w_sb, fl_sb, N, Na, S, ti, tj, write_weights, lds_raw);
+    } else {
+        const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        auto run = [&](auto job, const int (&am)[4], const int (&bn)[2]) {
+            xtile_mm<DT, TILE, decltype(job)>(z, vis_ch, w_sb, fl_sb, N, Na, S, ti, tj, write_weights, lds_raw,
+                                              am, bn);
+        };
+        if constexpr (TILE == 128) {
+            if (ti != tj) {
+                const int am[4] = {0, 1, 2, 3}, bn[2] = {wid, 0};
+                run(JobRows4{}, am, bn);
+            } else if (wid == 0) {
+                run(JobDiag0{}, JobDiag0::AM, JobDiag0::BN);
+            } else if (wid == 1) {
+                run(JobDiag1{}, JobDiag1::AM, JobDiag1::BN);
+            } else if (wid == 2) {
+                run(JobDiag2{}, JobDiag2::AM, JobDiag2::BN);
+            } else {
+                run(JobDiag3{}, JobDiag3::AM, JobDiag3::BN);
+            }
+        } else {
+            static_assert(TILE == 64, "int8 / fp16 tiles are 128 or 64 wide");
+            const int wr = wid >> 1, wc = wid & 1;
+            const int am[4] = {wr, 0, 0, 0}, bn[2] = {wc, 0};
+            if (ti == tj && wr < wc) run(JobIdle{}, am, bn);
+            else run(JobOne{}, am, bn);
+        }
+    }
 }
 
 template <int DT, int TILE>
