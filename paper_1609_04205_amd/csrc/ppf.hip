@@ -95,18 +95,31 @@ __device__ __forceinline__ unsigned requant_bits(float y, float gain) {
     return __float_as_uint(__fadd_rn(c, 12582912.0f));
 }
 
-// store at sample index base + off (base wave-uniform, off per lane)
+// store at sample index base + off (base wave-uniform, off per lane) with a
+// buffer store: the channel base is scalar and the per-lane byte offset a
+// 32-bit value, so the store needs no vector address arithmetic (a channel
+// of samples is far below 2 GiB: one subband of input is bounded to 2^31
+// values).
 template <int DT>
-__device__ __forceinline__ void store_sample(void* zs, int64_t base, int off, float2 y, float gain) {
+__device__ __forceinline__ void store_sample(void* zs, int64_t base, unsigned off, float2 y, float gain) {
+    constexpr unsigned kB = DT == AFC_F32 ? 8 : DT == AFC_F16 ? 4 : 2;
+#if defined(__HIP_DEVICE_COMPILE__)
+    // raw buffer store: scalar base (this channel), per-lane 32-bit offset
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+        reinterpret_cast<char*>(zs) + base * kB, (short)0, 0x7FFFFFFF, 0x00020000);
     if constexpr (DT == AFC_F32) {
-        (reinterpret_cast<float2*>(zs) + base)[off] = y;
+        typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, y), r, off * kB, 0, 0);
     } else if constexpr (DT == AFC_F16) {
-        (reinterpret_cast<__half2*>(zs) + base)[off] = __floats2half2_rn(y.x, y.y);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, __floats2half2_rn(y.x, y.y)), r,
+                                                  off * kB, 0, 0);
     } else {
         const unsigned qr = requant_bits(y.x, gain), qi = requant_bits(y.y, gain);
         // bytes: low = real, high = imaginary
-        (reinterpret_cast<uint16_t*>(zs) + base)[off] = (uint16_t)__builtin_amdgcn_perm(qi, qr, 0x0c0c0400u);
+        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)__builtin_amdgcn_perm(qi, qr, 0x0c0c0400u), r,
+                                                  off * kB, 0, 0);
     }
+#endif
 }
 
 
@@ -232,16 +245,19 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
             const int blk = (sg >> 3) + bh;
             if (rf < N && blk < Sb) {
                 const bool live = s < S;
-                const int lane_zoff = (blk * N + rf) * kSBlk + sl;          // samples within a channel
+                const unsigned lane_zoff = (blk * N + rf) * kSBlk + sl;     // samples within a channel
                 const int64_t ch_stride = (int64_t)Sb * N * kSBlk;          // samples per channel
+                // spectra >= S are stored as zeros (int8: through a zero gain)
+                const float g = live ? gain : 0.0f;
 #pragma unroll
                 for (int ga = 0; ga < 4; ++ga)
 #pragma unroll
                     for (int de = 0; de < 4; ++de) {
                         const int k = k1 + 4 * (ga + 4 * de);
                         float2 y = a[4 * ga + de];
-                        if (!live) y = make_float2(0.0f, 0.0f);
-                        store_sample<DT>(zs, (int64_t)k * ch_stride, lane_zoff, y, gain);
+                        if constexpr (DT != AFC_I8)
+                            if (!live) y = make_float2(0.0f, 0.0f);
+                        store_sample<DT>(zs, (int64_t)k * ch_stride, lane_zoff, y, g);
                     }
             }
         }
