@@ -12,8 +12,9 @@
  *                       gradient with respect to the complex gains
  *   afc_plan_*          batching form: many subbands with their own
  *                       integration length, sample type and antenna flags in
- *                       one graph of one channeliser and one persistent
- *                       correlator launch, tile shape from a measured tuner
+ *                       one graph of one channeliser launch and one
+ *                       correlator launch per sample-type family, tile shape
+ *                       from a measured tuner
  *
  * Conventions (all entry points):
  *   - Pointers are DEVICE pointers unless the comment says "host".  The caller
@@ -172,8 +173,9 @@ AFC_API int afc_calibrate_grad(int32_t n_antennas, int32_t n_channels, const voi
 /* ---------------------------------------------------------------------------
  * Batching form (Sec. "GPU Processing": each subband is an independent unit
  * of work; the paper hands subbands to free GPUs one by one, here all of them
- * go into one channeliser launch and one persistent correlator launch,
- * replayed as a HIP graph).
+ * go into one channeliser launch and one correlator launch per family of
+ * sample types (int8 + fp16 together, fp32 apart) whose workgroups each take
+ * one tile of a host-built, XCD-balanced work list, replayed as a HIP graph).
  *
  * afc_plan_create    d: shape with n_spectra = max S_b; dtype_per_sb host
  *                    [B] (AFC_F16 or AFC_I8 each, or AFC_F32); n_spectra_per_sb
@@ -205,7 +207,8 @@ AFC_API int afc_plan_launch(afc_plan* p, const int16_t* x, const float* taps,
                             const float* gain_per_sb, void* z_workspace,
                             const uint8_t* flags, void* vis, int32_t* weights,
                             hipStream_t stream);
-/* Tile configuration the plan's correlator uses (host out-params). */
+/* Tile configuration the plan's correlator uses (host out-params):
+ * tile width, workgroups of its launch and work items in the list. */
 AFC_API int afc_plan_info(const afc_plan* p, int32_t* tile_rows, int32_t* tile_cols,
                           int32_t* n_workgroups, int32_t* n_work_items);
 AFC_API void afc_plan_destroy(afc_plan* p);

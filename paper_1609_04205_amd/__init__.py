@@ -232,7 +232,7 @@ class PlanInfo:
 
 
 class Plan:
-    """Batching form: one graph of one channeliser launch and one persistent correlator launch."""
+    """Batching form: one graph of one channeliser launch and one correlator launch per sample-type family."""
 
     def __init__(self, n_antennas: int, n_spectra_per_sb: Sequence[int], dtypes: Sequence[str],
                  tune_cache: Optional[str] = None, n_spectra: Optional[int] = None):

@@ -190,7 +190,7 @@ struct afc_plan {
         int n_wg = 0;
         int n_items = 0;
         XWork* d_work = nullptr;
-        int32_t* d_begin = nullptr;
+        XcdRanges ranges{};
     } mode[2];
     std::vector<PpfItem> items;
     // graph
@@ -203,8 +203,6 @@ struct afc_plan {
 
 namespace {
 
-int num_cus() { return device_cu_count(); }
-
 // Cost of one tile item in MFMA cycles per spectrum (per SIMD), from the
 // instruction rates: int8 32x32x32 and fp16 32x32x16 take the same cycles,
 // int8 covers twice the spectra; fp32 32x32x2 covers one spectrum per pair.
@@ -214,11 +212,10 @@ double tile_cost(int dt, int tile, int S, bool diag) {
     return blocks * per_spec * S + 2000.0;                                      // + fixed cost (epilogue)
 }
 
-// Build a balanced work list for one mode: groups (subband, channel) are
-// spread over the XCDs, then the tiles of each group over the workgroups of
-// its XCD, longest-processing-time first, in group order.
-void build_work(const afc_plan& p, int m, int tile, int n_wg, std::vector<XWork>& work_out,
-                std::vector<int32_t>& begin_out) {
+// Build the work list of one mode: the (subband, channel) groups are spread
+// over the 8 XCDs by cost (longest first onto the least loaded XCD), and each
+// XCD's items are stored contiguously, group after group, tiles in row order.
+void build_work(const afc_plan& p, int m, int tile, std::vector<XWork>& work_out, XcdRanges& ranges) {
     const int nT = (int)ceil_div(p.N, tile);
     struct G {
         int sb, ch;
@@ -244,57 +241,31 @@ void build_work(const afc_plan& p, int m, int tile, int n_wg, std::vector<XWork>
         xload[best] += groups[gi].cost;
         xgroups[best].push_back(gi);
     }
-    std::vector<std::vector<XWork>> per_wg(n_wg);
-    for (int x = 0; x < n_xcd; ++x) {
-        std::vector<int> wgs;
-        for (int w = x; w < n_wg; w += n_xcd) wgs.push_back(w);
-        if (wgs.empty()) continue;
-        using E = std::pair<double, int>;
-        std::priority_queue<E, std::vector<E>, std::greater<E>> heap;
-        for (int w : wgs) heap.push({0.0, w});
-        for (int gi : xgroups[x]) {
-            const G& g = groups[gi];
-            std::vector<std::pair<double, XWork>> tiles;
-            for (int ti = 0; ti < nT; ++ti)
-                for (int tj = 0; tj <= ti; ++tj)
-                    tiles.push_back({tile_cost(p.dt[g.sb], tile, p.S[g.sb], ti == tj), XWork{g.sb, g.ch, ti, tj}});
-            std::stable_sort(tiles.begin(), tiles.end(),
-                             [](const auto& a, const auto& b) { return a.first > b.first; });
-            for (auto& t : tiles) {
-                E e = heap.top();
-                heap.pop();
-                per_wg[e.second].push_back(t.second);
-                heap.push({e.first + t.first, e.second});
-            }
-        }
-    }
     work_out.clear();
-    begin_out.assign(n_wg + 1, 0);
-    for (int w = 0; w < n_wg; ++w) {
-        begin_out[w] = (int32_t)work_out.size();
-        work_out.insert(work_out.end(), per_wg[w].begin(), per_wg[w].end());
+    for (int x = 0; x < n_xcd; ++x) {
+        ranges.begin[x] = (int32_t)work_out.size();
+        for (int gi : xgroups[x])
+            for (int ti = 0; ti < nT; ++ti)
+                for (int tj = 0; tj <= ti; ++tj) work_out.push_back(XWork{groups[gi].sb, groups[gi].ch, ti, tj});
+        ranges.count[x] = (int32_t)work_out.size() - ranges.begin[x];
     }
-    begin_out[n_wg] = (int32_t)work_out.size();
 }
 
-int upload_mode(afc_plan* p, int m, int tile, int n_wg) {
+int upload_mode(afc_plan* p, int m, int tile) {
     afc_plan::Mode& md = p->mode[m];
     std::vector<XWork> work;
-    std::vector<int32_t> begin;
-    build_work(*p, m, tile, n_wg, work, begin);
+    XcdRanges ranges{};
+    build_work(*p, m, tile, work, ranges);
     if (md.d_work) hipFree(md.d_work);
-    if (md.d_begin) hipFree(md.d_begin);
     md.d_work = nullptr;
-    md.d_begin = nullptr;
     md.used = !work.empty();
     md.tile = tile;
-    md.n_wg = n_wg;
+    md.ranges = ranges;
+    md.n_wg = xengine_list_grid(ranges);
     md.n_items = (int)work.size();
     if (!md.used) return AFC_OK;
     hipError_t e = hipMalloc(&md.d_work, work.size() * sizeof(XWork));
-    if (e == hipSuccess) e = hipMalloc(&md.d_begin, begin.size() * sizeof(int32_t));
     if (e == hipSuccess) e = hipMemcpy(md.d_work, work.data(), work.size() * sizeof(XWork), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(md.d_begin, begin.data(), begin.size() * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "plan work upload");
     return AFC_OK;
 }
@@ -348,11 +319,11 @@ void write_cache(const char* path, const std::map<std::string, std::pair<int, in
     f << "}\n";
 }
 
-// Time the int8/fp16 persistent correlator of the plan's own work for each
-// candidate (tile, workgroups per CU) on scratch buffers; returns the best.
+// Time the int8/fp16 correlator of the plan's own work for each candidate
+// tile (128 wide at 2 workgroups per CU, 64 wide at 4) on scratch buffers
+// holding random samples; returns the best.
 int tune_mode0(afc_plan* p, int& tile_out, int& wg_per_cu_out) {
-    const int cus = num_cus();
-    const int cands[][2] = {{128, 2}, {128, 1}, {64, 2}, {64, 4}};
+    const int cands[][2] = {{128, 2}, {64, 4}};
     size_t vis_bytes = (size_t)p->d.n_subbands * kP * nbl_of(p->Na) * 32;
     void* z = nullptr;
     void* vis = nullptr;
@@ -362,7 +333,14 @@ int tune_mode0(afc_plan* p, int& tile_out, int& wg_per_cu_out) {
         if (z) hipFree(z);
         return hip_fail(e, "tuner scratch allocation");
     }
-    hipMemset(z, 0, p->ws_bytes);
+    // random samples: the MFMA rate (and clock) depends on the data, so zeros
+    // would time the candidates unrepresentatively
+    e = launch_fill_scratch(z, p->ws_bytes, nullptr);
+    if (e != hipSuccess) {
+        hipFree(z);
+        hipFree(vis);
+        return hip_fail(e, "tuner scratch fill");
+    }
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
     hipEventCreate(&e1);
@@ -370,14 +348,14 @@ int tune_mode0(afc_plan* p, int& tile_out, int& wg_per_cu_out) {
     tile_out = 128;
     wg_per_cu_out = 2;
     for (const auto& c : cands) {
-        int rc = upload_mode(p, 0, c[0], cus * c[1]);
+        int rc = upload_mode(p, 0, c[0]);
         if (rc != AFC_OK) break;
         const afc_plan::Mode& md = p->mode[0];
         float tmin = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
             hipEventRecord(e0, nullptr);
-            launch_xengine_persistent(z, vis, nullptr, nullptr, p->d_sbs, md.d_work, md.d_begin, md.n_wg, p->N, p->Na,
-                                      0, md.tile, nullptr);
+            launch_xengine_list(z, vis, nullptr, nullptr, p->d_sbs, md.d_work, md.ranges, p->N, p->Na, 0, md.tile,
+                                nullptr);
             hipEventRecord(e1, nullptr);
             hipEventSynchronize(e1);
             float ms = 0;
@@ -464,7 +442,6 @@ AFC_API int afc_plan_create(const afc_dims* d, const afc_dtype* dtype_per_sb, co
         afc_plan_destroy(p);
         return hip_fail(e, "plan allocation");
     }
-    const int cus = num_cus();
     // int8 / fp16 subbands: tile choice from the tune cache or the tuner
     bool any0 = false, any1 = false;
     for (int b = 0; b < B; ++b) {
@@ -491,14 +468,14 @@ AFC_API int afc_plan_create(const afc_dims* d, const afc_dtype* dtype_per_sb, co
                 write_cache(tune_cache_path, cache);
             }
         }
-        rc = upload_mode(p, 0, tile, cus * wpc);
+        rc = upload_mode(p, 0, tile);
         if (rc != AFC_OK) {
             afc_plan_destroy(p);
             return rc;
         }
     }
     if (any1) {
-        rc = upload_mode(p, 1, 64, cus * 2);
+        rc = upload_mode(p, 1, 64);
         if (rc != AFC_OK) {
             afc_plan_destroy(p);
             return rc;
@@ -550,8 +527,8 @@ AFC_API int afc_plan_launch(afc_plan* p, const int16_t* x, const float* taps, co
         for (int m = 0; m < 2 && le == hipSuccess; ++m) {
             const afc_plan::Mode& md = p->mode[m];
             if (!md.used) continue;
-            le = launch_xengine_persistent(z_workspace, vis, weights, flags, p->d_sbs, md.d_work, md.d_begin, md.n_wg,
-                                           p->N, p->Na, m, md.tile, p->cap_stream);
+            le = launch_xengine_list(z_workspace, vis, weights, flags, p->d_sbs, md.d_work, md.ranges, p->N, p->Na,
+                                     m, md.tile, p->cap_stream);
         }
         e = hipStreamEndCapture(p->cap_stream, &p->graph);
         if (le != hipSuccess) {
@@ -575,10 +552,8 @@ AFC_API int afc_plan_launch(afc_plan* p, const int16_t* x, const float* taps, co
 AFC_API void afc_plan_destroy(afc_plan* p) {
     if (!p) return;
     plan_free_graph(p);
-    for (auto& md : p->mode) {
+    for (auto& md : p->mode)
         if (md.d_work) hipFree(md.d_work);
-        if (md.d_begin) hipFree(md.d_begin);
-    }
     if (p->d_items) hipFree(p->d_items);
     if (p->d_sbs) hipFree(p->d_sbs);
     if (p->cap_stream) hipStreamDestroy(p->cap_stream);

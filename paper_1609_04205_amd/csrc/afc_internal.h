@@ -14,8 +14,6 @@ constexpr int kSBlk = AFC_SPECTRUM_BLOCK;
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int sample_bytes(afc_dtype t) { return t == AFC_F32 ? 8 : t == AFC_F16 ? 4 : 2; }
-// compute units of the current device (cached per device)
-int device_cu_count();
 
 // ---------------------------------------------------------------- PPF
 struct PpfLaunch {
@@ -59,8 +57,8 @@ struct XLaunch {
 };
 hipError_t launch_xengine(const XLaunch& a, hipStream_t stream);
 
-// Batched persistent X-engine work item (one lower-triangle tile of one
-// channel of one subband).
+// Batched X-engine work item (one lower-triangle tile of one channel of one
+// subband).
 struct XWork {
     int32_t sb;             // subband index
     int32_t ch;             // channel
@@ -74,10 +72,22 @@ struct XSubband {
     int32_t dt;
     int32_t pad;
 };
-hipError_t launch_xengine_persistent(const void* z_ws, void* vis, int32_t* weights,
-                                     const uint8_t* flags, const XSubband* sbs_dev,
-                                     const XWork* work_dev, const int32_t* wg_begin_dev,
-                                     int n_wg, int N, int Na, int mode, int tile, hipStream_t stream);
+// The work list is laid out XCD by XCD: XCD x owns items
+// [begin[x], begin[x] + count[x]).
+struct XcdRanges {
+    int32_t begin[8];
+    int32_t count[8];
+};
+// One workgroup per work item (workgroup ids go round-robin over the 8
+// XCDs); mode 0: int8 / fp16 subbands with tile-wide tiles (128 or 64),
+// mode 1: fp32 subbands (64).  Returns the grid size through n_wg_out.
+hipError_t launch_xengine_list(const void* z_ws, void* vis, int32_t* weights, const uint8_t* flags,
+                               const XSubband* sbs_dev, const XWork* work_dev, const XcdRanges& ranges,
+                               int N, int Na, int mode, int tile, hipStream_t stream);
+int xengine_list_grid(const XcdRanges& ranges);
+// Fill `bytes` (a multiple of 4) of device memory with hashed bytes that are
+// valid int8 samples and finite fp16 values (bit 6 of every byte clear).
+hipError_t launch_fill_scratch(void* p, size_t bytes, hipStream_t stream);
 int xengine_tile(afc_dtype dt);
 
 // ---------------------------------------------------------------- calibration

@@ -796,58 +796,67 @@ __global__ __launch_bounds__(kThreads, 2) void xengine_kernel(XArgs a) {
     xtile<DT, TILE>(z, vis, wsb, fl, a.N, a.Na, a.S[sb], ti, tj, wsb != nullptr && ch == 0, lds);
 }
 
-// Persistent batched form: a fixed grid walks a host-balanced list of work
-// items; each item is one tile of one channel of one subband with its own
-// sample type and integration length.  MODE 0 serves int8 and fp16 subbands
-// (mixed in one launch) with TILE-wide tiles, MODE 1 fp32 subbands (64).
+// Batched form: one workgroup per work item of a host-built list; each item
+// is one tile of one channel of one subband with its own sample type and
+// integration length.  MODE 0 serves int8 and fp16 subbands (mixed in one
+// launch) with TILE-wide tiles, MODE 1 fp32 subbands (64).  Workgroup ids go
+// round-robin over the 8 XCDs and the list holds each XCD's items (whole
+// channels, cost-balanced across XCDs) contiguously, so that the hardware
+// dispatcher keeps the tiles in flight on an XCD a window of few channels.
 template <int MODE, int TILE, int WPC>
-__global__ __launch_bounds__(kThreads, WPC) void xengine_persistent_kernel(
+__global__ __launch_bounds__(kThreads, WPC) void xengine_list_kernel(
     const char* __restrict__ z_ws, char* __restrict__ vis, int32_t* __restrict__ weights,
     const uint8_t* __restrict__ flags, const XSubband* __restrict__ sbs, const XWork* __restrict__ work,
-    const int32_t* __restrict__ wg_begin, int N, int Na) {
+    XcdRanges r, int N, int Na) {
     constexpr int kLds = MODE == 0 ? (lds_bytes<AFC_I8, TILE>() > lds_bytes<AFC_F16, TILE>() ? lds_bytes<AFC_I8, TILE>()
                                                                                             : lds_bytes<AFC_F16, TILE>())
                                    : lds_bytes<AFC_F32, TILE>();
     __shared__ __attribute__((aligned(16))) char lds[kLds];
+    const int x = blockIdx.x & 7, k = blockIdx.x >> 3;
+    if (k >= r.count[x]) return;
     const int64_t nbl = (int64_t)Na * (Na + 1) / 2;
-    const int b = blockIdx.x;
-    const int e0 = wg_begin[b], e1 = wg_begin[b + 1];
-    for (int e = e0; e < e1; ++e) {
-        const XWork wk = work[e];
-        const XSubband sd = sbs[wk.sb];
-        char* vis_ch = vis + sd.vis_off + (int64_t)wk.ch * nbl * 4 * 8;
-        int32_t* wsb = weights ? weights + (int64_t)wk.sb * nbl : nullptr;
-        const uint8_t* fl = flags ? flags + (int64_t)wk.sb * Na : nullptr;
-        const bool ww = wsb != nullptr && wk.ch == 0;
-        if constexpr (MODE == 0) {
-            if (sd.dt == AFC_I8) {
-                const char* z = z_ws + sd.z_off + (int64_t)wk.ch * sd.Sb * N * kSBlk * 2;
-                xtile<AFC_I8, TILE>(z, vis_ch, wsb, fl, N, Na, sd.S, wk.ti, wk.tj, ww, lds);
-            } else {
-                const char* z = z_ws + sd.z_off + (int64_t)wk.ch * sd.Sb * N * kSBlk * 4;
-                xtile<AFC_F16, TILE>(z, vis_ch, wsb, fl, N, Na, sd.S, wk.ti, wk.tj, ww, lds);
-            }
+    const XWork wk = work[r.begin[x] + k];
+    const XSubband sd = sbs[wk.sb];
+    char* vis_ch = vis + sd.vis_off + (int64_t)wk.ch * nbl * 4 * 8;
+    int32_t* wsb = weights ? weights + (int64_t)wk.sb * nbl : nullptr;
+    const uint8_t* fl = flags ? flags + (int64_t)wk.sb * Na : nullptr;
+    const bool ww = wsb != nullptr && wk.ch == 0;
+    if constexpr (MODE == 0) {
+        if (sd.dt == AFC_I8) {
+            const char* z = z_ws + sd.z_off + (int64_t)wk.ch * sd.Sb * N * kSBlk * 2;
+            xtile<AFC_I8, TILE>(z, vis_ch, wsb, fl, N, Na, sd.S, wk.ti, wk.tj, ww, lds);
         } else {
-            const char* z = z_ws + sd.z_off + (int64_t)wk.ch * sd.Sb * N * kSBlk * 8;
-            xtile<AFC_F32, TILE>(z, vis_ch, wsb, fl, N, Na, sd.S, wk.ti, wk.tj, ww, lds);
+            const char* z = z_ws + sd.z_off + (int64_t)wk.ch * sd.Sb * N * kSBlk * 4;
+            xtile<AFC_F16, TILE>(z, vis_ch, wsb, fl, N, Na, sd.S, wk.ti, wk.tj, ww, lds);
         }
-        lds_barrier();
+    } else {
+        const char* z = z_ws + sd.z_off + (int64_t)wk.ch * sd.Sb * N * kSBlk * 8;
+        xtile<AFC_F32, TILE>(z, vis_ch, wsb, fl, N, Na, sd.S, wk.ti, wk.tj, ww, lds);
     }
 }
 
 }  // namespace
 
-int device_cu_count() {
-    static int cache[64] = {0};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 256;
-    if (dev < 0 || dev >= 64) dev = 0;
-    if (cache[dev] == 0) {
-        int v = 0;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v < 1) v = 256;
-        cache[dev] = v;
+namespace {
+__global__ void fill_scratch_kernel(uint32_t* p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        uint32_t h = (uint32_t)i * 0x9E3779B9u ^ (uint32_t)(i >> 32);
+        h ^= h >> 16;
+        h *= 0x85EBCA6Bu;
+        h ^= h >> 13;
+        h *= 0xC2B2AE35u;
+        h ^= h >> 16;
+        p[i] = h & 0xBFBFBFBFu;
     }
-    return cache[dev];
+}
+}  // namespace
+
+hipError_t launch_fill_scratch(void* p, size_t bytes, hipStream_t stream) {
+    const size_t n = bytes / 4;
+    if (n == 0) return hipSuccess;
+    const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(fill_scratch_kernel, dim3(grid), dim3(256), 0, stream, reinterpret_cast<uint32_t*>(p), n);
+    return hipGetLastError();
 }
 
 int xengine_tile(afc_dtype dt) { return dt == AFC_F32 ? 64 : 128; }
@@ -883,21 +892,29 @@ hipError_t launch_xengine(const XLaunch& l, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_xengine_persistent(const void* z_ws, void* vis, int32_t* weights, const uint8_t* flags,
-                                     const XSubband* sbs_dev, const XWork* work_dev, const int32_t* wg_begin_dev,
-                                     int n_wg, int N, int Na, int mode, int tile, hipStream_t stream) {
+int xengine_list_grid(const XcdRanges& r) {
+    int mx = 0;
+    for (int x = 0; x < 8; ++x) mx = std::max(mx, (int)r.count[x]);
+    return mx * 8;
+}
+
+hipError_t launch_xengine_list(const void* z_ws, void* vis, int32_t* weights, const uint8_t* flags,
+                               const XSubband* sbs_dev, const XWork* work_dev, const XcdRanges& ranges, int N,
+                               int Na, int mode, int tile, hipStream_t stream) {
     const char* z = reinterpret_cast<const char*>(z_ws);
     char* v = reinterpret_cast<char*>(vis);
-    const dim3 grid((unsigned)n_wg), block(kThreads);
+    const int g = xengine_list_grid(ranges);
+    if (g == 0) return hipSuccess;
+    const dim3 grid((unsigned)g), block(kThreads);
     if (mode == 1)  // fp32 subbands
-        hipLaunchKernelGGL((xengine_persistent_kernel<1, 64, 2>), grid, block, 0, stream, z, v, weights, flags,
-                           sbs_dev, work_dev, wg_begin_dev, N, Na);
+        hipLaunchKernelGGL((xengine_list_kernel<1, 64, 2>), grid, block, 0, stream, z, v, weights, flags, sbs_dev,
+                           work_dev, ranges, N, Na);
     else if (tile == 128)
-        hipLaunchKernelGGL((xengine_persistent_kernel<0, 128, 2>), grid, block, 0, stream, z, v, weights, flags,
-                           sbs_dev, work_dev, wg_begin_dev, N, Na);
+        hipLaunchKernelGGL((xengine_list_kernel<0, 128, 2>), grid, block, 0, stream, z, v, weights, flags, sbs_dev,
+                           work_dev, ranges, N, Na);
     else
-        hipLaunchKernelGGL((xengine_persistent_kernel<0, 64, 4>), grid, block, 0, stream, z, v, weights, flags,
-                           sbs_dev, work_dev, wg_begin_dev, N, Na);
+        hipLaunchKernelGGL((xengine_list_kernel<0, 64, 4>), grid, block, 0, stream, z, v, weights, flags, sbs_dev,
+                           work_dev, ranges, N, Na);
     return hipGetLastError();
 }
 
