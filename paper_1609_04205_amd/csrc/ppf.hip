@@ -290,14 +290,17 @@ __global__ __launch_bounds__(kThreads) void ppf_kernel(const int16_t* __restrict
 __global__ __launch_bounds__(kThreads) void ppf_batched_kernel(const int16_t* __restrict__ x,
                                                               const float* __restrict__ taps, void* __restrict__ z,
                                                               Tw64 tw, const PpfItem* __restrict__ items,
-                                                              int N, int n_groups, int n_chunks) {
+                                                              int N, int n_groups, int n_chunks, int total,
+                                                              int per_xcd) {
     __shared__ float2 lds[kSpectraPerPhase * kSStride];
     __shared__ __attribute__((aligned(16))) float ltaps[kT * kP];
-    int bid = blockIdx.x;
-    const int chunk = bid % n_chunks;
-    bid /= n_chunks;
-    const int grp = bid % n_groups;
-    const int it = bid / n_groups;
+    // XCD-aware order as in ppf_kernel: neighbouring receiver groups (which
+    // share 128-byte lines of the input rows) run on one XCD at one time
+    const int w = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (w >= total) return;
+    const int grp = w % n_groups;
+    const int chunk = (w / n_groups) % n_chunks;
+    const int it = w / (n_groups * n_chunks);
     const PpfItem item = items[it];
     const int s_begin = chunk * kChunk;
     if (s_begin >= item.S) return;                       // uniform over the workgroup
@@ -353,9 +356,13 @@ hipError_t launch_ppf_batched(const int16_t* x, const float* taps, void* z_ws, c
     static const Tw64 tw = make_twiddles();
     const int n_groups = (int)ceil_div(N, kNi);
     const int n_chunks = (int)ceil_div(max_S, kChunk);
-    const dim3 grid((unsigned)((int64_t)n_items * n_groups * n_chunks));
+    const int64_t total64 = (int64_t)n_items * n_groups * n_chunks;
+    if (total64 > (1LL << 30)) return hipErrorInvalidValue;
+    const int total = (int)total64;
+    const int per_xcd = (int)ceil_div(total, 8);
+    const dim3 grid((unsigned)(per_xcd * 8));
     hipLaunchKernelGGL(ppf_batched_kernel, grid, dim3(kThreads), 0, stream, x, taps, z_ws, tw, items_dev, N,
-                       n_groups, n_chunks);
+                       n_groups, n_chunks, total, per_xcd);
     return hipGetLastError();
 }
 
