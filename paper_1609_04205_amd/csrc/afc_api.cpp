@@ -1,5 +1,5 @@
 // C ABI of the FX-correlator library: argument checks, launch set-up, the
-// batching plan (host-balanced persistent work lists, HIP graph replay and
+// batching plan (XCD-balanced work lists, HIP graph replay and
 // the tile tuner).  See include/afc.h for the contract of each entry point.
 #include <hip/hip_runtime.h>
 

@@ -1,4 +1,4 @@
-"""Batching form: one graph (channeliser + persistent correlator) over subbands
+"""Batching form: one graph (channeliser + correlator launches) over subbands
 with their own integration length, sample type and antenna flags."""
 import numpy as np
 import pytest
