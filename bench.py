@@ -9,10 +9,12 @@ Inputs are synthetic, seeded, and resident in HBM before timing starts.
 Prints ONE JSON line.  `value` is the whole step's useful complex
 multiply-accumulates per second (TCMAC/s).  Beside it: per-kernel times from
 HIP events on the launch stream, the X-engine's fraction of the int8 MFMA
-peak, the PPF's algorithmic GB/s, the real-time factor, the fp32 path for the
-int8-vs-fp32 comparison, the batching plan (32 subbands, ragged, flagged,
-mixed fp16/int8) and the calibration gradient, and the CPU oracle timed on
-a bounded sample on the host cores.
+peak (and the MACs it issues including diagonal-tile and padding waste), the
+PPF's algorithmic GB/s, the real-time factor, the fp32 path for the
+int8-vs-fp32 comparison, the host-to-device rate of the int16 input (not in
+the step), the whole 32-subband band of the same shape, the batching plan
+(32 subbands, ragged, flagged, mixed fp16/int8) and the calibration
+gradient, and the CPU oracle timed on a bounded sample on the host cores.
 """
 import argparse
 import json
@@ -187,6 +189,15 @@ def main():
                "frac": round(xe_tops / PEAK_INT8_TOPS, 4), "traffic": measured_traffic("xengine_kernel<int8,128>")}
     out["roofline"] = xe_roof if xe_ms >= ppf_ms else ppf_roof
     out["roofline_other"] = ppf_roof if xe_ms >= ppf_ms else xe_roof
+    # complex MACs the int8 X-engine actually issues on MFMA: whole 128 x 128
+    # off-diagonal tiles, ten 32 x 32 blocks per diagonal tile, spectra padded
+    # to whole stages of 4 blocks of 8
+    T = -(-N // 128)
+    pairs_computed = T * (T - 1) // 2 * 128 * 128 + T * 10 * 32 * 32
+    spectra_computed = -(-((S + 7) // 8) // 4) * 32
+    computed = float(B) * P * pairs_computed * spectra_computed
+    out["xengine_computed_cmac"] = computed
+    out["xengine_useful_fraction"] = round(cmac / computed, 4)
     log(f"int8 step {ms_step:.3f} ms (ppf {ppf_ms:.3f}, xengine {xe_ms:.3f})")
 
     if not args.no_extras:
@@ -217,6 +228,48 @@ def main():
         out["int8_speedup_over_fp32_xengine"] = round(f32_xe / xe_ms, 2)
         log(f"fp32 xengine {f32_xe:.3f} ms")
         del z32, vis32, x, vis
+        torch.cuda.empty_cache()
+
+        # ---- host-to-device copy of the int16 input (not part of the step:
+        # the entry points take device buffers), one subband-second at a time
+        xh = torch.empty((L, N, 2), dtype=torch.int16, pin_memory=True)
+        xd = torch.empty((L, N, 2), dtype=torch.int16, device=dev)
+        th = Timer(torch)
+        for it in range(4):
+            e = th.rec("h2d") if it > 0 else None
+            xd.copy_(xh, non_blocking=True)
+            if e is not None:
+                e.record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        h2d_ms = th.ms("h2d")
+        sb_bytes = float(L) * N * 4
+        out["h2d"] = {"bytes_per_subband_second": sb_bytes, "gbs": round(sb_bytes / (h2d_ms * 1e-3) / 1e9, 1),
+                      "ms_per_subband_second": round(h2d_ms, 3),
+                      "step_ms_with_h2d": round(ms_step + B * h2d_ms, 3),
+                      "real_time_factor_with_h2d": round(data_s / ((ms_step + B * h2d_ms) * 1e-3), 2)}
+        log(f"h2d {h2d_ms:.3f} ms per subband-second")
+        del xh, xd
+
+        # ---- the whole AARTFAAC-12 band: 32 subbands of the same shape
+        cfg32 = W.Config("a12-576ant-32sb", Na, 32, n_spectra=S, sigma_n=cfg.sigma_n, n_sources=cfg.n_sources,
+                         seed=cfg.seed, layout=cfg.layout)
+        x32 = W.make_voltages(cfg32, device=dev)
+        z32b = torch.empty(afc.channelised_shape(32, S, N), dtype=torch.int8, device=dev)
+        v32 = torch.empty(afc.visibility_shape(32, Na), dtype=torch.int32, device=dev)
+        w32 = torch.empty((32, nbl), dtype=torch.int32, device=dev)
+        t32b = Timer(torch)
+        for it in range(3):
+            e = t32b.rec("step") if it > 0 else None
+            afc.channelise(x32, taps, S, "i8", gain, out=z32b)
+            afc.correlate(z32b, n_spectra=S, out=v32, weights=w32)
+            if e is not None:
+                e.record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        ms32 = t32b.ms("step")
+        out["a12_32sb"] = {"ms": round(ms32, 3), "tcmacs": round(2 * cmac / (ms32 * 1e-3) / 1e12, 3),
+                           "real_time_factor": round(data_s / (ms32 * 1e-3), 2)}
+        log(f"32 subbands {ms32:.3f} ms")
+        del x32, z32b, v32, w32
         torch.cuda.empty_cache()
 
         # ---- batching form: 32 subbands, ragged S, flags, mixed fp16/int8, one graph
