@@ -48,6 +48,9 @@ def _load():
     lib.orc_xcorr_i64.restype = C.c_int
     lib.orc_cal_loss_grad.argtypes = [_p, _p, _p, _i64, _i64, _p, _p]
     lib.orc_cal_loss_grad.restype = C.c_int
+    lib.orc_fine_channelise.argtypes = [_p, _i64, _i64, _i64, _p, _i64, _i64, _i64, _i64,
+                                        C.c_double, C.c_double, C.c_double, _p, _i64, _p]
+    lib.orc_fine_channelise.restype = C.c_int
     _lib = lib
     return lib
 
@@ -96,6 +99,38 @@ def ppf_subband(x: np.ndarray, taps: np.ndarray, P: int, T: int, S: int,
     out = np.empty((P, S, len(inputs)), np.complex128)
     for n, i in enumerate(inputs):
         out[:, :, n] = ppf_stream(x, taps, i, P, T, 0, S).T
+    return out
+
+
+def fine_channelise(x: np.ndarray, taps: np.ndarray, input: int, Pf: int, T: int, s0: int, s1: int,
+                    tau: float, nu_c: float, df: float, w: np.ndarray, R: int) -> np.ndarray:
+    """Fine channeliser + delay/bandpass compensation + R:1 channel
+    integration of one input (Sec. "Polyphase Filterbank", Sec. "Delay,
+    Bandpass Compensation and Transpose Kernel"): complex128 [s1-s0][Pf/R]."""
+    x = _c(x, np.int16)
+    L = x.shape[0]
+    Rr = x.size // (2 * L)
+    taps = _c(taps, np.float32)
+    w = _c(w, np.float32)
+    assert taps.size == Pf * T and w.size == Pf and Pf % R == 0
+    out = np.empty((s1 - s0, Pf // R, 2), np.float64)
+    rc = _load().orc_fine_channelise(_ptr(x), L, Rr, input, _ptr(taps), Pf, T, s0, s1, float(tau), float(nu_c),
+                                     float(df), _ptr(w), R, _ptr(out))
+    if rc != 0:
+        raise ValueError("orc_fine_channelise: invalid range or sizes")
+    return _to_complex(out)
+
+
+def fine_subband(x: np.ndarray, taps: np.ndarray, Pf: int, T: int, S: int, tau: np.ndarray, nu_c: float,
+                 df: float, w: np.ndarray, R: int, inputs=None) -> np.ndarray:
+    """All (or the listed) inputs of one subband: complex128 [Pf/R][S][R']."""
+    x = _c(x, np.int16)
+    L = x.shape[0]
+    Rr = x.size // (2 * L)
+    inputs = range(Rr) if inputs is None else list(inputs)
+    out = np.empty((Pf // R, S, len(inputs)), np.complex128)
+    for n, i in enumerate(inputs):
+        out[:, :, n] = fine_channelise(x, taps, i, Pf, T, 0, S, tau[i], nu_c, df, w, R).T
     return out
 
 
