@@ -118,6 +118,51 @@ AFC_API int afc_channelise(const afc_dims* d, const int16_t* x, const float* tap
                            hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * afc_channelise_fine -- the paper's channeliser configuration: a 256-channel
+ * polyphase filter bank (Sec. "Polyphase Filterbank": 256 16-tap FIR filters
+ * and a 256-point complex FFT), fixed cable-delay compensation as phase
+ * rotations and a fixed real weight per channel against the first-stage
+ * bandpass ripple, then integration of adjacent channels to the output
+ * resolution and the corner turn (Sec. "Delay, Bandpass Compensation and
+ * Transpose Kernel").  Per receiver i of subband b:
+ *
+ *   u[s][p] = sum_{t<16} taps[t*256 + p] * x[(s+t)*256 + p]     (p < 256)
+ *   y[s][k] = sum_{p<256} u[s][p] * exp(-2 pi i k p / 256)      (k < 256)
+ *   f_k     = (k < 128 ? k : k - 256) * subband_width_hz / 256
+ *   z[s][c] = sum_{j<4} bandpass[4c+j] * exp(2 pi i (center_hz[b] + f_{4c+j})
+ *                                              * delays[i]) * y[s][4c+j]
+ *
+ * for c < 64: output channel c is the coherent sum of fine channels
+ * 4c .. 4c+3 in natural FFT order.  A spectrum s spans 256 input samples, so
+ * z holds d->n_spectra spectra of 64 channels and is laid out, typed and
+ * sized exactly as afc_channelise's output (afc_correlate takes it as is).
+ *
+ * d        n_channels = 64 (the output channels), n_taps = 16, n_spectra = S
+ *          (256-sample spectra).
+ * x        int16 [B][L][N][2], L = (S + 15) * 256 rows, as in afc_channelise.
+ * taps     float [16*256] in the order taps[t*256 + p].
+ * delays   double [N] (device), seconds, per receiver; positive = the signal
+ *          arrives late.
+ * bandpass float [256] (device), real weight per fine channel k (natural order).
+ * center_hz  double [B] (host), sky frequency of each subband's centre.
+ * subband_width_hz  > 0 (195312.5 for the 200 MHz sample clock).
+ * out_dtype, requant_gain  as in afc_channelise.
+ * workspace  device buffer of afc_channelise_fine_workspace_bytes(d) bytes:
+ *          the tables of exp(-2 pi i m / 256), of bandpass-weighted delay
+ *          phases per (receiver, fine channel) and of centre-frequency phases
+ *          per (subband, receiver), recomputed in float64 on every call.
+ *          Calls sharing one workspace on different streams race.
+ * out      as afc_channelise, afc_channelised_bytes(d, out_dtype) bytes.
+ * Limits: L*N*2 < 2^31 per subband; other limits as afc_channelise.
+ * ------------------------------------------------------------------------- */
+AFC_API size_t afc_channelise_fine_workspace_bytes(const afc_dims* d);
+AFC_API int afc_channelise_fine(const afc_dims* d, const int16_t* x, const float* taps,
+                                const double* delays, const float* bandpass,
+                                const double* center_hz, double subband_width_hz,
+                                afc_dtype out_dtype, float requant_gain, void* workspace,
+                                void* out, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * afc_correlate -- X-engine (Sec. "Correlation Kernel": only one triangle of
  * the Hermitian covariance matrix is computed, per channel, and the
  * visibilities are accumulated over the integration; Sec. "CPU Data

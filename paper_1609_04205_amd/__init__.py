@@ -21,6 +21,8 @@ DTYPES = {"f32": AFC_F32, "f16": AFC_F16, "i8": AFC_I8}
 SPECTRUM_BLOCK = 8
 N_CHANNELS = 64
 N_TAPS = 16
+N_FINE = 256          # channels of the fine bank, integrated 4:1 to N_CHANNELS
+SUBBAND_HZ = 195312.5
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run paper_1609_04205_amd/build.py (or __graft_entry__.build())")
@@ -41,6 +43,10 @@ _lib.afc_visibility_bytes.argtypes = [C.POINTER(Dims)]
 _lib.afc_visibility_bytes.restype = _sz
 _lib.afc_channelise.argtypes = [C.POINTER(Dims), _vp, _vp, C.c_int, _f32, _vp, _vp]
 _lib.afc_correlate.argtypes = [C.POINTER(Dims), C.c_int, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.afc_channelise_fine_workspace_bytes.argtypes = [C.POINTER(Dims)]
+_lib.afc_channelise_fine_workspace_bytes.restype = _sz
+_lib.afc_channelise_fine.argtypes = [C.POINTER(Dims), _vp, _vp, _vp, _vp, C.POINTER(C.c_double), C.c_double,
+                                     C.c_int, _f32, _vp, _vp, _vp]
 _lib.afc_calibrate_workspace_bytes.argtypes = [_i32, _i32]
 _lib.afc_calibrate_workspace_bytes.restype = _sz
 _lib.afc_calibrate_grad.argtypes = [_i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -52,7 +58,8 @@ _lib.afc_plan_info.argtypes = [_vp, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(
 _lib.afc_plan_destroy.argtypes = [_vp]
 _lib.afc_plan_destroy.restype = None
 
-EXPORTS = ["afc_channelised_bytes", "afc_visibility_bytes", "afc_channelise", "afc_correlate",
+EXPORTS = ["afc_channelised_bytes", "afc_visibility_bytes", "afc_channelise",
+           "afc_channelise_fine_workspace_bytes", "afc_channelise_fine", "afc_correlate",
            "afc_calibrate_workspace_bytes", "afc_calibrate_grad", "afc_plan_create",
            "afc_plan_workspace_bytes", "afc_plan_launch", "afc_plan_info", "afc_plan_destroy",
            "afc_last_error"]
@@ -125,6 +132,47 @@ def channelise(x, taps, n_spectra: int, out_dtype: str = "f32", gain: float = 1.
         raise AfcError(f"out shape {tuple(out.shape)} != {shape}")
     _check(_lib.afc_channelise(C.byref(d), _ptr(x), _ptr(taps), DTYPES[out_dtype], float(gain), _ptr(out),
                                _stream(x.device)), "afc_channelise")
+    return out
+
+
+def channelise_fine(x, taps, n_spectra: int, delays, bandpass, center_hz: Sequence[float],
+                    subband_hz: float = SUBBAND_HZ, out_dtype: str = "f32", gain: float = 1.0, out=None,
+                    workspace=None):
+    """256-channel bank, delay and bandpass compensation, 4:1 channel
+    integration: x int16 [B][L][N][2], L = (S+15)*256 -> z [B][64][Sb][N][8][2]
+    (the layout of channelise).  delays float64 [N] seconds and bandpass
+    float32 [256] on the GPU; center_hz: B sky frequencies (host)."""
+    torch = _torch()
+    _require(x, torch.int16, "x")
+    _require(taps, torch.float32, "taps")
+    _require(delays, torch.float64, "delays")
+    _require(bandpass, torch.float32, "bandpass")
+    B, L = x.shape[0], x.shape[1]
+    N = x[0, 0].numel() // 2
+    d = dims(N // 2, B, n_spectra)
+    if L != (n_spectra + N_TAPS - 1) * N_FINE:
+        raise AfcError(f"x has {L} rows, expected (S+T-1)*256 = {(n_spectra + N_TAPS - 1) * N_FINE}")
+    if taps.numel() != N_TAPS * N_FINE or delays.numel() != N or bandpass.numel() != N_FINE:
+        raise AfcError("taps, delays or bandpass has the wrong size")
+    nu = (C.c_double * B)(*[float(v) for v in center_hz])
+    if len(center_hz) != B:
+        raise AfcError(f"center_hz has {len(center_hz)} entries, expected {B}")
+    shape = channelised_shape(B, n_spectra, N)
+    tdt = getattr(torch, _TORCH_OF[out_dtype])
+    if out is None:
+        out = torch.empty(shape, dtype=tdt, device=x.device)
+    _require(out, tdt, "out")
+    if tuple(out.shape) != shape:
+        raise AfcError(f"out shape {tuple(out.shape)} != {shape}")
+    need = _lib.afc_channelise_fine_workspace_bytes(C.byref(d))
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
+    _require(workspace, torch.uint8, "workspace")
+    if workspace.numel() < need:
+        raise AfcError(f"workspace holds {workspace.numel()} bytes, {need} needed")
+    _check(_lib.afc_channelise_fine(C.byref(d), _ptr(x), _ptr(taps), _ptr(delays), _ptr(bandpass), nu,
+                                    float(subband_hz), DTYPES[out_dtype], float(gain), _ptr(workspace),
+                                    _ptr(out), _stream(x.device)), "afc_channelise_fine")
     return out
 
 

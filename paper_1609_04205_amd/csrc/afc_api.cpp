@@ -109,6 +109,63 @@ AFC_API int afc_channelise(const afc_dims* d, const int16_t* x, const float* tap
     return AFC_OK;
 }
 
+namespace {
+// int16 values of one subband of fine-channeliser input: (S + T - 1) * 256 rows
+int64_t fine_x_values(const afc_dims* d) {
+    return ((int64_t)d->n_spectra + kT - 1) * kPFine * 2LL * d->n_antennas * 2;
+}
+}  // namespace
+
+AFC_API size_t afc_channelise_fine_workspace_bytes(const afc_dims* d) {
+    if (check_dims(d) != AFC_OK) return 0;
+    return fine_workspace_bytes(2 * d->n_antennas, d->n_subbands);
+}
+
+AFC_API int afc_channelise_fine(const afc_dims* d, const int16_t* x, const float* taps, const double* delays,
+                                const float* bandpass, const double* center_hz, double subband_width_hz,
+                                afc_dtype out_dtype, float requant_gain, void* workspace, void* out,
+                                hipStream_t stream) {
+    g_err.clear();
+    int rc = check_dims(d);
+    if (rc != AFC_OK) return rc;
+    if (!x || !taps || !delays || !bandpass || !center_hz || !out)
+        return fail(AFC_ERR_INVALID, "NULL pointer (x, taps, delays, bandpass, center_hz or out)");
+    if (!workspace) return fail(AFC_ERR_WORKSPACE, "workspace is NULL");
+    if (!dtype_ok(out_dtype)) return fail(AFC_ERR_INVALID, "unknown out_dtype %d", (int)out_dtype);
+    if (out_dtype == AFC_I8 && !(std::isfinite(requant_gain) && requant_gain > 0.0f))
+        return fail(AFC_ERR_INVALID, "requant_gain must be finite and > 0 for AFC_I8");
+    if (!(std::isfinite(subband_width_hz) && subband_width_hz > 0.0))
+        return fail(AFC_ERR_INVALID, "subband_width_hz must be finite and > 0");
+    for (int b = 0; b < d->n_subbands; ++b)
+        if (!std::isfinite(center_hz[b])) return fail(AFC_ERR_INVALID, "center_hz[%d] is not finite", b);
+    if (fine_x_values(d) >= (1LL << 31))
+        return fail(AFC_ERR_UNSUPPORTED, "one subband of input holds %lld int16 values (limit 2^31)",
+                    (long long)fine_x_values(d));
+    const int64_t N = 2LL * d->n_antennas;
+    const int64_t z_sb = z_sb_samples(N, d->n_spectra);
+    if (z_sb * sample_bytes(out_dtype) >= (1LL << 40)) return fail(AFC_ERR_UNSUPPORTED, "output too large");
+    FineLaunch l{};
+    l.x = x;
+    l.taps = taps;
+    l.tau = delays;
+    l.bandpass = bandpass;
+    l.nu_center = center_hz;
+    l.subband_hz = subband_width_hz;
+    l.workspace = workspace;
+    l.z = out;
+    l.x_sb_stride = fine_x_values(d);
+    l.z_sb_stride = z_sb;
+    l.N = (int)N;
+    l.S = d->n_spectra;
+    l.Sb = (int)blocks_of(d->n_spectra);
+    l.B = d->n_subbands;
+    l.gain = requant_gain;
+    l.dt = out_dtype;
+    hipError_t e = launch_ppf_fine(l, stream);
+    if (e != hipSuccess) return hip_fail(e, "fine channeliser launch");
+    return AFC_OK;
+}
+
 AFC_API int afc_correlate(const afc_dims* d, afc_dtype in_dtype, const void* z, const int32_t* n_spectra_per_sb,
                           const uint8_t* flags, void* vis, int32_t* weights, hipStream_t stream) {
     g_err.clear();

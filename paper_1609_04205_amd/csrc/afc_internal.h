@@ -10,6 +10,7 @@ namespace afc {
 
 constexpr int kP = 64;                 // channels
 constexpr int kT = 16;                 // taps per branch
+constexpr int kPFine = 256;            // channels of the fine bank
 constexpr int kSBlk = AFC_SPECTRUM_BLOCK;
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -42,6 +43,27 @@ struct PpfItem {
 };
 hipError_t launch_ppf_batched(const int16_t* x, const float* taps, void* z_ws, const PpfItem* items_dev,
                               int n_items, int N, int max_S, hipStream_t stream);
+
+// Fine channeliser: 256-channel bank, delay and bandpass compensation,
+// coherent 4:1 integration to 64 channels, stored in the layout of the
+// 64-channel bank (one table launch, then one channeliser launch).
+struct FineLaunch {
+    const int16_t* x;       // subband 0 base, rows of 256 samples per spectrum
+    const float* taps;      // [T*256]
+    const double* tau;      // device [N] delays in seconds
+    const float* bandpass;  // device [256] weights, natural FFT order
+    const double* nu_center;// host [B] subband centre frequencies in Hz
+    double subband_hz;      // subband width in Hz
+    void* workspace;        // fine_workspace_bytes(N, B)
+    void* z;
+    int64_t x_sb_stride;    // int16 elements between subbands
+    int64_t z_sb_stride;    // samples between subbands
+    int N, S, Sb, B;
+    float gain;
+    afc_dtype dt;
+};
+size_t fine_workspace_bytes(int N, int B);
+hipError_t launch_ppf_fine(const FineLaunch& l, hipStream_t stream);
 
 // ---------------------------------------------------------------- X-engine
 struct XLaunch {

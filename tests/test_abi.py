@@ -72,3 +72,37 @@ def test_invalid_arguments_are_rejected_on_host(afc):
     out = C.c_void_p()
     assert lib.afc_plan_create(C.byref(d), None, None, None, C.byref(out)) == -1
     assert not out.value
+
+
+def test_fine_channeliser_sizes_and_argument_checks(afc):
+    lib = afc._lib
+    d = afc.dims(576, 16, 762)
+    N, B = 1152, 16
+    assert lib.afc_channelise_fine_workspace_bytes(C.byref(d)) == (256 + N * 256 + B * N) * 8
+    bad = afc.dims(576, 16, 762, n_channels=256)
+    assert lib.afc_channelise_fine_workspace_bytes(C.byref(bad)) == 0
+    dummy = C.c_void_p(0x1000)          # never dereferenced: validation fails first
+    nu = (C.c_double * 16)(*([60e6] * 16))
+    ok = dict(x=dummy, taps=dummy, delays=dummy, bp=dummy, nu=nu, width=195312.5, dt=afc.AFC_F32, gain=1.0,
+              ws=dummy, out=dummy)
+
+    def call(dims=d, **kw):
+        a = dict(ok, **kw)
+        return lib.afc_channelise_fine(C.byref(dims), a["x"], a["taps"], a["delays"], a["bp"], a["nu"],
+                                       a["width"], a["dt"], a["gain"], a["ws"], a["out"], None)
+
+    assert call(delays=None) == -1
+    assert call(bp=None) == -1
+    assert call(nu=None) == -1
+    assert call(ws=None) == -4
+    assert call(width=0.0) == -1
+    assert call(width=float("nan")) == -1
+    assert call(dt=afc.AFC_I8, gain=0.0) == -1
+    assert call(dt=9) == -1
+    nan_nu = (C.c_double * 16)(*([float("inf")] * 16))
+    assert call(nu=nan_nu) == -1
+    assert call(dims=bad) == -2
+    # (S + 15) * 256 rows of 2 N int16 values must stay below 2^31 per subband
+    huge = afc.dims(576, 1, 4000)
+    assert call(dims=huge) == -2
+    assert b"2^31" in lib.afc_last_error()

@@ -113,6 +113,48 @@ def requant_gain(cfg: Config, taps: np.ndarray, clip_sigmas: float = 4.0) -> flo
 
 
 # --------------------------------------------------------------------------
+# inputs of the fine channeliser: cable delays and bandpass weights
+# --------------------------------------------------------------------------
+N_FINE = 256                  # channels of the paper's filter bank
+FINE_RATIO = 4                # fine channels per output channel
+
+
+def fine_rows(n_spectra: int, n_taps: int = 16) -> int:
+    """Input rows of the fine channeliser for n_spectra 256-sample spectra."""
+    return (n_spectra + n_taps - 1) * N_FINE
+
+
+def cable_delays(n_inputs: int, seed: int = 5, max_delay: float = 6.0e-7) -> np.ndarray:
+    """Per-receiver fixed cable delays in seconds, float64 [N].
+
+    The paper reads them from calibration tables it does not print; a
+    dual-polarised antenna's two receivers share one cable run, so both get
+    the antenna's delay U[0, max_delay] plus an independent 0..2 ns offset
+    (0.6 us is about 120 m of coax).
+    """
+    rng = np.random.default_rng([seed, 606])
+    Na = n_inputs // 2
+    base = rng.uniform(0.0, max_delay, size=Na)
+    return (np.repeat(base, 2) + rng.uniform(0.0, 2.0e-9, size=2 * Na)).astype(np.float64)
+
+
+def bandpass_weights(n_fine: int = N_FINE, seed: int = 6) -> np.ndarray:
+    """Real positive weights per fine channel (natural FFT order), float32.
+
+    Stand-in for the correction of the first-stage filter bank's ripple
+    across a subband, which the paper applies from fixed tables it does not
+    print: the inverse of a smooth response that falls by about 30 % towards
+    the subband edges, with a 2 % ripple.
+    """
+    rng = np.random.default_rng([seed, 707])
+    k = np.arange(n_fine)
+    f = np.where(k < n_fine // 2, k, k - n_fine) / n_fine          # -0.5 .. 0.5
+    ph = rng.uniform(0.0, 2.0 * np.pi)
+    resp = (1.0 - 1.2 * f * f) * (1.0 + 0.02 * np.cos(2.0 * np.pi * 7.0 * f + ph))
+    return (1.0 / resp).astype(np.float32)
+
+
+# --------------------------------------------------------------------------
 # array geometry and sky
 # --------------------------------------------------------------------------
 def _disc(rng: np.random.Generator, n: int, radius: float) -> np.ndarray:
