@@ -12,7 +12,9 @@ HIP events on the launch stream, the X-engine's fraction of the int8 MFMA
 peak (and the MACs it issues including diagonal-tile and padding waste), the
 PPF's algorithmic GB/s, the real-time factor, the fp32 path for the
 int8-vs-fp32 comparison, the host-to-device rate of the int16 input (not in
-the step), the whole 32-subband band of the same shape, the batching plan
+the step), the whole 32-subband band of the same shape, the paper's
+256-channel configuration (fused delay/bandpass compensation and 4:1 channel
+integration, then the X-engine), the batching plan
 (32 subbands, ragged, flagged, mixed fp16/int8) and the calibration
 gradient, and the CPU oracle timed on a bounded sample on the host cores.
 """
@@ -63,6 +65,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="time only the int8 step")
     ap.add_argument("--cpu-sample-spectra", type=int, default=512)
+    ap.add_argument("--fine-only", action="store_true",
+                    help="only time the 256-channel configuration (fine channeliser + X-engine on its output)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (three times), to scale HBM byte counters")
     return ap.parse_args()
@@ -111,6 +115,9 @@ def main():
 
     dev = torch.device("cuda:0")
     cfg = W.CONFIGS[3]
+    if args.fine_only:
+        print(json.dumps({"fine": run_fine(torch, afc, W, dev, cfg, reps=args.steps)}), flush=True)
+        return
     B, Na, S, P = cfg.n_subbands, cfg.n_antennas, cfg.n_spectra, 64
     N = 2 * Na
     nbl = Na * (Na + 1) // 2
@@ -272,6 +279,9 @@ def main():
         del x32, z32b, v32, w32
         torch.cuda.empty_cache()
 
+        # ---- the paper's channeliser configuration on the same array
+        out["fine"] = run_fine(torch, afc, W, dev, cfg)
+
         # ---- batching form: 32 subbands, ragged S, flags, mixed fp16/int8, one graph
         cfg4 = W.CONFIGS[4]
         bp = W.batch_params(cfg4)
@@ -324,6 +334,63 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_spectra)
     print(json.dumps(out), flush=True)
+
+
+def run_fine(torch, afc, W, dev, cfg, reps=3):
+    """The paper's channeliser configuration on the given array: 256-channel
+    bank, cable-delay and bandpass compensation, 4:1 channel integration (one
+    fused kernel after a small table kernel), then the int8 X-engine on its
+    output; about 1 s of data (762 spectra of 256 samples)."""
+    B, Na, S, P = cfg.n_subbands, cfg.n_antennas, cfg.n_spectra, 64
+    N = 2 * Na
+    nbl = Na * (Na + 1) // 2
+    Sf = S // 4                                               # 762 spectra of 256 samples
+    xf = W.make_voltages(cfg, device=dev, n_rows=W.fine_rows(Sf))
+    tf_np = W.prototype_taps(256, 16)
+    bp_np = W.bandpass_weights()
+    tapsf = torch.from_numpy(tf_np).to(dev)
+    tau = torch.from_numpy(W.cable_delays(N)).to(dev)
+    bpw = torch.from_numpy(bp_np).to(dev)
+    nus = [W.subband_frequency(b) for b in range(B)]
+    gf = W.fine_requant_gain(cfg, tf_np, bp_np)
+    wsf = torch.empty(afc.fine_workspace_bytes(Na, B, Sf), dtype=torch.uint8, device=dev)
+    zf = torch.empty(afc.channelised_shape(B, Sf, N), dtype=torch.int8, device=dev)
+    visf = torch.empty(afc.visibility_shape(B, Na), dtype=torch.int32, device=dev)
+    wf = torch.empty((B, nbl), dtype=torch.int32, device=dev)
+    tfn = Timer(torch)
+    for it in range(reps + 1):
+        tm = tfn if it > 0 else None
+        if tm:
+            e = tm.rec("fine")
+        afc.channelise_fine(xf, tapsf, Sf, tau, bpw, nus, W.F_SUBBAND, "i8", gf, out=zf, workspace=wsf)
+        if tm:
+            e.record(torch.cuda.current_stream())
+            e = tm.rec("xengine")
+        afc.correlate(zf, n_spectra=Sf, out=visf, weights=wf)
+        if tm:
+            e.record(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    f_ms, fx_ms = tfn.ms("fine"), tfn.ms("xengine")
+    Lf = W.fine_rows(Sf)
+    # int16 input, int8 output, the tables written once and read once, the taps
+    fine_bytes = (float(B) * Lf * N * 4 + float(B) * P * ((Sf + 7) // 8) * 8 * N * 2
+                  + (256 + N * 256 + B * N) * 8 * 2 + 16 * 256 * 4)
+    cmac_f = float(B) * P * (N * (N + 1) // 2) * Sf
+    data_f = Sf * 256 / W.F_SUBBAND
+    res = {"workload": f"a12-576ant-16sb-{Sf}spectra-256ch-4to1",
+                   "channelise_ms": round(f_ms, 3),
+                   "channelise_gbs": round(fine_bytes / (f_ms * 1e-3) / 1e9, 1),
+                   "channelise_hbm_frac": round(fine_bytes / (f_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                   "channelise_ms_per_subband_second": round(f_ms / B / data_f, 3),
+                   "xengine_ms": round(fx_ms, 3),
+                   "step_ms": round(f_ms + fx_ms, 3),
+                   "tcmacs": round(cmac_f / ((f_ms + fx_ms) * 1e-3) / 1e12, 3),
+                   "real_time_factor": round(data_f / ((f_ms + fx_ms) * 1e-3), 2),
+                   "traffic": measured_traffic("ppf_fine_kernel<int8>")}
+    log(f"fine channeliser {f_ms:.3f} ms, xengine on its output {fx_ms:.3f} ms")
+    del xf, zf, visf, wf, wsf
+    torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline(S_s):

@@ -135,6 +135,11 @@ def channelise(x, taps, n_spectra: int, out_dtype: str = "f32", gain: float = 1.
     return out
 
 
+def fine_workspace_bytes(n_antennas: int, n_subbands: int, n_spectra: int) -> int:
+    d = dims(n_antennas, n_subbands, n_spectra)
+    return int(_lib.afc_channelise_fine_workspace_bytes(C.byref(d)))
+
+
 def channelise_fine(x, taps, n_spectra: int, delays, bandpass, center_hz: Sequence[float],
                     subband_hz: float = SUBBAND_HZ, out_dtype: str = "f32", gain: float = 1.0, out=None,
                     workspace=None):

@@ -65,8 +65,10 @@ template <int DT>
 __global__ __launch_bounds__(kThreadsF) void ppf_fine_kernel(FineArgs a, Tw64 tw64) {
     __shared__ __attribute__((aligned(16))) float2 lds[kSppF * kSSF];
     __shared__ __attribute__((aligned(16))) float ltaps[kT * kPF];
-    __shared__ float2 lcomp[kNiF * kPF];
-    __shared__ float2 ltw[4 * 16];               // [qd][k2] exp(-2 pi i qd k2 / 64)
+    // rows padded by one element: the four receivers' rows start in
+    // different banks
+    __shared__ float2 lcomp[kNiF * (kPF + 1)];
+    __shared__ float2 ltw[4 * 17];               // [qd][k2] exp(-2 pi i qd k2 / 64)
     // XCD-aware order: neighbouring receiver groups (which share 128-byte
     // lines of the input rows) run on one XCD at one time
     const int w = (blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
@@ -95,8 +97,8 @@ __global__ __launch_bounds__(kThreadsF) void ppf_fine_kernel(FineArgs a, Tw64 tw
     {
         const int il = tid / kPF, k = tid % kPF;
         const int i = min(i0 + il, N - 1);
-        lcomp[tid] = cmul(a.E[(int64_t)i * kPF + k], a.A[(int64_t)sb * N + i]);
-        if (tid < 64) ltw[tid] = tw64.w[((tid >> 4) * (tid & 15)) & 63];
+        lcomp[il * (kPF + 1) + k] = cmul(a.E[(int64_t)i * kPF + k], a.A[(int64_t)sb * N + i]);
+        if (tid < 64) ltw[(tid >> 4) * 17 + (tid & 15)] = tw64.w[((tid >> 4) * (tid & 15)) & 63];
     }
 
     // ---- FIR-phase roles: lane = il * 16 + ps * 4 + jh * 2 + comp
@@ -111,8 +113,10 @@ __global__ __launch_bounds__(kThreadsF) void ppf_fine_kernel(FineArgs a, Tw64 tw
     const float2 rtw_o = k1o == 0 ? tw_o : k1o == 1 ? make_float2(tw_o.y, -tw_o.x)
                        : k1o == 2 ? make_float2(-tw_o.x, -tw_o.y) : make_float2(-tw_o.y, tw_o.x);
     const float sgn = (k1o & 1) ? -1.0f : 1.0f;
-    // [spectrum][k1][p1 * 4 + receiver], bit 4 of the index flipped for odd k1
-    const int fir_w = k1o * kKSF + ((p1 * kNiF + il) ^ ((k1o & 1) << 4));
+    // [spectrum][k1][p1 * 4 + (receiver ^ k1)], bit 4 of the index flipped
+    // for odd k1: the 16 lanes of (branch group, k1) of one receiver, and the
+    // 32 of two receivers, write to distinct banks
+    const int fir_w = k1o * kKSF + ((p1 * kNiF + (il ^ k1o)) ^ ((k1o & 1) << 4));
 
     lds_barrier();
     const float4* tp0 = reinterpret_cast<const float4*>(ltaps + (p1 + 128 * jh) * kT);
@@ -136,17 +140,18 @@ __global__ __launch_bounds__(kThreadsF) void ppf_fine_kernel(FineArgs a, Tw64 tw
     // ---- FFT phase 1 roles: lane = k1 * 16 + qd * 4 + receiver, wave = spectrum
     const int il1 = lane & 3, qd1 = (lane >> 2) & 3, k1f = lane >> 4, q1 = wv;
     const int b1 = k1f & 1;
-    const float2* src1e = lds + q1 * kSSF + k1f * kKSF + 4 * qd1 + il1 + 16 * b1;   // r even
-    const float2* src1o = lds + q1 * kSSF + k1f * kKSF + 4 * qd1 + il1 - 16 * b1;   // r odd
+    const int il1s = il1 ^ k1f;
+    const float2* src1e = lds + q1 * kSSF + k1f * kKSF + 4 * qd1 + il1s + 16 * b1;   // r even
+    const float2* src1o = lds + q1 * kSSF + k1f * kKSF + 4 * qd1 + il1s - 16 * b1;   // r odd
     // exchange buffer [k2][spectrum][(k1 * 4 + qd) * 4 + receiver], the
     // (k1 * 4 + qd) index XOR spectrum % 8
     const int xw = q1 * 64 + (((k1f * 4 + qd1) * 4 + il1) ^ ((q1 & 7) << 2));
-    const float2* tw1 = ltw + qd1 * 16;
+    const float2* tw1 = ltw + qd1 * 17;
     // ---- FFT phase 2 roles: lane = k2lo * 32 + (spectrum % 8) * 4 + receiver
     const int il2 = lane & 3, ql2 = (lane >> 2) & 7, k2lo = lane >> 5;
     const int q2 = (wv & 1) * 8 + ql2, k2 = (wv >> 1) * 2 + k2lo;
     const float2* src2 = lds + k2 * kXS + q2 * 64 + il2;
-    const float2* comp2 = lcomp + il2 * kPF + 4 * k2;
+    const float2* comp2 = lcomp + il2 * (kPF + 1) + 4 * k2;
     const int rf = i0 + il2;
 
     int pf[kDepthF][2];

@@ -154,6 +154,22 @@ def bandpass_weights(n_fine: int = N_FINE, seed: int = 6) -> np.ndarray:
     return (1.0 / resp).astype(np.float32)
 
 
+def fine_requant_gain(cfg: Config, taps: np.ndarray, w: np.ndarray, ratio: int = FINE_RATIO,
+                      clip_sigmas: float = 4.0) -> float:
+    """Gain that maps the fine channeliser's per-component output sigma, in
+    its loudest output channel, to 127/clip_sigmas.
+
+    A fine channel of white input has sigma_in * sqrt(sum h^2) per component;
+    an output channel sums `ratio` of them, weighted by w (the delay phases
+    leave the power unchanged), so its variance carries sum_j w[4c+j]^2.
+    Analytic, from the generator parameters.
+    """
+    s2 = cfg.sigma_n ** 2 + sum(s * s for s in source_sigmas(cfg))
+    w2 = (w.astype(np.float64) ** 2).reshape(-1, ratio).sum(1).max()
+    sigma_z = math.sqrt(s2) * math.sqrt(float(np.sum(taps.astype(np.float64) ** 2))) * math.sqrt(w2)
+    return float(np.float32(127.0 / (clip_sigmas * sigma_z)))
+
+
 # --------------------------------------------------------------------------
 # array geometry and sky
 # --------------------------------------------------------------------------
