@@ -51,6 +51,10 @@ def _load():
     lib.orc_fine_channelise.argtypes = [_p, _i64, _i64, _i64, _p, _i64, _i64, _i64, _i64,
                                         C.c_double, C.c_double, C.c_double, _p, _i64, _p]
     lib.orc_fine_channelise.restype = C.c_int
+    lib.orc_spectrum_validity.argtypes = [_p, _i64, _i64, _i64, _i64, _i64, _i64, _i64, _i64, _p]
+    lib.orc_spectrum_validity.restype = None
+    lib.orc_validity_weights.argtypes = [_p, _i64, _i64, _i64, _p, _p]
+    lib.orc_validity_weights.restype = None
     _lib = lib
     return lib
 
@@ -202,6 +206,38 @@ def xcorr_int(z: np.ndarray, flags: Optional[np.ndarray] = None) -> Tuple[np.nda
     if rc != 0:
         raise OverflowError("integer visibility does not fit in int32")
     return V, W
+
+
+# --------------------------------------------------------------------------
+# lost packets and the weighting matrix (Sec. "CPU Data Collation";
+# Sec. "Calibration Pipeline", weighting)
+# --------------------------------------------------------------------------
+def spectrum_validity(pkt: np.ndarray, Q: int, P: int, T: int, S: int, antennas=None) -> np.ndarray:
+    """pkt uint8 [n_packets][Na] (nonzero = arrived), Q samples per packet ->
+    uint8 [Na'][S]: spectrum s valid iff samples s*P .. (s+T)*P-1 all arrived."""
+    pkt = _c(pkt, np.uint8)
+    n_pk, Na = pkt.shape
+    a0, a1 = (0, Na) if antennas is None else antennas
+    v = np.empty((a1 - a0, S), np.uint8)
+    _load().orc_spectrum_validity(_ptr(pkt), n_pk, Na, Q, P, T, S, a0, a1, _ptr(v))
+    return v
+
+
+def validity_weights(v: np.ndarray, S: int, flags: Optional[np.ndarray] = None) -> np.ndarray:
+    """v uint8 [Na][>=S] -> int32 [Nbl]: spectra s < S valid for both antennas."""
+    v = _c(v, np.uint8)
+    Na = v.shape[0]
+    W = np.empty(Na * (Na + 1) // 2, np.int32)
+    fl = None if flags is None else _c(flags, np.uint8)
+    _load().orc_validity_weights(_ptr(v), Na, v.shape[1], S, _ptr(fl), _ptr(W))
+    return W
+
+
+def zero_invalid(z: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """z [S][2*Na] (complex) with the samples of invalid spectra set to zero:
+    z'[s][2a+p] = z[s][2a+p] if v[a][s] else 0 (both polarisations)."""
+    keep = np.repeat(np.asarray(v, bool).T[:, :, None], 2, axis=2).reshape(z.shape[0], -1)
+    return np.where(keep, z, 0)
 
 
 # --------------------------------------------------------------------------

@@ -27,6 +27,11 @@
  *       L = || V - G M G^H ||_F^2,  G = diag(g)
  *       grad_a = dL/dRe g_a + i dL/dIm g_a
  *              = -2 sum_b [ R_ab conj(M_ab) + conj(R_ba) M_ba ] g_b
+ *   validity     (Sec. "CPU Data Collation": lost UDP packets and the
+ *                weighting matrix; Sec. "Calibration Pipeline", weighting):
+ *                spectrum s of antenna a is valid iff every input sample of
+ *                its FIR window, s*P .. (s+T)*P - 1, arrived; the weight of
+ *                a baseline is the number of spectra valid for both antennas
  */
 #include <math.h>
 #include <stdint.h>
@@ -398,4 +403,48 @@ int orc_fine_channelise(const int16_t *x, int64_t n_rows, int64_t row_stride, in
         }
     free(y); free(fr); free(fi);
     return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Validity of channelised spectra after lost packets (Sec. "CPU Data
+ * Collation": the correlator handles lost UDP packets and produces a
+ * weighting matrix with the visibilities).
+ *
+ * pkt[k * Na + a] != 0 when packet k of antenna a arrived; a packet carries
+ * Q consecutive input samples (sample n is in packet n / Q; samples past the
+ * last packet count as lost).  Spectrum s of a bank with P samples per
+ * spectrum and T taps reads samples s*P .. (s+T)*P - 1 and is valid iff all
+ * of them arrived.  Antennas a0 .. a1-1; v[(a - a0) * S + s] = 0 or 1.
+ * ------------------------------------------------------------------------- */
+void orc_spectrum_validity(const uint8_t *pkt, int64_t n_pk, int64_t Na, int64_t Q, int64_t P,
+                           int64_t T, int64_t S, int64_t a0, int64_t a1, uint8_t *v)
+{
+    int64_t a;
+#pragma omp parallel for schedule(static)
+    for (a = a0; a < a1; ++a)
+        for (int64_t s = 0; s < S; ++s) {
+            int ok = 1;
+            for (int64_t n = s * P; n < (s + T) * P && ok; ++n) {
+                const int64_t k = n / Q;
+                if (k >= n_pk || !pkt[k * Na + a]) ok = 0;
+            }
+            v[(a - a0) * S + s] = (uint8_t)ok;
+        }
+}
+
+/* Weighting matrix of one subband: W[bl(a,b)] = number of spectra s < S
+ * valid for both antennas (v[a * S_stride + s]), 0 when either antenna is
+ * flagged (flags may be NULL). */
+void orc_validity_weights(const uint8_t *v, int64_t Na, int64_t S_stride, int64_t S,
+                          const uint8_t *flags, int32_t *W)
+{
+    int64_t a;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (a = 0; a < Na; ++a)
+        for (int64_t b = 0; b <= a; ++b) {
+            int64_t n = 0;
+            if (!(flags && (flags[a] || flags[b])))
+                for (int64_t s = 0; s < S; ++s) n += v[a * S_stride + s] && v[b * S_stride + s];
+            W[a * (a + 1) / 2 + b] = (int32_t)n;
+        }
 }
