@@ -189,6 +189,54 @@ AFC_API int afc_correlate(const afc_dims* d, afc_dtype in_dtype, const void* z,
                           void* vis, int32_t* weights, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Lost packets and the weighting matrix (Sec. "CPU Data Collation": the
+ * correlator handles lost UDP packets from the stations and produces a
+ * weighting matrix along with the visibilities; Sec. "Calibration
+ * Pipeline", weighting: visibilities are re-weighted for the lost data).
+ *
+ * A spectrum s of antenna a is valid iff every input sample of its FIR
+ * window, samples s*Ps .. (s+T)*Ps - 1 (Ps = 64 for afc_channelise, 256 for
+ * afc_channelise_fine), arrived.  The masked chain is
+ *   channelise -> afc_validity -> afc_zero_invalid -> afc_correlate
+ *   -> afc_validity_weights [-> afc_normalise_visibilities]
+ * so that V_ab sums the spectra valid for both antennas (zeroed samples add
+ * exactly nothing) and W_ab counts them.
+ *
+ * afc_validity_words  uint32 words of the validity mask: B * ceil(S/32) * Na.
+ * afc_validity   packet_valid uint8 [B][n_packets][Na], nonzero = packet k
+ *                of antenna a arrived; a packet holds packet_samples
+ *                consecutive input samples (sample n is in packet
+ *                n / packet_samples; samples past the last packet count as
+ *                lost).  spec_valid out: uint32 [B][ceil(S/32)][Na], bit
+ *                s % 32 of word s / 32 set iff spectrum s is valid; bits of
+ *                s >= S are 0.
+ * afc_zero_invalid  sets to zero, in z (afc_channelise layout, type dt), the
+ *                samples of both receivers of antenna a, in every channel,
+ *                of each spectrum invalid for a.  Writes only those samples.
+ * afc_validity_weights  weights int32 [B][Nbl]: the number of spectra
+ *                s < S_b valid for both antennas (n_spectra_per_sb host
+ *                [B] or NULL = all S), 0 when either is flagged (flags
+ *                uint8 [B][Na] or NULL).  Use it in place of the weights of
+ *                afc_correlate.
+ * afc_normalise_visibilities  out float2 [B][P][Nbl][2][2] = vis / W per
+ *                baseline (0 where W = 0): the mean visibility per valid
+ *                spectrum.  vis is int2 for vis_dtype AFC_I8 (divided in
+ *                float64, rounded once) and float2 otherwise (one float32
+ *                division).  out may not alias vis.
+ * ------------------------------------------------------------------------- */
+AFC_API size_t afc_validity_words(const afc_dims* d);
+AFC_API int afc_validity(const afc_dims* d, const uint8_t* packet_valid, int32_t n_packets,
+                         int32_t packet_samples, int32_t samples_per_spectrum,
+                         uint32_t* spec_valid, hipStream_t stream);
+AFC_API int afc_zero_invalid(const afc_dims* d, afc_dtype dt, const uint32_t* spec_valid, void* z,
+                             hipStream_t stream);
+AFC_API int afc_validity_weights(const afc_dims* d, const uint32_t* spec_valid,
+                                 const int32_t* n_spectra_per_sb, const uint8_t* flags,
+                                 int32_t* weights, hipStream_t stream);
+AFC_API int afc_normalise_visibilities(const afc_dims* d, afc_dtype vis_dtype, const void* vis,
+                                       const int32_t* weights, void* out, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * afc_calibrate_grad -- gain-calibration loss and its gradient
  * (Sec. "Calibration Pipeline": per-channel amplitude and phase calibration
  * of XX and YY against a point-source sky model; least-squares reading).

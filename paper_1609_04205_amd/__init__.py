@@ -43,6 +43,12 @@ _lib.afc_visibility_bytes.argtypes = [C.POINTER(Dims)]
 _lib.afc_visibility_bytes.restype = _sz
 _lib.afc_channelise.argtypes = [C.POINTER(Dims), _vp, _vp, C.c_int, _f32, _vp, _vp]
 _lib.afc_correlate.argtypes = [C.POINTER(Dims), C.c_int, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.afc_validity_words.argtypes = [C.POINTER(Dims)]
+_lib.afc_validity_words.restype = _sz
+_lib.afc_validity.argtypes = [C.POINTER(Dims), _vp, _i32, _i32, _i32, _vp, _vp]
+_lib.afc_zero_invalid.argtypes = [C.POINTER(Dims), C.c_int, _vp, _vp, _vp]
+_lib.afc_validity_weights.argtypes = [C.POINTER(Dims), _vp, _vp, _vp, _vp, _vp]
+_lib.afc_normalise_visibilities.argtypes = [C.POINTER(Dims), C.c_int, _vp, _vp, _vp, _vp]
 _lib.afc_channelise_fine_workspace_bytes.argtypes = [C.POINTER(Dims)]
 _lib.afc_channelise_fine_workspace_bytes.restype = _sz
 _lib.afc_channelise_fine.argtypes = [C.POINTER(Dims), _vp, _vp, _vp, _vp, C.POINTER(C.c_double), C.c_double,
@@ -60,6 +66,8 @@ _lib.afc_plan_destroy.restype = None
 
 EXPORTS = ["afc_channelised_bytes", "afc_visibility_bytes", "afc_channelise",
            "afc_channelise_fine_workspace_bytes", "afc_channelise_fine", "afc_correlate",
+           "afc_validity_words", "afc_validity", "afc_zero_invalid", "afc_validity_weights",
+           "afc_normalise_visibilities",
            "afc_calibrate_workspace_bytes", "afc_calibrate_grad", "afc_plan_create",
            "afc_plan_workspace_bytes", "afc_plan_launch", "afc_plan_info", "afc_plan_destroy",
            "afc_last_error"]
@@ -178,6 +186,85 @@ def channelise_fine(x, taps, n_spectra: int, delays, bandpass, center_hz: Sequen
     _check(_lib.afc_channelise_fine(C.byref(d), _ptr(x), _ptr(taps), _ptr(delays), _ptr(bandpass), nu,
                                     float(subband_hz), DTYPES[out_dtype], float(gain), _ptr(workspace),
                                     _ptr(out), _stream(x.device)), "afc_channelise_fine")
+    return out
+
+
+def validity_shape(n_subbands, n_spectra, n_antennas):
+    return (n_subbands, (n_spectra + 31) // 32, n_antennas)
+
+
+def validity(packet_valid, n_spectra: int, packet_samples: int, samples_per_spectrum: int = N_CHANNELS,
+             out=None):
+    """packet_valid uint8 [B][n_packets][Na] -> spectrum validity bits, int32
+    [B][ceil(S/32)][Na] (bit s % 32 of word s // 32 = spectrum s valid)."""
+    torch = _torch()
+    _require(packet_valid, torch.uint8, "packet_valid")
+    B, n_pk, Na = packet_valid.shape
+    d = dims(Na, B, n_spectra)
+    shape = validity_shape(B, n_spectra, Na)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.int32, device=packet_valid.device)
+    _require(out, torch.int32, "out")
+    if tuple(out.shape) != shape:
+        raise AfcError(f"out shape {tuple(out.shape)} != {shape}")
+    _check(_lib.afc_validity(C.byref(d), _ptr(packet_valid), int(n_pk), int(packet_samples),
+                             int(samples_per_spectrum), _ptr(out), _stream(packet_valid.device)), "afc_validity")
+    return out
+
+
+def zero_invalid(z, spec_valid, n_spectra: int):
+    """Zero, in place, the samples of z [B][64][Sb][N][8][2] whose spectrum is
+    invalid for their antenna."""
+    torch = _torch()
+    dt = {torch.float32: "f32", torch.float16: "f16", torch.int8: "i8"}[z.dtype]
+    _require(z, z.dtype, "z")
+    _require(spec_valid, torch.int32, "spec_valid")
+    B, N = z.shape[0], z.shape[3]
+    if tuple(spec_valid.shape) != validity_shape(B, n_spectra, N // 2):
+        raise AfcError("spec_valid does not match z")
+    d = dims(N // 2, B, n_spectra)
+    _check(_lib.afc_zero_invalid(C.byref(d), DTYPES[dt], _ptr(spec_valid), _ptr(z), _stream(z.device)),
+           "afc_zero_invalid")
+    return z
+
+
+def validity_weights(spec_valid, n_spectra: int, n_spectra_per_sb: Optional[Sequence[int]] = None, flags=None,
+                     out=None):
+    """Weighting matrix int32 [B][Nbl]: spectra valid for both antennas of each baseline."""
+    torch = _torch()
+    _require(spec_valid, torch.int32, "spec_valid")
+    B, _, Na = spec_valid.shape
+    d = dims(Na, B, n_spectra)
+    if out is None:
+        out = torch.empty((B, Na * (Na + 1) // 2), dtype=torch.int32, device=spec_valid.device)
+    _require(out, torch.int32, "out")
+    if flags is not None:
+        _require(flags, torch.uint8, "flags")
+    sp = None
+    if n_spectra_per_sb is not None:
+        arr = (C.c_int32 * B)(*[int(v) for v in n_spectra_per_sb])
+        sp = C.cast(arr, C.c_void_p)
+    _check(_lib.afc_validity_weights(C.byref(d), _ptr(spec_valid), sp, _ptr(flags), _ptr(out),
+                                     _stream(spec_valid.device)), "afc_validity_weights")
+    return out
+
+
+def normalise_visibilities(vis, weights, out=None):
+    """vis [B][64][Nbl][2][2][2] (int32 or float32) / weights [B][Nbl] -> float32, 0 where W = 0."""
+    torch = _torch()
+    _require(weights, torch.int32, "weights")
+    _require(vis, vis.dtype, "vis")
+    dt = "i8" if vis.dtype == torch.int32 else "f32"
+    B, P, nbl = vis.shape[0], vis.shape[1], vis.shape[2]
+    Na = int(round(((8 * nbl + 1) ** 0.5 - 1) / 2))
+    if P != N_CHANNELS or Na * (Na + 1) // 2 != nbl or tuple(weights.shape) != (B, nbl):
+        raise AfcError("vis / weights shapes do not match")
+    if out is None:
+        out = torch.empty(vis.shape, dtype=torch.float32, device=vis.device)
+    _require(out, torch.float32, "out")
+    d = dims(Na, B, 1)
+    _check(_lib.afc_normalise_visibilities(C.byref(d), DTYPES[dt], _ptr(vis), _ptr(weights), _ptr(out),
+                                           _stream(vis.device)), "afc_normalise_visibilities")
     return out
 
 

@@ -166,6 +166,68 @@ AFC_API int afc_channelise_fine(const afc_dims* d, const int16_t* x, const float
     return AFC_OK;
 }
 
+AFC_API size_t afc_validity_words(const afc_dims* d) {
+    if (check_dims(d) != AFC_OK) return 0;
+    return (size_t)d->n_subbands * ceil_div(d->n_spectra, 32) * d->n_antennas;
+}
+
+AFC_API int afc_validity(const afc_dims* d, const uint8_t* packet_valid, int32_t n_packets, int32_t packet_samples,
+                         int32_t samples_per_spectrum, uint32_t* spec_valid, hipStream_t stream) {
+    g_err.clear();
+    int rc = check_dims(d);
+    if (rc != AFC_OK) return rc;
+    if (!packet_valid || !spec_valid) return fail(AFC_ERR_INVALID, "NULL pointer (packet_valid or spec_valid)");
+    if (n_packets < 1 || packet_samples < 1)
+        return fail(AFC_ERR_INVALID, "n_packets = %d and packet_samples = %d must be >= 1", n_packets, packet_samples);
+    if (samples_per_spectrum != kP && samples_per_spectrum != kPFine)
+        return fail(AFC_ERR_INVALID, "samples_per_spectrum = %d (64 or 256)", samples_per_spectrum);
+    hipError_t e = launch_validity(packet_valid, spec_valid, d->n_subbands, d->n_antennas, d->n_spectra, n_packets,
+                                   packet_samples, samples_per_spectrum, stream);
+    if (e != hipSuccess) return hip_fail(e, "validity launch");
+    return AFC_OK;
+}
+
+AFC_API int afc_zero_invalid(const afc_dims* d, afc_dtype dt, const uint32_t* spec_valid, void* z,
+                             hipStream_t stream) {
+    g_err.clear();
+    int rc = check_dims(d);
+    if (rc != AFC_OK) return rc;
+    if (!spec_valid || !z) return fail(AFC_ERR_INVALID, "NULL pointer (spec_valid or z)");
+    if (!dtype_ok(dt)) return fail(AFC_ERR_INVALID, "unknown dtype %d", (int)dt);
+    hipError_t e = launch_zero_invalid(spec_valid, z, dt, d->n_subbands, d->n_antennas, d->n_spectra, stream);
+    if (e != hipSuccess) return hip_fail(e, "zero-invalid launch");
+    return AFC_OK;
+}
+
+AFC_API int afc_validity_weights(const afc_dims* d, const uint32_t* spec_valid, const int32_t* n_spectra_per_sb,
+                                 const uint8_t* flags, int32_t* weights, hipStream_t stream) {
+    g_err.clear();
+    int rc = check_dims(d);
+    if (rc != AFC_OK) return rc;
+    if (!spec_valid || !weights) return fail(AFC_ERR_INVALID, "NULL pointer (spec_valid or weights)");
+    if (n_spectra_per_sb)
+        for (int b = 0; b < d->n_subbands; ++b)
+            if (n_spectra_per_sb[b] < 1 || n_spectra_per_sb[b] > d->n_spectra)
+                return fail(AFC_ERR_INVALID, "n_spectra_per_sb[%d] = %d outside 1..%d", b, n_spectra_per_sb[b],
+                            d->n_spectra);
+    hipError_t e = launch_validity_weights(spec_valid, flags, weights, d->n_subbands, d->n_antennas, d->n_spectra,
+                                           n_spectra_per_sb, stream);
+    if (e != hipSuccess) return hip_fail(e, "validity-weights launch");
+    return AFC_OK;
+}
+
+AFC_API int afc_normalise_visibilities(const afc_dims* d, afc_dtype vis_dtype, const void* vis,
+                                       const int32_t* weights, void* out, hipStream_t stream) {
+    g_err.clear();
+    int rc = check_dims(d);
+    if (rc != AFC_OK) return rc;
+    if (!vis || !weights || !out) return fail(AFC_ERR_INVALID, "NULL pointer (vis, weights or out)");
+    if (!dtype_ok(vis_dtype)) return fail(AFC_ERR_INVALID, "unknown vis_dtype %d", (int)vis_dtype);
+    hipError_t e = launch_normalise(vis, vis_dtype == AFC_I8, weights, out, d->n_subbands, d->n_antennas, stream);
+    if (e != hipSuccess) return hip_fail(e, "normalise launch");
+    return AFC_OK;
+}
+
 AFC_API int afc_correlate(const afc_dims* d, afc_dtype in_dtype, const void* z, const int32_t* n_spectra_per_sb,
                           const uint8_t* flags, void* vis, int32_t* weights, hipStream_t stream) {
     g_err.clear();

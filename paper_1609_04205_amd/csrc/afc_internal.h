@@ -112,6 +112,16 @@ int xengine_list_grid(const XcdRanges& ranges);
 hipError_t launch_fill_scratch(void* p, size_t bytes, hipStream_t stream);
 int xengine_tile(afc_dtype dt);
 
+// ---------------------------------------------------------------- validity
+// spectrum validity bits [B][ceil(S/32)][Na] from packet flags [B][n_pk][Na]
+hipError_t launch_validity(const uint8_t* pkt, uint32_t* v, int B, int Na, int S, int64_t n_pk, int Q, int Ps,
+                           hipStream_t stream);
+hipError_t launch_zero_invalid(const uint32_t* v, void* z, afc_dtype dt, int B, int Na, int S, hipStream_t stream);
+hipError_t launch_validity_weights(const uint32_t* v, const uint8_t* flags, int32_t* W, int B, int Na, int S,
+                                   const int32_t* S_host, hipStream_t stream);
+hipError_t launch_normalise(const void* vis, bool is_int, const int32_t* W, void* out, int B, int Na,
+                            hipStream_t stream);
+
 // ---------------------------------------------------------------- calibration
 size_t cal_workspace_bytes(int Na, int P);
 hipError_t launch_calibrate(int Na, int P, const float2* V, const float2* M, const float2* g,

@@ -171,6 +171,41 @@ def fine_requant_gain(cfg: Config, taps: np.ndarray, w: np.ndarray, ratio: int =
 
 
 # --------------------------------------------------------------------------
+# lost packets (per station, per subband)
+# --------------------------------------------------------------------------
+PACKET_SAMPLES = 16           # time samples per station packet
+ANTENNAS_PER_STATION = 48
+
+
+def packet_loss(n_subbands: int, n_antennas: int, n_rows: int, seed: int, rate: float = 1e-3,
+                mean_burst: float = 8.0, dead: Sequence[tuple] = (),
+                packet_samples: int = PACKET_SAMPLES) -> np.ndarray:
+    """Packet arrival flags uint8 [B][n_packets][Na] (1 = arrived).
+
+    A station's packets carry all of its 48 antennas, so loss is drawn per
+    (subband, station): bursts of lost packets starting with probability
+    `rate / mean_burst` per packet, lengths geometric with mean
+    `mean_burst` (about `rate` of the packets lost); `dead` lists
+    (subband, station) pairs whose packets are all lost.
+    """
+    rng = np.random.default_rng([seed, 808])
+    n_pk = -(-n_rows // packet_samples)
+    n_st = -(-n_antennas // ANTENNAS_PER_STATION)
+    ok = np.ones((n_subbands, n_pk, n_st), np.uint8)
+    p_start = rate / mean_burst
+    for b in range(n_subbands):
+        for st in range(n_st):
+            starts = np.flatnonzero(rng.random(n_pk) < p_start)
+            lens = rng.geometric(1.0 / mean_burst, size=starts.size)
+            for s0, ln in zip(starts, lens):
+                ok[b, s0:s0 + ln, st] = 0
+    for b, st in dead:
+        ok[b, :, st] = 0
+    ant_station = np.arange(n_antennas) // ANTENNAS_PER_STATION
+    return np.ascontiguousarray(ok[:, :, ant_station])
+
+
+# --------------------------------------------------------------------------
 # array geometry and sky
 # --------------------------------------------------------------------------
 def _disc(rng: np.random.Generator, n: int, radius: float) -> np.ndarray:
