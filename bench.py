@@ -10,7 +10,9 @@ Prints ONE JSON line.  `value` is the whole step's useful complex
 multiply-accumulates per second (TCMAC/s).  Beside it: per-kernel times from
 HIP events on the launch stream, the X-engine's fraction of the int8 MFMA
 peak (and the MACs it issues including diagonal-tile and padding waste), the
-PPF's algorithmic GB/s, the real-time factor, the fp32 path for the
+PPF's algorithmic GB/s, the real-time factor, the lost-packet path on the
+same step (validity masks, zeroing, weighting matrix, normalisation), the
+fp32 path for the
 int8-vs-fp32 comparison, the host-to-device rate of the int16 input (not in
 the step), the whole 32-subband band of the same shape, the paper's
 256-channel configuration (fused delay/bandpass compensation and 4:1 channel
@@ -208,6 +210,40 @@ def main():
     log(f"int8 step {ms_step:.3f} ms (ppf {ppf_ms:.3f}, xengine {xe_ms:.3f})")
 
     if not args.no_extras:
+        # ---- lost packets on the same step: validity masks from packet flags
+        # (0.1% of the packets lost in bursts, one station dead in one
+        # subband), zeroing of invalid spectra, the weighting matrix, and the
+        # visibilities divided by their weights
+        pkt_np = W.packet_loss(B, Na, L, seed=cfg.seed, dead=[(5, 7)])
+        pkt = torch.from_numpy(pkt_np).to(dev)
+        bits = torch.empty(afc.validity_shape(B, S, Na), dtype=torch.int32, device=dev)
+        visn = torch.empty(vis.shape, dtype=torch.float32, device=dev)
+        tv = Timer(torch)
+        for it in range(4):
+            tm = tv if it > 0 else None
+            marks = []
+            for name, fn in (("validity", lambda: afc.validity(pkt, S, W.PACKET_SAMPLES, out=bits)),
+                             ("zero", lambda: afc.zero_invalid(z8, bits, S)),
+                             ("weights", lambda: afc.validity_weights(bits, S, out=wts)),
+                             ("normalise", lambda: afc.normalise_visibilities(vis, wts, out=visn))):
+                e = tm.rec(name) if tm else None
+                fn()
+                if e is not None:
+                    e.record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        ms_v = {k: tv.ms(k) for k in ("validity", "zero", "weights", "normalise")}
+        norm_bytes = 2.0 * vis.numel() * 4 + wts.numel() * 4
+        out["lost_packets"] = {"packets_lost_fraction": round(1.0 - float(pkt_np.mean()), 5),
+                               "validity_ms": round(ms_v["validity"], 4), "zero_invalid_ms": round(ms_v["zero"], 4),
+                               "weights_ms": round(ms_v["weights"], 4),
+                               "masked_step_overhead": round((ms_v["validity"] + ms_v["zero"] + ms_v["weights"])
+                                                             / ms_step, 4),
+                               "normalise_ms": round(ms_v["normalise"], 3),
+                               "normalise_gbs": round(norm_bytes / (ms_v["normalise"] * 1e-3) / 1e9, 1)}
+        log(f"lost packets: validity {ms_v['validity']:.3f} zero {ms_v['zero']:.3f} weights {ms_v['weights']:.3f} "
+            f"normalise {ms_v['normalise']:.3f} ms")
+        del pkt, bits, visn
+
         # ---- fp32 path on the same input: int8 vs fp32
         del z8
         z32 = torch.empty(afc.channelised_shape(B, S, N), dtype=torch.float32, device=dev)
