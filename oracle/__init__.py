@@ -260,3 +260,100 @@ def cal_loss_grad(V: np.ndarray, M: np.ndarray, g: np.ndarray,
     if rc != 0:
         raise MemoryError("orc_cal_loss_grad")
     return loss, (None if grad is None else _to_complex(grad))
+
+
+# --------------------------------------------------------------------------
+# calibration solver and flagging (Sec. "Calibration Pipeline")
+# --------------------------------------------------------------------------
+def _full(T_lower: np.ndarray, Na: int, pol: int) -> np.ndarray:
+    """Hermitian Na x Na matrix (complex128) of polarisation pol (0 = XX,
+    1 = YY) from a lower triangle float [Nbl][2][2][2]: entry (a, b), a >= b,
+    at bl = a(a+1)/2 + b; the upper triangle is the conjugate."""
+    t = T_lower[:, pol, pol, 0].astype(np.float64) + 1j * T_lower[:, pol, pol, 1].astype(np.float64)
+    F = np.zeros((Na, Na), np.complex128)
+    a, b = np.tril_indices(Na)
+    F[a, b] = t
+    F[b, a] = np.conj(t)
+    return F
+
+
+def cal_solve(V: np.ndarray, M: np.ndarray, g0: np.ndarray, n_iter: int) -> np.ndarray:
+    """Per-channel complex gains minimising L = ||V - G M G^H||_F^2 for XX and
+    YY (Sec. "Calibration Pipeline": amplitude and phase calibration per
+    channel against a point-source model; least-squares reading).
+
+    Alternating least squares with averaging (the StEFCal iteration of
+    Salvini & Wijnholds, 2014): with every other gain fixed, the best g_a is
+    sum_b V_ab conj(z_ab) / sum_b |z_ab|^2, z_ab = M_ab conj(g_b); all gains
+    are updated from the previous iterate at once, and on every second
+    iteration the new iterate is averaged with the previous one.  After
+    n_iter iterations the common phase is removed so that g_0 is real and
+    positive.
+
+    V, M float32 [P][Nbl][2][2][2]; g0 complex [P][Na][2] -> complex128 [P][Na][2].
+    """
+    P, nbl = V.shape[0], V.shape[1]
+    Na = int(round((np.sqrt(8 * nbl + 1) - 1) / 2))
+    out = np.empty((P, Na, 2), np.complex128)
+    for ch in range(P):
+        for pol in range(2):
+            Vf = _full(V[ch], Na, pol)
+            Mf = _full(M[ch], Na, pol)
+            g = np.asarray(g0[ch, :, pol], np.complex128).copy()
+            for it in range(1, n_iter + 1):
+                z = Mf * np.conj(g)[None, :]
+                num = (Vf * np.conj(z)).sum(axis=1)
+                den = (np.abs(z) ** 2).sum(axis=1)
+                g_new = np.where(den > 0, num / np.where(den > 0, den, 1.0), g)
+                if it % 2 == 0:
+                    g_new = 0.5 * (g_new + g)
+                g = g_new
+            if abs(g[0]) > 0:
+                g = g * (np.conj(g[0]) / abs(g[0]))
+            out[ch, :, pol] = g
+    return out
+
+
+def sigma_clip(V: np.ndarray, k: float) -> np.ndarray:
+    """Flags uint8 [P][Nbl][2] (XX, YY) of the real-time flagger (Sec.
+    "Calibration Pipeline", flagging): sigma clipping of visibility
+    amplitudes against the locally computed RMS, first across the
+    visibilities of each channel, then across the channels of each
+    visibility.
+
+    Stage 1, per channel and polarisation: RMS^2 = mean |V|^2 over the
+    cross-correlations; flag those with |V| > k RMS.  Stage 2, per
+    cross-correlation and polarisation: RMS^2 = mean |V|^2 over the channels
+    not flagged in stage 1; flag the channels with |V| > k RMS.
+    Autocorrelations are neither used nor flagged.  V float32
+    [P][Nbl][2][2][2].
+    """
+    P, nbl = V.shape[0], V.shape[1]
+    Na = int(round((np.sqrt(8 * nbl + 1) - 1) / 2))
+    a, b = np.tril_indices(Na)
+    cross = a != b
+    flags = np.zeros((P, nbl, 2), np.uint8)
+    k2 = float(k) * float(k)
+    for pol in range(2):
+        re = V[:, :, pol, pol, 0].astype(np.float64)
+        im = V[:, :, pol, pol, 1].astype(np.float64)
+        a2 = re * re + im * im                                     # [P][Nbl]
+        for ch in range(P):
+            m = a2[ch, cross].mean()
+            flags[ch, cross & (a2[ch] > k2 * m), pol] = 1
+        for bl in np.flatnonzero(cross):
+            keep = flags[:, bl, pol] == 0
+            if not keep.any():
+                continue
+            m = a2[keep, bl].mean()
+            flags[:, bl, pol] |= (a2[:, bl] > k2 * m).astype(np.uint8)
+    return flags
+
+
+def apply_vis_flags(T: np.ndarray, flags: np.ndarray) -> np.ndarray:
+    """Copy of T float [P][Nbl][2][2][2] with the flagged XX / YY entries set
+    to zero (a zeroed visibility and model drop out of the loss)."""
+    T = np.array(T, copy=True)
+    for pol in range(2):
+        T[:, :, pol, pol, :] *= (flags[:, :, pol] == 0)[:, :, None]
+    return T
