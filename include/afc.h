@@ -264,6 +264,57 @@ AFC_API int afc_calibrate_grad(int32_t n_antennas, int32_t n_channels, const voi
                                void* workspace, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * afc_calibrate_solve -- per-channel gains for XX and YY (Sec. "Calibration
+ * Pipeline": amplitude and phase calibration at the channel level against
+ * a point-source model), minimising the afc_calibrate_grad loss.
+ *
+ * n_iter iterations, every gain at once from the previous iterate:
+ *   g_a <- g_a - grad_a / (4 D_a),   D_a = sum_b |M_ab|^2 |g_b|^2
+ * with grad the afc_calibrate_grad gradient; since grad_a = -4 (sum_b V_ab
+ * conj(z_ab) - g_a D_a), z_ab = M_ab conj(g_b), this is the least-squares
+ * optimum of each g_a with the others fixed (the StEFCal iteration of
+ * Salvini & Wijnholds, 2014).  On every second iteration the new iterate is
+ * averaged with the previous one.  Gains with D_a = 0 stay unchanged.
+ * Finally each (channel, polarisation) is rotated so that g_0 is real and
+ * positive (the loss is blind to a common phase).
+ *
+ * V, M     as afc_calibrate_grad; flagged entries may be zeroed first
+ *          (afc_apply_vis_flags): a zero V_ab with a zero M_ab drops out.
+ * g        float2 [P][Na][2]: initial gains in, solution out.
+ * loss     double [P][2] of the solution, or NULL.
+ * workspace  afc_calibrate_solve_workspace_bytes(Na, P) bytes.
+ * Limits: n_antennas <= 4096, 0 <= n_iter <= 100000.
+ * ------------------------------------------------------------------------- */
+AFC_API size_t afc_calibrate_solve_workspace_bytes(int32_t n_antennas, int32_t n_channels);
+AFC_API int afc_calibrate_solve(int32_t n_antennas, int32_t n_channels, const void* V,
+                                const void* M, void* g, int32_t n_iter, double* loss,
+                                void* workspace, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * afc_sigma_clip -- real-time flagging (Sec. "Calibration Pipeline",
+ * flagging: sigma clipping of visibility amplitudes against a threshold
+ * above the locally computed RMS, first across the visibilities within a
+ * channel, then across the channels of every visibility), on XX and YY:
+ *   stage 1, per (channel, pol): RMS^2 = mean |V_ab|^2 over a != b;
+ *            flag |V_ab| > threshold * RMS
+ *   stage 2, per (baseline, pol): RMS^2 = mean |V_ab|^2 over the channels
+ *            not flagged in stage 1; flag |V_ab| > threshold * RMS
+ * Autocorrelations are neither used nor flagged.  |V|^2 in float64; sums in
+ * a fixed order (reproducible).
+ * V          float2 [P][Nbl][2][2] (the afc_correlate / afc_normalise layout).
+ * vis_flags  uint8 [P][Nbl][2] out (XX, YY): 1 = flagged.
+ * workspace  afc_sigma_clip_workspace_bytes(Na, P) bytes.
+ *
+ * afc_apply_vis_flags sets the flagged XX / YY entries of V and of M (either
+ * may be NULL) to zero, in place.
+ * ------------------------------------------------------------------------- */
+AFC_API size_t afc_sigma_clip_workspace_bytes(int32_t n_antennas, int32_t n_channels);
+AFC_API int afc_sigma_clip(int32_t n_antennas, int32_t n_channels, const void* V, float threshold,
+                           uint8_t* vis_flags, void* workspace, hipStream_t stream);
+AFC_API int afc_apply_vis_flags(int32_t n_antennas, int32_t n_channels, const uint8_t* vis_flags,
+                                void* V, void* M, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Batching form (Sec. "GPU Processing": each subband is an independent unit
  * of work; the paper hands subbands to free GPUs one by one, here all of them
  * go into one channeliser launch and one correlator launch per family of

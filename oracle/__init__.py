@@ -341,12 +341,11 @@ def sigma_clip(V: np.ndarray, k: float) -> np.ndarray:
         for ch in range(P):
             m = a2[ch, cross].mean()
             flags[ch, cross & (a2[ch] > k2 * m), pol] = 1
-        for bl in np.flatnonzero(cross):
-            keep = flags[:, bl, pol] == 0
-            if not keep.any():
-                continue
-            m = a2[keep, bl].mean()
-            flags[:, bl, pol] |= (a2[:, bl] > k2 * m).astype(np.uint8)
+        keep = flags[:, :, pol] == 0                               # [P][Nbl]
+        n = keep.sum(axis=0)
+        m = np.where(keep, a2, 0.0).sum(axis=0) / np.maximum(n, 1)   # per baseline
+        hit = (a2 > k2 * m[None, :]) & (cross & (n > 0))[None, :]
+        flags[:, :, pol] |= hit.astype(np.uint8)
     return flags
 
 

@@ -56,6 +56,13 @@ _lib.afc_channelise_fine.argtypes = [C.POINTER(Dims), _vp, _vp, _vp, _vp, C.POIN
 _lib.afc_calibrate_workspace_bytes.argtypes = [_i32, _i32]
 _lib.afc_calibrate_workspace_bytes.restype = _sz
 _lib.afc_calibrate_grad.argtypes = [_i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.afc_calibrate_solve_workspace_bytes.argtypes = [_i32, _i32]
+_lib.afc_calibrate_solve_workspace_bytes.restype = _sz
+_lib.afc_calibrate_solve.argtypes = [_i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp]
+_lib.afc_sigma_clip_workspace_bytes.argtypes = [_i32, _i32]
+_lib.afc_sigma_clip_workspace_bytes.restype = _sz
+_lib.afc_sigma_clip.argtypes = [_i32, _i32, _vp, _f32, _vp, _vp, _vp]
+_lib.afc_apply_vis_flags.argtypes = [_i32, _i32, _vp, _vp, _vp, _vp]
 _lib.afc_plan_create.argtypes = [C.POINTER(Dims), _vp, _vp, C.c_char_p, C.POINTER(_vp)]
 _lib.afc_plan_workspace_bytes.argtypes = [_vp]
 _lib.afc_plan_workspace_bytes.restype = _sz
@@ -67,7 +74,8 @@ _lib.afc_plan_destroy.restype = None
 EXPORTS = ["afc_channelised_bytes", "afc_visibility_bytes", "afc_channelise",
            "afc_channelise_fine_workspace_bytes", "afc_channelise_fine", "afc_correlate",
            "afc_validity_words", "afc_validity", "afc_zero_invalid", "afc_validity_weights",
-           "afc_normalise_visibilities",
+           "afc_normalise_visibilities", "afc_calibrate_solve_workspace_bytes", "afc_calibrate_solve",
+           "afc_sigma_clip_workspace_bytes", "afc_sigma_clip", "afc_apply_vis_flags",
            "afc_calibrate_workspace_bytes", "afc_calibrate_grad", "afc_plan_create",
            "afc_plan_workspace_bytes", "afc_plan_launch", "afc_plan_info", "afc_plan_destroy",
            "afc_last_error"]
@@ -324,6 +332,60 @@ def calibrate_grad(V, M, g, want_grad: bool = True, workspace=None):
     _check(_lib.afc_calibrate_grad(Na, P, _ptr(V), _ptr(M), _ptr(g), _ptr(loss), _ptr(grad), _ptr(workspace),
                                    _stream(V.device)), "afc_calibrate_grad")
     return loss, grad
+
+
+def calibrate_solve(V, M, g, n_iter: int = 40, want_loss: bool = True, workspace=None):
+    """Gains minimising ||V - G M G^H||_F^2 per (channel, XX/YY): g float32
+    [P][Na][2][2] is updated in place (initial gains in, phase-referenced
+    solution out).  Returns the loss float64 [P][2] of the solution (or None)."""
+    torch = _torch()
+    for t, n in ((V, "V"), (M, "M"), (g, "g")):
+        _require(t, torch.float32, n)
+    P, Na = g.shape[0], g.shape[1]
+    nbl = Na * (Na + 1) // 2
+    if tuple(V.shape) != (P, nbl, 2, 2, 2) or tuple(M.shape) != tuple(V.shape) or tuple(g.shape) != (P, Na, 2, 2):
+        raise AfcError("calibrate_solve: V, M must be [P][Nbl][2][2][2] and g [P][Na][2][2]")
+    loss = torch.empty((P, 2), dtype=torch.float64, device=V.device) if want_loss else None
+    wsb = _lib.afc_calibrate_solve_workspace_bytes(Na, P)
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=V.device)
+    _check(_lib.afc_calibrate_solve(Na, P, _ptr(V), _ptr(M), _ptr(g), int(n_iter), _ptr(loss), _ptr(workspace),
+                                    _stream(V.device)), "afc_calibrate_solve")
+    return loss
+
+
+def sigma_clip(V, threshold: float = 5.0, out=None, workspace=None):
+    """Two-stage sigma clipping of XX / YY: V float32 [P][Nbl][2][2][2] -> uint8 flags [P][Nbl][2]."""
+    torch = _torch()
+    _require(V, torch.float32, "V")
+    P, nbl = V.shape[0], V.shape[1]
+    Na = int(round(((8 * nbl + 1) ** 0.5 - 1) / 2))
+    if Na * (Na + 1) // 2 != nbl or tuple(V.shape[2:]) != (2, 2, 2):
+        raise AfcError("sigma_clip: V must be [P][Nbl][2][2][2]")
+    if out is None:
+        out = torch.empty((P, nbl, 2), dtype=torch.uint8, device=V.device)
+    _require(out, torch.uint8, "out")
+    wsb = _lib.afc_sigma_clip_workspace_bytes(Na, P)
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=V.device)
+    _check(_lib.afc_sigma_clip(Na, P, _ptr(V), float(threshold), _ptr(out), _ptr(workspace), _stream(V.device)),
+           "afc_sigma_clip")
+    return out
+
+
+def apply_vis_flags(flags, V=None, M=None):
+    """Zero, in place, the flagged XX / YY entries of V and / or M."""
+    torch = _torch()
+    _require(flags, torch.uint8, "flags")
+    P, nbl = flags.shape[0], flags.shape[1]
+    Na = int(round(((8 * nbl + 1) ** 0.5 - 1) / 2))
+    for t, n in ((V, "V"), (M, "M")):
+        if t is not None:
+            _require(t, torch.float32, n)
+            if tuple(t.shape) != (P, nbl, 2, 2, 2):
+                raise AfcError(f"apply_vis_flags: {n} does not match the flags")
+    _check(_lib.afc_apply_vis_flags(Na, P, _ptr(flags), _ptr(V), _ptr(M), _stream(flags.device)),
+           "afc_apply_vis_flags")
 
 
 def _make_cal_loss():

@@ -288,6 +288,59 @@ AFC_API int afc_calibrate_grad(int32_t n_antennas, int32_t n_channels, const voi
     return AFC_OK;
 }
 
+AFC_API size_t afc_calibrate_solve_workspace_bytes(int32_t n_antennas, int32_t n_channels) {
+    if (n_antennas < 1 || n_antennas > 4096 || n_channels < 1 || n_channels > 65535) return 0;
+    return cal_solve_workspace_bytes(n_antennas, n_channels);
+}
+
+AFC_API int afc_calibrate_solve(int32_t n_antennas, int32_t n_channels, const void* V, const void* M, void* g,
+                                int32_t n_iter, double* loss, void* workspace, hipStream_t stream) {
+    g_err.clear();
+    if (n_antennas < 1 || n_antennas > 4096) return fail(AFC_ERR_INVALID, "n_antennas = %d outside 1..4096", n_antennas);
+    if (n_channels < 1 || n_channels > 65535) return fail(AFC_ERR_INVALID, "n_channels = %d outside 1..65535", n_channels);
+    if (n_iter < 0 || n_iter > 100000) return fail(AFC_ERR_INVALID, "n_iter = %d outside 0..100000", n_iter);
+    if (!V || !M || !g) return fail(AFC_ERR_INVALID, "NULL pointer (V, M or g)");
+    if (!workspace) return fail(AFC_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)",
+                                cal_solve_workspace_bytes(n_antennas, n_channels));
+    hipError_t e = launch_calibrate_solve(n_antennas, n_channels, reinterpret_cast<const float2*>(V),
+                                          reinterpret_cast<const float2*>(M), reinterpret_cast<float2*>(g), n_iter,
+                                          loss, workspace, stream);
+    if (e != hipSuccess) return hip_fail(e, "calibration solver launch");
+    return AFC_OK;
+}
+
+AFC_API size_t afc_sigma_clip_workspace_bytes(int32_t n_antennas, int32_t n_channels) {
+    if (n_antennas < 1 || n_antennas > 4096 || n_channels < 1 || n_channels > 65535) return 0;
+    return sigma_clip_workspace_bytes(n_antennas, n_channels);
+}
+
+AFC_API int afc_sigma_clip(int32_t n_antennas, int32_t n_channels, const void* V, float threshold,
+                           uint8_t* vis_flags, void* workspace, hipStream_t stream) {
+    g_err.clear();
+    if (n_antennas < 1 || n_antennas > 4096) return fail(AFC_ERR_INVALID, "n_antennas = %d outside 1..4096", n_antennas);
+    if (n_channels < 1 || n_channels > 65535) return fail(AFC_ERR_INVALID, "n_channels = %d outside 1..65535", n_channels);
+    if (!V || !vis_flags) return fail(AFC_ERR_INVALID, "NULL pointer (V or vis_flags)");
+    if (!(std::isfinite(threshold) && threshold > 0.0f)) return fail(AFC_ERR_INVALID, "threshold must be finite and > 0");
+    if (!workspace) return fail(AFC_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)",
+                                sigma_clip_workspace_bytes(n_antennas, n_channels));
+    hipError_t e = launch_sigma_clip(n_antennas, n_channels, reinterpret_cast<const float2*>(V), threshold, vis_flags,
+                                     workspace, stream);
+    if (e != hipSuccess) return hip_fail(e, "sigma-clip launch");
+    return AFC_OK;
+}
+
+AFC_API int afc_apply_vis_flags(int32_t n_antennas, int32_t n_channels, const uint8_t* vis_flags, void* V, void* M,
+                                hipStream_t stream) {
+    g_err.clear();
+    if (n_antennas < 1 || n_antennas > 4096) return fail(AFC_ERR_INVALID, "n_antennas = %d outside 1..4096", n_antennas);
+    if (n_channels < 1 || n_channels > 65535) return fail(AFC_ERR_INVALID, "n_channels = %d outside 1..65535", n_channels);
+    if (!vis_flags || (!V && !M)) return fail(AFC_ERR_INVALID, "NULL pointer (vis_flags, or both V and M)");
+    hipError_t e = launch_apply_vis_flags(n_antennas, n_channels, vis_flags, reinterpret_cast<float2*>(V),
+                                          reinterpret_cast<float2*>(M), stream);
+    if (e != hipSuccess) return hip_fail(e, "apply-flags launch");
+    return AFC_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------

@@ -126,6 +126,15 @@ hipError_t launch_normalise(const void* vis, bool is_int, const int32_t* W, void
 size_t cal_workspace_bytes(int Na, int P);
 hipError_t launch_calibrate(int Na, int P, const float2* V, const float2* M, const float2* g,
                             double* loss, float2* grad, void* ws, hipStream_t stream);
+// gain solver: n_iter preconditioned-gradient (alternating least-squares)
+// iterations from g, result phase-referenced to antenna 0, written to g
+size_t cal_solve_workspace_bytes(int Na, int P);
+hipError_t launch_calibrate_solve(int Na, int P, const float2* V, const float2* M, float2* g, int n_iter,
+                                  double* loss, void* ws, hipStream_t stream);
+// two-stage sigma clipping of XX / YY visibility amplitudes -> flags [P][Nbl][2]
+size_t sigma_clip_workspace_bytes(int Na, int P);
+hipError_t launch_sigma_clip(int Na, int P, const float2* V, float k, uint8_t* flags, void* ws, hipStream_t stream);
+hipError_t launch_apply_vis_flags(int Na, int P, const uint8_t* flags, float2* V, float2* M, hipStream_t stream);
 
 }  // namespace afc
 

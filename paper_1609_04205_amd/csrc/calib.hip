@@ -23,6 +23,8 @@
 // tiles in a fixed order (float64) and writes -4 x the sum; the first block
 // of each (channel, polarisation) adds the tile losses in a fixed order.
 // No atomics: the result is bitwise reproducible.
+#include <utility>
+
 #include "afc_internal.h"
 
 // The error-free transformations below need every product and sum rounded
@@ -91,12 +93,18 @@ __device__ __forceinline__ void tile_rc(int t, int& ti, int& tj) {
     tj = t - r * (r + 1) / 2;
 }
 
-// workspace layout: rowpart, colpart double2 [P][2][n_tiles][64]; loss float [P][2][n_tiles]
+// workspace layout: rowpart, colpart double2 [P][2][n_tiles][64]; loss float [P][2][n_tiles];
+// with kDiag also rowd, cold double [P][2][n_tiles][64]: the partial sums of
+// D_a = sum_b |M_ab|^2 |g_b|^2 over the full Hermitian matrix (the diagonal
+// of the Gauss-Newton normal matrix of the row-wise least-squares problem)
+template <bool kDiag>
 __global__ __launch_bounds__(kThreads) void cal_tiles_kernel(int Na, int P, int n_tiles, const float2* __restrict__ V,
                                                              const float2* __restrict__ M, const float2* __restrict__ g,
                                                              double2* __restrict__ rowpart, double2* __restrict__ colpart,
-                                                             float* __restrict__ losspart) {
+                                                             float* __restrict__ losspart, double* __restrict__ rowd,
+                                                             double* __restrict__ cold) {
     __shared__ double2 col_lds[4][kTileA];
+    __shared__ double cold_lds[kDiag ? 4 : 1][kTileA];
     __shared__ float loss_lds[4];
     const int t = blockIdx.x, ch = blockIdx.y, pol = blockIdx.z;
     int ti, tj;
@@ -109,14 +117,14 @@ __global__ __launch_bounds__(kThreads) void cal_tiles_kernel(int Na, int P, int 
     const float2* gc = g + (int64_t)ch * Na * 2 + pol;        // [a][2]
     const float2 gb = b < Na ? gc[(int64_t)b * 2] : make_float2(0.0f, 0.0f);
 
-    double cre = 0.0, cim = 0.0;
+    double cre = 0.0, cim = 0.0, cd = 0.0;
     float lsum = 0.0f;
     const int64_t slot = ((int64_t)(ch * 2 + pol) * n_tiles + t) * kTileA;
 #pragma unroll 4
     for (int m = 0; m < kTileA / 4; ++m) {
         const int r = rg + 4 * m;
         const int a = ti * kTileA + r;                            // wave-uniform
-        double rre = 0.0, rim = 0.0;
+        double rre = 0.0, rim = 0.0, rd = 0.0;
         if (a < Na) {
             const float2 ga = gc[(int64_t)a * 2];
             if (b < Na && b <= a) {
@@ -136,13 +144,24 @@ __global__ __launch_bounds__(kThreads) void cal_tiles_kernel(int Na, int P, int 
                     cre += (double)(tr * ga.x + tm * ga.y);
                     cim += (double)(tr * ga.y - tm * ga.x);
                 }
+                if constexpr (kDiag) {
+                    // |M|^2 |g_b|^2 to row a; |M|^2 |g_a|^2 to column b off the diagonal
+                    const double m2 = (double)mm.x * mm.x + (double)mm.y * mm.y;
+                    rd = m2 * ((double)gb.x * gb.x + (double)gb.y * gb.y);
+                    if (a != b) cd += m2 * ((double)ga.x * ga.x + (double)ga.y * ga.y);
+                }
             }
         }
         rre = wave_sum(rre);
         rim = wave_sum(rim);
         if (cb == 0) rowpart[slot + r] = make_double2(rre, rim);
+        if constexpr (kDiag) {
+            rd = wave_sum(rd);
+            if (cb == 0) rowd[slot + r] = rd;
+        }
     }
     col_lds[rg][cb] = make_double2(cre, cim);
+    if constexpr (kDiag) cold_lds[rg][cb] = cd;
     lsum = wave_sumf(lsum);
     if (cb == 0) loss_lds[rg] = lsum;
     __syncthreads();
@@ -154,15 +173,19 @@ __global__ __launch_bounds__(kThreads) void cal_tiles_kernel(int Na, int P, int 
             si += col_lds[w][tid].y;
         }
         colpart[slot + tid] = make_double2(sr, si);
+        if constexpr (kDiag)
+            cold[slot + tid] = (cold_lds[0][tid] + cold_lds[1][tid]) + (cold_lds[2][tid] + cold_lds[3][tid]);
     }
     if (tid == 0) losspart[(int64_t)(ch * 2 + pol) * n_tiles + t] = (loss_lds[0] + loss_lds[1]) + (loss_lds[2] + loss_lds[3]);
 }
 
+template <bool kDiag>
 __global__ __launch_bounds__(256) void cal_reduce_kernel(int Na, int P, int nT, int n_tiles,
                                                          const double2* __restrict__ rowpart,
                                                          const double2* __restrict__ colpart,
                                                          const float* __restrict__ losspart, double* __restrict__ loss,
-                                                         float2* __restrict__ grad) {
+                                                         float2* __restrict__ grad, const double* __restrict__ rowd,
+                                                         const double* __restrict__ cold, double* __restrict__ D) {
     const int ch = blockIdx.y, pol = blockIdx.z;
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t base = (int64_t)(ch * 2 + pol) * n_tiles;
@@ -180,6 +203,12 @@ __global__ __launch_bounds__(256) void cal_reduce_kernel(int Na, int P, int nT, 
             si += v.y;
         }
         grad[((int64_t)ch * Na + a) * 2 + pol] = make_float2((float)(-4.0 * sr), (float)(-4.0 * si));
+        if constexpr (kDiag) {
+            double sd = 0.0;
+            for (int tj = 0; tj <= ta; ++tj) sd += rowd[(base + ta * (ta + 1) / 2 + tj) * kTileA + ra];
+            for (int ti = ta; ti < nT; ++ti) sd += cold[(base + ti * (ti + 1) / 2 + ta) * kTileA + ra];
+            D[((int64_t)ch * Na + a) * 2 + pol] = sd;
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         float s = 0.0f;
@@ -190,12 +219,99 @@ __global__ __launch_bounds__(256) void cal_reduce_kernel(int Na, int P, int nT, 
 
 int n_tiles_side(int Na) { return (int)ceil_div(Na, kTileA); }
 
+// One iteration of the gain solver per (channel, antenna, polarisation):
+// g_new = g - grad / (4 D), which with grad = -4 (sum_b V_ab conj(z_ab) -
+// g_a D_a), z_ab = M_ab conj(g_b), is the alternating least-squares update
+// sum_b V_ab conj(z_ab) / D_a of each gain with all others fixed; on every
+// second iteration the new gain is averaged with the previous one.
+__global__ void cal_update_kernel(int n, const float2* __restrict__ g, const float2* __restrict__ grad,
+                                  const double* __restrict__ D, float2* __restrict__ g_next, int average) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const float2 gc = g[e];
+    const double d = D[e];
+    double nr = gc.x, ni = gc.y;
+    if (d > 0.0) {
+        nr = (double)gc.x - (double)grad[e].x / (4.0 * d);
+        ni = (double)gc.y - (double)grad[e].y / (4.0 * d);
+    }
+    if (average) {
+        nr = 0.5 * (nr + (double)gc.x);
+        ni = 0.5 * (ni + (double)gc.y);
+    }
+    g_next[e] = make_float2((float)nr, (float)ni);
+}
+
+// Remove the common phase of each (channel, polarisation): g_a conj(g_0) / |g_0|.
+__global__ void cal_reference_kernel(int Na, int P, const float2* __restrict__ g, float2* __restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P * Na * 2) return;
+    const int pol = e & 1, ch = e / (2 * Na);
+    const float2 g0 = g[(int64_t)ch * Na * 2 + pol];
+    const float2 ga = g[e];
+    const double m = sqrt((double)g0.x * g0.x + (double)g0.y * g0.y);
+    if (m > 0.0) {
+        const double cr = g0.x / m, ci = -(double)g0.y / m;
+        out[e] = make_float2((float)(ga.x * cr - ga.y * ci), (float)(ga.x * ci + ga.y * cr));
+    } else {
+        out[e] = ga;
+    }
+}
+
 }  // namespace
 
 size_t cal_workspace_bytes(int Na, int P) {
     const int nT = n_tiles_side(Na);
     const size_t n_tiles = (size_t)nT * (nT + 1) / 2;
     return (size_t)P * 2 * n_tiles * (2 * kTileA * sizeof(double2) + sizeof(float)) + 256;
+}
+
+size_t cal_solve_workspace_bytes(int Na, int P) {
+    const int nT = n_tiles_side(Na);
+    const size_t n_tiles = (size_t)nT * (nT + 1) / 2;
+    const size_t n_g = (size_t)P * Na * 2;
+    // gradient workspace (rounded up to 256 B), row and column partials of D,
+    // D, the gradient, two gain buffers, the per-iteration loss
+    return ((cal_workspace_bytes(Na, P) + 255) & ~(size_t)255) + (size_t)P * 2 * n_tiles * kTileA * 2 * sizeof(double)
+           + n_g * (sizeof(double) + 3 * sizeof(float2)) + (size_t)P * 2 * sizeof(double);
+}
+
+hipError_t launch_calibrate_solve(int Na, int P, const float2* V, const float2* M, float2* g, int n_iter,
+                                  double* loss, void* ws, hipStream_t stream) {
+    const int nT = n_tiles_side(Na);
+    const int n_tiles = nT * (nT + 1) / 2;
+    const size_t n_g = (size_t)P * Na * 2;
+    char* w = reinterpret_cast<char*>(ws);
+    double2* rowpart = reinterpret_cast<double2*>(w);
+    double2* colpart = rowpart + (size_t)P * 2 * n_tiles * kTileA;
+    float* losspart = reinterpret_cast<float*>(colpart + (size_t)P * 2 * n_tiles * kTileA);
+    char* w2 = w + ((cal_workspace_bytes(Na, P) + 255) & ~(size_t)255);
+    double* rowd = reinterpret_cast<double*>(w2);
+    double* cold = rowd + (size_t)P * 2 * n_tiles * kTileA;
+    double* D = cold + (size_t)P * 2 * n_tiles * kTileA;
+    float2* grad = reinterpret_cast<float2*>(D + n_g);
+    float2* ga = grad + n_g;
+    float2* gb = ga + n_g;
+    double* it_loss = reinterpret_cast<double*>(gb + n_g);
+    hipError_t e = hipMemcpyAsync(ga, g, n_g * sizeof(float2), hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return e;
+    const unsigned ug = (unsigned)ceil_div((int64_t)n_g, 256);
+    for (int it = 1; it <= n_iter; ++it) {
+        hipLaunchKernelGGL(cal_tiles_kernel<true>, dim3(n_tiles, P, 2), dim3(kThreads), 0, stream, Na, P, n_tiles, V,
+                           M, ga, rowpart, colpart, losspart, rowd, cold);
+        hipLaunchKernelGGL(cal_reduce_kernel<true>, dim3((unsigned)ceil_div(Na, 256), P, 2), dim3(256), 0, stream,
+                           Na, P, nT, n_tiles, rowpart, colpart, losspart, it_loss, grad, rowd, cold, D);
+        hipLaunchKernelGGL(cal_update_kernel, dim3(ug), dim3(256), 0, stream, (int)n_g, ga, grad, D, gb,
+                           (int)(it % 2 == 0));
+        std::swap(ga, gb);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(cal_reference_kernel, dim3(ug), dim3(256), 0, stream, Na, P, ga, g);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (loss) return launch_calibrate(Na, P, V, M, g, loss, nullptr, ws, stream);
+    return hipSuccess;
 }
 
 hipError_t launch_calibrate(int Na, int P, const float2* V, const float2* M, const float2* g, double* loss,
@@ -206,12 +322,12 @@ hipError_t launch_calibrate(int Na, int P, const float2* V, const float2* M, con
     double2* rowpart = reinterpret_cast<double2*>(w);
     double2* colpart = rowpart + (size_t)P * 2 * n_tiles * kTileA;
     float* losspart = reinterpret_cast<float*>(colpart + (size_t)P * 2 * n_tiles * kTileA);
-    hipLaunchKernelGGL(cal_tiles_kernel, dim3(n_tiles, P, 2), dim3(kThreads), 0, stream, Na, P, n_tiles, V, M, g,
-                       rowpart, colpart, losspart);
+    hipLaunchKernelGGL(cal_tiles_kernel<false>, dim3(n_tiles, P, 2), dim3(kThreads), 0, stream, Na, P, n_tiles, V, M,
+                       g, rowpart, colpart, losspart, nullptr, nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(cal_reduce_kernel, dim3((unsigned)ceil_div(Na, 256), P, 2), dim3(256), 0, stream, Na, P, nT,
-                       n_tiles, rowpart, colpart, losspart, loss, grad);
+    hipLaunchKernelGGL(cal_reduce_kernel<false>, dim3((unsigned)ceil_div(Na, 256), P, 2), dim3(256), 0, stream, Na, P,
+                       nT, n_tiles, rowpart, colpart, losspart, loss, grad, nullptr, nullptr, nullptr);
     return hipGetLastError();
 }
 
