@@ -17,8 +17,9 @@ int8-vs-fp32 comparison, the host-to-device rate of the int16 input (not in
 the step), the whole 32-subband band of the same shape, the paper's
 256-channel configuration (fused delay/bandpass compensation and 4:1 channel
 integration, then the X-engine), the batching plan
-(32 subbands, ragged, flagged, mixed fp16/int8) and the calibration
-gradient, and the CPU oracle timed on a bounded sample on the host cores.
+(32 subbands, ragged, flagged, mixed fp16/int8), the calibration
+gradient, gain solver and sigma-clip flagger, and the CPU oracle timed on a
+bounded sample on the host cores.
 """
 import argparse
 import json
@@ -366,6 +367,34 @@ def main():
         cal_bytes = 2.0 * 64 * nbl * 2 * 8          # XX and YY of V and M
         out["calibration"] = {"ms": round(cal_ms, 4), "algorithmic_gbs": round(cal_bytes / (cal_ms * 1e-3) / 1e9, 1)}
         log(f"calibration {cal_ms:.3f} ms")
+        # ---- gain solver (30 iterations from unit gains) and sigma-clip flagging
+        n_it = 30
+        g_unit = torch.zeros_like(gt)
+        g_unit[..., 0] = 1.0
+        gs = g_unit.clone()
+        wss = torch.empty(afc._lib.afc_calibrate_solve_workspace_bytes(576, 64), dtype=torch.uint8, device=dev)
+        afc.calibrate_solve(Vt, Mt, gs, n_it, workspace=wss)
+        flg = afc.sigma_clip(Vt, 5.0)
+        torch.cuda.synchronize()
+        ts = Timer(torch)
+        for _ in range(3):
+            gs.copy_(g_unit)
+            e = ts.rec("solve")
+            lsol = afc.calibrate_solve(Vt, Mt, gs, n_it, workspace=wss)
+            e.record(torch.cuda.current_stream())
+            e = ts.rec("clip")
+            afc.sigma_clip(Vt, 5.0, out=flg)
+            e.record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        gsn = gs.cpu().numpy()
+        gtn = gc[..., 0].astype(np.float64) + 1j * gc[..., 1]
+        gtn = gtn * (np.conj(gtn[:, :1, :]) / np.abs(gtn[:, :1, :]))
+        dev_true = float(np.abs((gsn[..., 0] + 1j * gsn[..., 1]) - gtn).max() / np.abs(gtn).max())
+        out["calibration"].update({"solve_iterations": n_it, "solve_ms": round(ts.ms("solve"), 3),
+                                   "solve_ms_per_iteration": round(ts.ms("solve") / n_it, 4),
+                                   "solve_max_gain_error_vs_true": round(dev_true, 5),
+                                   "sigma_clip_ms": round(ts.ms("clip"), 4)})
+        log(f"solve {ts.ms('solve'):.3f} ms ({n_it} iterations), sigma clip {ts.ms('clip'):.3f} ms")
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_spectra)
