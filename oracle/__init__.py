@@ -356,3 +356,74 @@ def apply_vis_flags(T: np.ndarray, flags: np.ndarray) -> np.ndarray:
     for pol in range(2):
         T[:, :, pol, pol, :] *= (flags[:, :, pol] == 0)[:, :, None]
     return T
+
+
+# --------------------------------------------------------------------------
+# gridding and imaging (Sec. "Imaging Pipeline")
+# --------------------------------------------------------------------------
+C_LIGHT = 299792458.0
+
+
+def grid_visibilities(V: np.ndarray, W, pos: np.ndarray, freq: np.ndarray, N: int, du: float):
+    """Spectral integration by bilinear gridding (Sec. "Imaging Pipeline":
+    the visibilities of several subbands are gridded onto one grid with
+    bilinear interpolation).
+
+    V float [B][P][Nbl][2][2][2] (calibrated, afc_correlate layout), W int
+    [B][Nbl] weights or None (1), pos [Na][2] east/north metres, freq [B][P]
+    sky frequency of each channel in Hz, N grid size (N % 4 == 0), du cell
+    size in wavelengths.  For every cross-correlation a > c with weight w > 0,
+    I = (XX + YY) / 2 sits at u = (x_a - x_c) nu / c, v = (y_a - y_c) nu / c;
+    with (pu, pv) = (u, v) / du + N/2, i0 = floor(pu), fu = pu - i0 (and j0,
+    fv), w I is spread over cells (j0 + dj, i0 + di), di, dj in {0, 1}, with
+    weights (1-fu or fu)(1-fv or fv), and w conj(I) over the mirrored cells
+    (N - j0 - dj, N - i0 - di) (the visibility at -u, -v).  A visibility is
+    gridded only if all eight cells lie inside the grid (1 <= i0, j0 and
+    i0, j0 <= N - 2).  Returns (G complex128 [N][N] indexed [v][u], norm = sum
+    of 2 w over the gridded visibilities)."""
+    V = np.asarray(V)
+    B, P, nbl = V.shape[0], V.shape[1], V.shape[2]
+    Na = pos.shape[0]
+    a, c = np.tril_indices(Na)
+    cross = a != c
+    a, c = a[cross], c[cross]
+    blx = np.flatnonzero(cross)
+    dx = pos[a, 0] - pos[c, 0]
+    dy = pos[a, 1] - pos[c, 1]
+    G = np.zeros((N, N), np.complex128)
+    norm = 0.0
+    for b in range(B):
+        w = np.ones(blx.size) if W is None else np.asarray(W[b], np.float64)[blx]
+        for k in range(P):
+            I = 0.5 * ((V[b, k, blx, 0, 0, 0].astype(np.float64) + V[b, k, blx, 1, 1, 0])
+                       + 1j * (V[b, k, blx, 0, 0, 1].astype(np.float64) + V[b, k, blx, 1, 1, 1]))
+            nu = float(freq[b, k])
+            pu = dx * nu / C_LIGHT / du + N / 2
+            pv = dy * nu / C_LIGHT / du + N / 2
+            i0 = np.floor(pu).astype(np.int64)
+            j0 = np.floor(pv).astype(np.int64)
+            fu = pu - i0
+            fv = pv - j0
+            ok = (w > 0) & (i0 >= 1) & (j0 >= 1) & (i0 <= N - 2) & (j0 <= N - 2)
+            for dj in (0, 1):
+                for di in (0, 1):
+                    wt = (fu if di else 1.0 - fu) * (fv if dj else 1.0 - fv) * w
+                    np.add.at(G, (j0[ok] + dj, i0[ok] + di), wt[ok] * I[ok])
+                    np.add.at(G, (N - j0[ok] - dj, N - i0[ok] - di), wt[ok] * np.conj(I[ok]))
+            norm += 2.0 * w[ok].sum()
+    return G, norm
+
+
+def image_from_grid(G: np.ndarray, norm: float) -> np.ndarray:
+    """Snapshot image (Sec. "Imaging Pipeline": the gridded visibilities are
+    Fourier transformed): for N % 4 == 0,
+        img[j][i] = Re sum_{q,p} G[q][p] exp(-2 pi i ((p - N/2)(i - N/2)
+                    + (q - N/2)(j - N/2)) / N) / norm,
+    pixel (i, j) at l = (i - N/2) / (N du), m = (j - N/2) / (N du).
+    Evaluated as (-1)^(i+j) Re FFT2[(-1)^(p+q) G] with numpy's FFT (the
+    exponent expands to pi + pi*i... terms that give these signs)."""
+    N = G.shape[0]
+    assert N % 4 == 0
+    s = (-1.0) ** np.add.outer(np.arange(N), np.arange(N))
+    F = np.fft.fft2(G * s)
+    return (s * F.real) / (norm if norm > 0 else 1.0)
