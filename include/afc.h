@@ -315,6 +315,46 @@ AFC_API int afc_apply_vis_flags(int32_t n_antennas, int32_t n_channels, const ui
                                 void* V, void* M, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Gridding and imaging (Sec. "Imaging Pipeline": the calibrated visibilities
+ * of several subbands are gridded onto one common grid with bilinear
+ * interpolation, which integrates them spectrally, and the grid is Fourier
+ * transformed into the snapshot image: 1024 x 1024 pixels for AARTFAAC-6,
+ * 2048 x 2048 for AARTFAAC-12).
+ *
+ * afc_grid_visibilities
+ *   vis       float2 [B][64][Nbl][2][2] (afc_correlate / afc_normalise
+ *             layout, calibrated); Stokes I = (XX + YY) / 2 is gridded.
+ *   weights   int32 [B][Nbl] (natural weights, e.g. afc_validity_weights)
+ *             or NULL (1); baselines of weight 0 are skipped.
+ *   positions double [Na][2] east / north antenna positions in metres.
+ *   freq_hz   double [B][64] sky frequency of every channel (device).
+ *   For each cross-correlation a > c: u = (x_a - x_c) nu / c, v = (y_a -
+ *   y_c) nu / c; (pu, pv) = (u, v) / cell_wavelengths + N/2; w I is spread
+ *   bilinearly over the four cells around (pu, pv) and w conj(I) over the
+ *   mirrored cells (N - j, N - i).  A visibility is gridded only if all
+ *   eight cells lie inside the grid (1 <= floor(pu), floor(pv) <= N - 2).
+ *   grid      float2 [N][N] out, indexed [v][u] (un-normalised sums).
+ *   norm      double [1] out (device): sum of 2 w over gridded visibilities.
+ *   The sums are formed in 64-bit fixed point with integer atomics, so the
+ *   grid is bitwise reproducible run to run.
+ * afc_image_from_grid
+ *   image     float [N][N] out: image[j][i] = Re sum_{q,p} grid[q][p]
+ *             exp(-2 pi i ((p - N/2)(i - N/2) + (q - N/2)(j - N/2)) / N)
+ *             / norm; pixel (i, j) at l = (i - N/2) / (N du), m = (j - N/2)
+ *             / (N du) (du = 1/2 wavelength images the whole sky).  A unit
+ *             point source peaks near 1 at its pixel.  Float32 FFT.
+ * workspace  afc_imaging_workspace_bytes(Na, B, N) bytes, shared by both.
+ * Limits: N a power of two in 32..4096; n_antennas <= 4096.
+ * ------------------------------------------------------------------------- */
+AFC_API size_t afc_imaging_workspace_bytes(int32_t n_antennas, int32_t n_subbands, int32_t grid_size);
+AFC_API int afc_grid_visibilities(int32_t n_antennas, int32_t n_subbands, const void* vis,
+                                  const int32_t* weights, const double* positions,
+                                  const double* freq_hz, int32_t grid_size, double cell_wavelengths,
+                                  void* grid, double* norm, void* workspace, hipStream_t stream);
+AFC_API int afc_image_from_grid(int32_t grid_size, const void* grid, const double* norm, float* image,
+                                void* workspace, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Batching form (Sec. "GPU Processing": each subband is an independent unit
  * of work; the paper hands subbands to free GPUs one by one, here all of them
  * go into one channeliser launch and one correlator launch per family of

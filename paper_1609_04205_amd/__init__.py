@@ -63,6 +63,10 @@ _lib.afc_sigma_clip_workspace_bytes.argtypes = [_i32, _i32]
 _lib.afc_sigma_clip_workspace_bytes.restype = _sz
 _lib.afc_sigma_clip.argtypes = [_i32, _i32, _vp, _f32, _vp, _vp, _vp]
 _lib.afc_apply_vis_flags.argtypes = [_i32, _i32, _vp, _vp, _vp, _vp]
+_lib.afc_imaging_workspace_bytes.argtypes = [_i32, _i32, _i32]
+_lib.afc_imaging_workspace_bytes.restype = _sz
+_lib.afc_grid_visibilities.argtypes = [_i32, _i32, _vp, _vp, _vp, _vp, _i32, C.c_double, _vp, _vp, _vp, _vp]
+_lib.afc_image_from_grid.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp]
 _lib.afc_plan_create.argtypes = [C.POINTER(Dims), _vp, _vp, C.c_char_p, C.POINTER(_vp)]
 _lib.afc_plan_workspace_bytes.argtypes = [_vp]
 _lib.afc_plan_workspace_bytes.restype = _sz
@@ -76,6 +80,7 @@ EXPORTS = ["afc_channelised_bytes", "afc_visibility_bytes", "afc_channelise",
            "afc_validity_words", "afc_validity", "afc_zero_invalid", "afc_validity_weights",
            "afc_normalise_visibilities", "afc_calibrate_solve_workspace_bytes", "afc_calibrate_solve",
            "afc_sigma_clip_workspace_bytes", "afc_sigma_clip", "afc_apply_vis_flags",
+           "afc_imaging_workspace_bytes", "afc_grid_visibilities", "afc_image_from_grid",
            "afc_calibrate_workspace_bytes", "afc_calibrate_grad", "afc_plan_create",
            "afc_plan_workspace_bytes", "afc_plan_launch", "afc_plan_info", "afc_plan_destroy",
            "afc_last_error"]
@@ -386,6 +391,55 @@ def apply_vis_flags(flags, V=None, M=None):
                 raise AfcError(f"apply_vis_flags: {n} does not match the flags")
     _check(_lib.afc_apply_vis_flags(Na, P, _ptr(flags), _ptr(V), _ptr(M), _stream(flags.device)),
            "afc_apply_vis_flags")
+
+
+class Imager:
+    """Bilinear gridding of calibrated visibilities and the snapshot image
+    (afc_grid_visibilities + afc_image_from_grid) for one array: positions
+    float64 [Na][2] metres, grid N x N cells of `cell_wavelengths`."""
+
+    def __init__(self, positions, n_subbands: int, grid_size: int, cell_wavelengths: float = 0.5):
+        torch = _torch()
+        _require(positions, torch.float64, "positions")
+        self.Na = positions.shape[0]
+        self.B = int(n_subbands)
+        self.N = int(grid_size)
+        self.du = float(cell_wavelengths)
+        self.pos = positions
+        wsb = _lib.afc_imaging_workspace_bytes(self.Na, self.B, self.N)
+        if wsb == 0:
+            raise AfcError(f"imaging: unsupported shape (Na={self.Na}, B={self.B}, N={self.N})")
+        self.ws = torch.empty(wsb, dtype=torch.uint8, device=positions.device)
+        self.norm = torch.empty(1, dtype=torch.float64, device=positions.device)
+
+    def grid(self, vis, freq_hz, weights=None, out=None):
+        """vis float32 [B][64][Nbl][2][2][2], freq_hz float64 [B][64] -> complex grid float32 [N][N][2]."""
+        torch = _torch()
+        _require(vis, torch.float32, "vis")
+        _require(freq_hz, torch.float64, "freq_hz")
+        nbl = self.Na * (self.Na + 1) // 2
+        if tuple(vis.shape) != (self.B, N_CHANNELS, nbl, 2, 2, 2) or tuple(freq_hz.shape) != (self.B, N_CHANNELS):
+            raise AfcError("imaging: vis must be [B][64][Nbl][2][2][2] and freq_hz [B][64]")
+        if weights is not None:
+            _require(weights, torch.int32, "weights")
+        if out is None:
+            out = torch.empty((self.N, self.N, 2), dtype=torch.float32, device=vis.device)
+        _require(out, torch.float32, "out")
+        _check(_lib.afc_grid_visibilities(self.Na, self.B, _ptr(vis), _ptr(weights), _ptr(self.pos), _ptr(freq_hz),
+                                          self.N, self.du, _ptr(out), _ptr(self.norm), _ptr(self.ws),
+                                          _stream(vis.device)), "afc_grid_visibilities")
+        return out
+
+    def image(self, grid, out=None):
+        """grid float32 [N][N][2] (from grid()) -> image float32 [N][N], normalised by the gridded weight."""
+        torch = _torch()
+        _require(grid, torch.float32, "grid")
+        if out is None:
+            out = torch.empty((self.N, self.N), dtype=torch.float32, device=grid.device)
+        _require(out, torch.float32, "out")
+        _check(_lib.afc_image_from_grid(self.N, _ptr(grid), _ptr(self.norm), _ptr(out), _ptr(self.ws),
+                                        _stream(grid.device)), "afc_image_from_grid")
+        return out
 
 
 def _make_cal_loss():

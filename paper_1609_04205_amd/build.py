@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libafc.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["ppf.hip", "ppf_fine.hip", "xengine.hip", "validity.hip", "flag.hip", "calib.hip", "afc_api.cpp"]
+SOURCES = ["ppf.hip", "ppf_fine.hip", "xengine.hip", "validity.hip", "flag.hip", "imaging.hip", "calib.hip", "afc_api.cpp"]
 # calib.hip relies on error-free product/sum transformations: no contraction
 EXTRA = {"calib.hip": ["-ffp-contract=off"]}
 ARCH = os.environ.get("AFC_OFFLOAD_ARCH", "gfx950")
@@ -40,7 +40,7 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     saved = COMMON
     COMMON = COMMON + [f"-D{d}" for d in defines]
     try:
-        with cf.ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
+        with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
             objs = list(ex.map(_compile, SOURCES))
     finally:
         COMMON = saved

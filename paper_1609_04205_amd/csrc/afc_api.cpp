@@ -341,6 +341,53 @@ AFC_API int afc_apply_vis_flags(int32_t n_antennas, int32_t n_channels, const ui
     return AFC_OK;
 }
 
+namespace {
+int check_grid(int32_t n_antennas, int32_t n_subbands, int32_t grid_size) {
+    if (n_antennas < 1 || n_antennas > 4096) return fail(AFC_ERR_INVALID, "n_antennas = %d outside 1..4096", n_antennas);
+    if (n_subbands < 1 || n_subbands > AFC_MAX_SUBBANDS)
+        return fail(AFC_ERR_INVALID, "n_subbands = %d outside 1..%d", n_subbands, AFC_MAX_SUBBANDS);
+    if (grid_size < 32 || grid_size > 4096 || (grid_size & (grid_size - 1)))
+        return fail(AFC_ERR_UNSUPPORTED, "grid_size = %d (a power of two in 32..4096)", grid_size);
+    return AFC_OK;
+}
+}  // namespace
+
+AFC_API size_t afc_imaging_workspace_bytes(int32_t n_antennas, int32_t n_subbands, int32_t grid_size) {
+    if (check_grid(n_antennas, n_subbands, grid_size) != AFC_OK) return 0;
+    return imaging_workspace_bytes(n_antennas, n_subbands, grid_size);
+}
+
+AFC_API int afc_grid_visibilities(int32_t n_antennas, int32_t n_subbands, const void* vis, const int32_t* weights,
+                                  const double* positions, const double* freq_hz, int32_t grid_size,
+                                  double cell_wavelengths, void* grid, double* norm, void* workspace,
+                                  hipStream_t stream) {
+    g_err.clear();
+    int rc = check_grid(n_antennas, n_subbands, grid_size);
+    if (rc != AFC_OK) return rc;
+    if (!vis || !positions || !freq_hz || !grid || !norm)
+        return fail(AFC_ERR_INVALID, "NULL pointer (vis, positions, freq_hz, grid or norm)");
+    if (!(std::isfinite(cell_wavelengths) && cell_wavelengths > 0.0))
+        return fail(AFC_ERR_INVALID, "cell_wavelengths must be finite and > 0");
+    if (!workspace) return fail(AFC_ERR_WORKSPACE, "workspace is NULL");
+    hipError_t e = launch_grid(reinterpret_cast<const float2*>(vis), weights, positions, freq_hz, n_antennas,
+                               n_subbands, grid_size, cell_wavelengths, reinterpret_cast<float2*>(grid), norm,
+                               workspace, stream);
+    if (e != hipSuccess) return hip_fail(e, "gridding launch");
+    return AFC_OK;
+}
+
+AFC_API int afc_image_from_grid(int32_t grid_size, const void* grid, const double* norm, float* image, void* workspace,
+                                hipStream_t stream) {
+    g_err.clear();
+    int rc = check_grid(1, 1, grid_size);
+    if (rc != AFC_OK) return rc;
+    if (!grid || !norm || !image) return fail(AFC_ERR_INVALID, "NULL pointer (grid, norm or image)");
+    if (!workspace) return fail(AFC_ERR_WORKSPACE, "workspace is NULL");
+    hipError_t e = launch_image(reinterpret_cast<const float2*>(grid), norm, image, grid_size, workspace, stream);
+    if (e != hipSuccess) return hip_fail(e, "imaging launch");
+    return AFC_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------

@@ -122,6 +122,12 @@ hipError_t launch_validity_weights(const uint32_t* v, const uint8_t* flags, int3
 hipError_t launch_normalise(const void* vis, bool is_int, const int32_t* W, void* out, int B, int Na,
                             hipStream_t stream);
 
+// ---------------------------------------------------------------- imaging
+size_t imaging_workspace_bytes(int Na, int B, int N);
+hipError_t launch_grid(const float2* vis, const int32_t* weights, const double* pos, const double* freq, int Na, int B,
+                       int N, double du, float2* grid_out, double* norm, void* ws, hipStream_t stream);
+hipError_t launch_image(const float2* grid, const double* norm, float* image, int N, void* ws, hipStream_t stream);
+
 // ---------------------------------------------------------------- calibration
 size_t cal_workspace_bytes(int Na, int P);
 hipError_t launch_calibrate(int Na, int P, const float2* V, const float2* M, const float2* g,
