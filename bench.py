@@ -18,7 +18,8 @@ the step), the whole 32-subband band of the same shape, the paper's
 256-channel configuration (fused delay/bandpass compensation and 4:1 channel
 integration, then the X-engine), the batching plan
 (32 subbands, ragged, flagged, mixed fp16/int8), the calibration
-gradient, gain solver and sigma-clip flagger, and the CPU oracle timed on a
+gradient, gain solver and sigma-clip flagger, gridding and imaging of 8
+subbands on a 2048^2 grid, and the CPU oracle timed on a
 bounded sample on the host cores.
 """
 import argparse
@@ -395,6 +396,12 @@ def main():
                                    "solve_max_gain_error_vs_true": round(dev_true, 5),
                                    "sigma_clip_ms": round(ts.ms("clip"), 4)})
         log(f"solve {ts.ms('solve'):.3f} ms ({n_it} iterations), sigma clip {ts.ms('clip'):.3f} ms")
+        del Vt, Mt, gt, gs, wss, flg
+        torch.cuda.empty_cache()
+
+        # ---- imaging: 8 subbands x 64 channels of the AARTFAAC-12 array
+        # gridded onto 2048 x 2048 cells of half a wavelength, then the image
+        out["imaging"] = run_imaging(torch, afc, W, dev, cfg)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_spectra)
@@ -454,6 +461,48 @@ def run_fine(torch, afc, W, dev, cfg, reps=3):
                    "traffic": measured_traffic("ppf_fine_kernel<int8>")}
     log(f"fine channeliser {f_ms:.3f} ms, xengine on its output {fx_ms:.3f} ms")
     del xf, zf, visf, wf, wsf
+    torch.cuda.empty_cache()
+    return res
+
+
+def run_imaging(torch, afc, W, dev, cfg, B_img=8, N=2048, reps=3):
+    """Gridding of B_img subbands (calibrated visibilities of three point
+    sources, unit weights) and the 2-D FFT image of the AARTFAAC-12 array."""
+    import numpy as np
+    Na = cfg.n_antennas
+    pos = torch.from_numpy(W.antenna_positions(cfg)).to(dev)
+    freq = torch.tensor([[W.subband_frequency(b) + W.channel_offset(k, 64) * W.F_SUBBAND / 64 for k in range(64)]
+                         for b in range(B_img)], dtype=torch.float64, device=dev)
+    a, c = np.tril_indices(Na)
+    dx, dy = pos[a, 0] - pos[c, 0], pos[a, 1] - pos[c, 1]
+    vis = torch.zeros((B_img, 64, a.size, 2, 2, 2), dtype=torch.float32, device=dev)
+    for flux, l0, m0 in ((10.0, 0.27, -0.31), (4.0, -0.12, 0.46), (2.0, 0.0, 0.07)):
+        ph = 2.0 * np.pi / 299792458.0 * (dx[None, None, :] * l0 + dy[None, None, :] * m0) * freq[:, :, None]
+        for p in range(2):
+            vis[:, :, :, p, p, 0] += (flux * torch.cos(ph)).float()
+            vis[:, :, :, p, p, 1] += (flux * torch.sin(ph)).float()
+    del ph
+    im = afc.Imager(pos, B_img, N, 0.5)
+    grid = im.grid(vis, freq)
+    img = im.image(grid)
+    torch.cuda.synchronize()
+    tm = Timer(torch)
+    for _ in range(reps):
+        e = tm.rec("grid")
+        im.grid(vis, freq, out=grid)
+        e.record(torch.cuda.current_stream())
+        e = tm.rec("image")
+        im.image(grid, out=img)
+        e.record(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    n_vis = B_img * 64 * (Na * (Na - 1) // 2)
+    res = {"workload": f"a12-576ant-{B_img}sb-grid{N}", "visibilities": n_vis,
+           "grid_ms": round(tm.ms("grid"), 3),
+           "grid_gvis_per_s": round(n_vis / (tm.ms("grid") * 1e-3) / 1e9, 2),
+           "grid_vis_gbs": round(float(vis.numel()) * 4 / (tm.ms("grid") * 1e-3) / 1e9, 1),
+           "image_ms": round(tm.ms("image"), 3)}
+    log(f"imaging: grid {tm.ms('grid'):.3f} ms, image {tm.ms('image'):.3f} ms")
+    del vis, grid, img, im
     torch.cuda.empty_cache()
     return res
 
