@@ -14,20 +14,25 @@
 //   f_k = (k < 128 ? k : k - 256) * (subband width / 256)
 //
 // 256 = 4 x 64 with p = p1 + 64 j, k = k1 + 4 k', k' = k2 + 16 k3.
-//  * FIR phase: as in the 64-channel bank, a lane keeps the 16-deep windows
-//    of two branches in registers; a lane quad holds the four branches
-//    p1 + 64 j of one receiver and after two DPP exchanges each quad lane owns
-//    one k1 of the radix-4 stage over j, times exp(-2 pi i p1 k1 / 256).
-//    16 waves x 4 branch groups cover p1 < 64, 16 lanes per branch group
-//    cover 4 receivers x 4 quad lanes.
-//  * FFT phase 1: lane (receiver, k1, qd), wave = spectrum, does the 16-point
-//    DFT over r (p1 = qd + 4 r) and the twiddle exp(-2 pi i qd k2 / 64).
-//  * FFT phase 2 (after an LDS exchange): lane (receiver, spectrum, k2) does
-//    the radix-4 over qd for each k1, which gives fine channels
-//    k = k1 + 4 k2 + 64 k3, weighs them with C and sums over k1: coarse
-//    channel c = k2 + 16 k3.
-// Both LDS buffers are XOR-swizzled instead of padded so that they fit in
-// 160 KB beside the taps and the compensation factors.
+// One workgroup = 8 receivers x a run of spectra of one subband, 512 threads
+// (8 waves, two per SIMD, so that a lane may hold 256 registers): a row of
+// the time-major input gives the workgroup 32 contiguous bytes (the rate of
+// L1-to-L2 line requests, not HBM, bounds this kernel; 8 receivers per
+// workgroup halve it against 4).
+//  * FIR phase: lane (p1, receiver half, j) owns branch p = p1 + 64 j of 4
+//    receivers: its taps (16 registers), the 16-deep windows of 4 receivers x
+//    2 components (128 registers), one 16-byte load per spectrum.  The radix-4
+//    stage over j runs across the lane quad in two DPP exchanges (sums and
+//    differences, then the +-1, +-i rotations), leaving A[k1] in quad lane j
+//    with k1 the bit reverse of j, times exp(-2 pi i p1 k1 / 256).
+//  * FFT phase 1: a lane takes two (spectrum, k1, receiver, qd) jobs: the
+//    16-point DFT over r (p1 = qd + 4 r) and the twiddle exp(-2 pi i qd k2 / 64).
+//  * FFT phase 2 (after an LDS exchange): lane (receiver, spectrum) of wave
+//    k2 (and k2 + 8) does the radix-4 over qd for each k1 (fine channels
+//    k = k1 + 4 k2 + 64 k3), weighs them with C and sums over k1: coarse
+//    channel c = k2 + 16 k3, stored as 8 receivers x 8 spectra, contiguous in
+//    the block layout.
+// A phase covers 8 spectra, one block of the output.
 #include "afc_internal.h"
 #include "ppf_common.h"
 
@@ -37,16 +42,16 @@ using namespace ppfk;
 
 constexpr int kPF = kPFine;                  // fine channels
 constexpr int kRF = 4;                       // fine channels per output channel
-constexpr int kNiF = 4;                      // receivers per workgroup
-constexpr int kThreadsF = 1024;              // 16 waves
-constexpr int kKSF = 64 * kNiF;              // float2 per k1 row of the FIR-phase buffer
-constexpr int kSSF = 4 * kKSF;               // float2 per spectrum
-constexpr int kSppF = 16;                    // spectra per phase
+constexpr int kNiF = 8;                      // receivers per workgroup
+constexpr int kThreadsF = 512;               // 8 waves
+constexpr int kQF = 8;                       // spectra per phase
+constexpr int kK1S = 64 * kNiF + 2;          // float2 per k1 row of the phase buffer (+2: the 4 k1 rows start 4 banks apart)
+constexpr int kQS = 4 * kK1S;                // float2 per spectrum of the phase buffer
+constexpr int kXR = 16 * kNiF;               // float2 per (spectrum, k2) row of the exchange buffer
 constexpr int kChunkF = 192;                 // spectra per workgroup, a multiple of 16
-constexpr int kDepthF = 4;                   // spectra of loads in flight per lane (divides 16)
-constexpr int kXS = 64 * kSppF;              // float2 per k2 plane of the exchange buffer
-static_assert(16 * kXS <= kSppF * kSSF, "the exchange of the FFT phase fits the LDS buffer");
-static_assert(kChunkF % kSppF == 0 && kSppF % kDepthF == 0, "phase and pipeline shapes");
+constexpr int kDepthF = 4;                   // spectra of loads in flight per lane (divides 8)
+static_assert(kQF * 16 * kXR <= kQF * kQS, "the exchange fits the phase buffer");
+static_assert(kChunkF % 16 == 0 && kQF % kDepthF == 0, "phase and pipeline shapes");
 
 struct FineArgs {
     const int16_t* x;
@@ -61,12 +66,18 @@ struct FineArgs {
     float gain;
 };
 
-template <int DT>
+// value of lane L of this lane's quad, and of the lanes at xor 1 / xor 2
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+constexpr int kQuadXor1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);   // quad_perm [1,0,3,2]
+constexpr int kQuadXor2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);   // quad_perm [2,3,0,1]
+
+template <int DT, bool kVec4>
 __global__ __launch_bounds__(kThreadsF) void ppf_fine_kernel(FineArgs a, Tw64 tw64) {
-    __shared__ __attribute__((aligned(16))) float2 lds[kSppF * kSSF];
-    __shared__ __attribute__((aligned(16))) float ltaps[kT * kPF];
-    // rows padded by one element: the four receivers' rows start in
-    // different banks
+    __shared__ __attribute__((aligned(16))) float2 lds[kQF * kQS];
+    // rows padded by one element: the receivers' rows start in different banks
     __shared__ float2 lcomp[kNiF * (kPF + 1)];
     __shared__ float2 ltw[4 * 17];               // [qd][k2] exp(-2 pi i qd k2 / 64)
     // XCD-aware order: neighbouring receiver groups (which share 128-byte
@@ -87,173 +98,178 @@ __global__ __launch_bounds__(kThreadsF) void ppf_fine_kernel(FineArgs a, Tw64 tw
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
 
-    // taps as [branch][t]; compensation factors C = E A of this subband as
-    // [receiver][fine channel] (receivers beyond N repeat receiver N-1 and
-    // are never stored)
-    for (int e = tid; e < kT * kPF; e += kThreadsF) {
-        const int t = e / kPF, p = e % kPF;
-        ltaps[p * kT + t] = a.taps[e];
-    }
-    {
-        const int il = tid / kPF, k = tid % kPF;
+    // compensation factors C = E A of this subband, [receiver][fine channel]
+    // (receivers beyond N repeat receiver N-1 and are never stored)
+    for (int e = tid; e < kNiF * kPF; e += kThreadsF) {
+        const int il = e / kPF, k = e % kPF;
         const int i = min(i0 + il, N - 1);
         lcomp[il * (kPF + 1) + k] = cmul(a.E[(int64_t)i * kPF + k], a.A[(int64_t)sb * N + i]);
-        if (tid < 64) ltw[(tid >> 4) * 17 + (tid & 15)] = tw64.w[((tid >> 4) * (tid & 15)) & 63];
     }
+    if (tid < 64) ltw[(tid >> 4) * 17 + (tid & 15)] = tw64.w[((tid >> 4) * (tid & 15)) & 63];
 
-    // ---- FIR-phase roles: lane = il * 16 + ps * 4 + jh * 2 + comp
-    const int comp = lane & 1, jh = (lane >> 1) & 1, ps = (lane >> 2) & 3, il = lane >> 4;
-    const int p1 = 4 * wv + ps;
-    const int rcv = min(i0 + il, N - 1);
-    const int row_stride = N * 2;
-    const int lane_off = (p1 + 128 * jh) * row_stride + rcv * 2 + comp;   // branch p1 + 64 (2 jh) at row 0
-    const int64_t spec_stride = (int64_t)kPF * row_stride;
-    const int k1o = comp + 2 * jh;
+    // ---- FIR roles: lane = x * 8 + rh * 4 + j
+    const int j = lane & 3, rh = (lane >> 2) & 1, x = lane >> 3;
+    const int p1 = 8 * wv + x;
+    const int p = p1 + 64 * j;
+    const int k1o = ((j & 1) << 1) | (j >> 1);                 // this lane ends with A[k1o]
     const float2 tw_o = a.W[p1 * k1o];
-    const float2 rtw_o = k1o == 0 ? tw_o : k1o == 1 ? make_float2(tw_o.y, -tw_o.x)
-                       : k1o == 2 ? make_float2(-tw_o.x, -tw_o.y) : make_float2(-tw_o.y, tw_o.x);
-    const float sgn = (k1o & 1) ? -1.0f : 1.0f;
-    // [spectrum][k1][p1 * 4 + (receiver ^ k1)], bit 4 of the index flipped
-    // for odd k1: the 16 lanes of (branch group, k1) of one receiver, and the
-    // 32 of two receivers, write to distinct banks
-    const int fir_w = k1o * kKSF + ((p1 * kNiF + (il ^ k1o)) ^ ((k1o & 1) << 4));
-
-    lds_barrier();
-    const float4* tp0 = reinterpret_cast<const float4*>(ltaps + (p1 + 128 * jh) * kT);
-    const float4* tp1 = reinterpret_cast<const float4*>(ltaps + (p1 + 128 * jh + 64) * kT);
-
-    // raw int16 sample of branch p1 + 64 (2 jh + jj) at spectrum-row m
-    // (clamped: every load is in bounds and unconditional)
-    auto ld = [&](int m, int jj) -> int {
-        const int16_t* rowp = xs + (int64_t)min(m, S + kT - 2) * spec_stride;
-        return rowp[jj * (64 * row_stride) + lane_off];
-    };
-
-    float win[2][16];
+    // radix-4 over j: step 1 (partner j ^ 2) own * s1 + partner gives
+    // u0+u2, u1+u3, u0-u2, u1-u3 in lanes 0..3; step 2 (partner j ^ 1)
+    // alpha own + beta partner gives A0, A2, A1, A3
+    const float s1 = (j >> 1) ? -1.0f : 1.0f;
+    const float2 al = j == 0 ? make_float2(1.0f, 0.0f) : j == 1 ? make_float2(-1.0f, 0.0f)
+                    : j == 2 ? make_float2(1.0f, 0.0f) : make_float2(0.0f, 1.0f);
+    const float2 be = j == 2 ? make_float2(0.0f, -1.0f) : make_float2(1.0f, 0.0f);
+    float h[16];
 #pragma unroll
-    for (int m = 0; m < 15; ++m)
-#pragma unroll
-        for (int jj = 0; jj < 2; ++jj) win[jj][m] = (float)ld(s_begin + m, jj);
-#pragma unroll
-    for (int jj = 0; jj < 2; ++jj) win[jj][15] = 0.0f;
-
-    // ---- FFT phase 1 roles: lane = k1 * 16 + qd * 4 + receiver, wave = spectrum
-    const int il1 = lane & 3, qd1 = (lane >> 2) & 3, k1f = lane >> 4, q1 = wv;
-    const int b1 = k1f & 1;
-    const int il1s = il1 ^ k1f;
-    const float2* src1e = lds + q1 * kSSF + k1f * kKSF + 4 * qd1 + il1s + 16 * b1;   // r even
-    const float2* src1o = lds + q1 * kSSF + k1f * kKSF + 4 * qd1 + il1s - 16 * b1;   // r odd
-    // exchange buffer [k2][spectrum][(k1 * 4 + qd) * 4 + receiver], the
-    // (k1 * 4 + qd) index XOR spectrum % 8
-    const int xw = q1 * 64 + (((k1f * 4 + qd1) * 4 + il1) ^ ((q1 & 7) << 2));
-    const float2* tw1 = ltw + qd1 * 17;
-    // ---- FFT phase 2 roles: lane = k2lo * 32 + (spectrum % 8) * 4 + receiver
-    const int il2 = lane & 3, ql2 = (lane >> 2) & 7, k2lo = lane >> 5;
-    const int q2 = (wv & 1) * 8 + ql2, k2 = (wv >> 1) * 2 + k2lo;
-    const float2* src2 = lds + k2 * kXS + q2 * 64 + il2;
-    const float2* comp2 = lcomp + il2 * (kPF + 1) + 4 * k2;
-    const int rf = i0 + il2;
-
-    int pf[kDepthF][2];
-    auto fetch = [&](int s, int (&dst)[2]) {
-#pragma unroll
-        for (int jj = 0; jj < 2; ++jj) dst[jj] = ld(s + 15, jj);
-    };
-#pragma unroll
-    for (int d = 0; d < kDepthF; ++d) fetch(s_begin + d, pf[d]);
-
-    for (int sg = s_begin; sg < s_end; sg += kSppF) {
-        float h[2][16];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const float4 a0 = tp0[v], a1 = tp1[v];
-            h[0][4 * v] = a0.x; h[0][4 * v + 1] = a0.y; h[0][4 * v + 2] = a0.z; h[0][4 * v + 3] = a0.w;
-            h[1][4 * v] = a1.x; h[1][4 * v + 1] = a1.y; h[1][4 * v + 2] = a1.z; h[1][4 * v + 3] = a1.w;
+    for (int t = 0; t < 16; ++t) h[t] = a.taps[t * kPF + p];
+    // first receiver of this lane's four; loads clamped into the row (the
+    // clamped receivers are never stored)
+    const int rb = i0 + 4 * rh;
+    const int64_t row_stride = 2LL * N;                        // int16 per input row
+    const int64_t spec_stride = (int64_t)kPF * row_stride;
+    const int16_t* lane_base = xs + (int64_t)p * row_stride;
+    const int rq0 = kVec4 ? min(rb, N - 4) : min(rb, N - 2);
+    const int rq1 = min(rb + 2, N - 2);
+    auto ld = [&](int m) -> int4 {
+        const int16_t* rowp = lane_base + (int64_t)min(m, S + kT - 2) * spec_stride;
+        if constexpr (kVec4) {
+            return *reinterpret_cast<const int4*>(rowp + 2 * rq0);
+        } else {
+            const int2 u0 = *reinterpret_cast<const int2*>(rowp + 2 * rq0);
+            const int2 u1 = *reinterpret_cast<const int2*>(rowp + 2 * rq1);
+            return make_int4(u0.x, u0.y, u1.x, u1.y);
         }
+    };
+
+    float win[4][2][16];
+    auto put = [&](int slot, int4 d) {
+        const int dd[4] = {d.x, d.y, d.z, d.w};
 #pragma unroll
-        for (int q = 0; q < kSppF; ++q) {
+        for (int r = 0; r < 4; ++r) {
+            win[r][0][slot] = (float)(int)(short)(dd[r] & 0xFFFF);
+            win[r][1][slot] = (float)(dd[r] >> 16);
+        }
+    };
 #pragma unroll
-            for (int jj = 0; jj < 2; ++jj) win[jj][(q + 15) & 15] = (float)pf[q % kDepthF][jj];
-            fetch(sg + q + kDepthF, pf[q % kDepthF]);
-            float u[2];
+    for (int m = 0; m < 15; ++m) put(m, ld(s_begin + m));
 #pragma unroll
-            for (int jj = 0; jj < 2; ++jj) {
-                float acc = 0.0f;
+    for (int r = 0; r < 4; ++r) win[r][0][15] = win[r][1][15] = 0.0f;
+
+    int4 pf[kDepthF];
 #pragma unroll
-                for (int t = 0; t < 16; ++t) acc = fmaf(h[jj][t], win[jj][(q + t) & 15], acc);
-                u[jj] = acc;
+    for (int d = 0; d < kDepthF; ++d) pf[d] = ld(s_begin + d + 15);
+
+    // ---- FFT phase 1 jobs: T = tid + 512 t, receiver = T % 8, qd = (T / 8) % 4,
+    // k1 = (T / 32) % 4, spectrum = T / 128
+    const int rc1 = tid & 7, qd1 = (tid >> 3) & 3, k11 = (tid >> 5) & 3, q1 = tid >> 7;   // t = 0; t = 1 adds 4 to q
+    // ---- FFT phase 2 roles: lane = spectrum * 8 + receiver, k2 = wave (+ 8)
+    const int rc2 = lane & 7, q2 = lane >> 3;
+    const int rf = i0 + rc2;
+    const float2* comp2 = lcomp + rc2 * (kPF + 1);
+
+    for (int sg = s_begin; sg < s_end; sg += 16) {
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            const int sp = sg + 8 * half;                      // first spectrum of this phase
+#pragma unroll
+            for (int ql = 0; ql < kQF; ++ql) {
+                const int q = 8 * half + ql;                   // window slot of spectrum sg + q
+                put((q + 15) & 15, pf[ql % kDepthF]);
+                pf[ql % kDepthF] = ld(sp + ql + kDepthF + 15);
+                float u[4][2];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        float acc = 0.0f;
+#pragma unroll
+                        for (int t = 0; t < 16; ++t) acc = fmaf(h[t], win[r][c][(q + t) & 15], acc);
+                        u[r][c] = acc;
+                    }
+                float2 o[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    // step 1: with the lane at j ^ 2
+                    const float e0 = fmaf(s1, u[r][0], dpp<kQuadXor2>(u[r][0]));
+                    const float e1 = fmaf(s1, u[r][1], dpp<kQuadXor2>(u[r][1]));
+                    // step 2: with the lane at j ^ 1
+                    const float f0 = dpp<kQuadXor1>(e0), f1 = dpp<kQuadXor1>(e1);
+                    float2 v;
+                    v.x = al.x * e0 - al.y * e1 + be.x * f0 - be.y * f1;
+                    v.y = al.x * e1 + al.y * e0 + be.x * f1 + be.y * f0;
+                    o[r] = cmul(v, tw_o);
+                }
+                float4* dst = reinterpret_cast<float4*>(lds + ql * kQS + k1o * kK1S + p1 * kNiF + 4 * rh);
+                dst[0] = make_float4(o[0].x, o[0].y, o[1].x, o[1].y);
+                dst[1] = make_float4(o[2].x, o[2].y, o[3].x, o[3].y);
+                __builtin_amdgcn_sched_barrier(0);
             }
-            // quad lane (comp, jh) holds component comp of branches j = 2 jh + jj
-            const float2 u0 = make_float2(quad_bcast<0>(u[0]), quad_bcast<1>(u[0]));
-            const float2 u1 = make_float2(quad_bcast<0>(u[1]), quad_bcast<1>(u[1]));
-            const float2 u2 = make_float2(quad_bcast<2>(u[0]), quad_bcast<3>(u[0]));
-            const float2 u3 = make_float2(quad_bcast<2>(u[1]), quad_bcast<3>(u[1]));
-            // A[k1] = (u0 + (-1)^k1 u2) + (-i)^k1 (u1 + (-1)^k1 u3), times the twiddle
-            const float2 E = make_float2(fmaf(sgn, u2.x, u0.x), fmaf(sgn, u2.y, u0.y));
-            const float2 Od = make_float2(fmaf(sgn, u3.x, u1.x), fmaf(sgn, u3.y, u1.y));
-            float2 o = cmul(E, tw_o);
-            o.x = fmaf(Od.x, rtw_o.x, fmaf(-Od.y, rtw_o.y, o.x));
-            o.y = fmaf(Od.x, rtw_o.y, fmaf(Od.y, rtw_o.x, o.y));
-            lds[q * kSSF + fir_w] = o;
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        lds_barrier();
-        {
-            float2 v[16];
-#pragma unroll
-            for (int r = 0; r < 16; ++r) v[r] = (r & 1) ? src1o[16 * r] : src1e[16 * r];
-            dft16(v);
             lds_barrier();
+            // 16-point DFT over r (p1 = qd + 4 r), spectra q1 then q1 + 4: the
+            // exchange rows of spectra 0..3 end before the phase-buffer rows
+            // of spectra 4..7 begin, so the second job's reads may overlap the
+            // first job's writes
+            static_assert(4 * 16 * kXR <= 4 * kQS, "exchange rows of spectra 0..3 precede phase rows 4..7");
 #pragma unroll
-            for (int ga = 0; ga < 4; ++ga)
+            for (int t = 0; t < 2; ++t) {
+                const int q = q1 + 4 * t;
+                float2 v[16];
+                const float2* src = lds + q * kQS + k11 * kK1S + qd1 * kNiF + rc1;
 #pragma unroll
-                for (int de = 0; de < 4; ++de) {
-                    const int kk = ga + 4 * de;            // k2
-                    float2 y = v[4 * ga + de];
-                    if (kk != 0) y = cmul(y, tw1[kk]);
-                    lds[kk * kXS + xw] = y;
-                }
-        }
-        lds_barrier();
-        {
-            float2 v[4][4];
-            // the swizzle is per lane: keep its 8 addresses out of the
-            // registers that live across the loop
-            int sw = ql2;
-            asm volatile("" : "+v"(sw));
+                for (int r = 0; r < 16; ++r) v[r] = src[r * 4 * kNiF];
+                lds_barrier();
+                dft16(v);
+                // exchange [spectrum][k2][(k1 * 4 + qd) ^ (spectrum & 1)][receiver]
+                float2* dst = lds + (q * 16) * kXR + (((k11 * 4 + qd1) ^ (q & 1)) * kNiF) + rc1;
 #pragma unroll
-            for (int m = 0; m < 16; ++m) v[m >> 2][m & 3] = src2[(m & 8) * 4 + (((m & 7) ^ sw) << 2)];
-            float2 c4[4];
+                for (int ga = 0; ga < 4; ++ga)
 #pragma unroll
-            for (int k3 = 0; k3 < 4; ++k3) c4[k3] = make_float2(0.0f, 0.0f);
-#pragma unroll
-            for (int k1 = 0; k1 < kRF; ++k1) {
-                dft4(v[k1][0], v[k1][1], v[k1][2], v[k1][3]);
-#pragma unroll
-                for (int k3 = 0; k3 < 4; ++k3) c4[k3] = c4[k3] + cmul(v[k1][k3], comp2[k1 + 64 * k3]);
+                    for (int de = 0; de < 4; ++de) {
+                        const int kk = ga + 4 * de;                    // k2
+                        float2 y = v[4 * ga + de];
+                        if (kk != 0) y = cmul(y, ltw[qd1 * 17 + kk]);
+                        dst[kk * kXR] = y;
+                    }
             }
-            const int s = sg + q2;
-            const int blk = s >> 3;
-            if (rf < N && blk < a.Sb) {
-                const bool live = s < S;
+            lds_barrier();
+            {
+                const int blk = sp >> 3;
+                const bool live = sp + q2 < S;
                 const float g = live ? a.gain : 0.0f;
-                // channel c = k2 + 16 k3: the wave-uniform part (k2 - k2lo +
-                // 16 k3) goes to the store's scalar base, k2lo to the lane
-                // offset (a channel pair spans far less than 4 GiB: one
-                // subband of input is bounded to 2^31 values)
                 const int64_t ch_stride = (int64_t)a.Sb * N * kSBlk;
-                const unsigned lane_zoff = (unsigned)((blk * N + rf) * kSBlk + ql2 + k2lo * ch_stride);
-                const int k2u = (wv >> 1) * 2;
+                const unsigned lane_zoff = (unsigned)((blk * N + rf) * kSBlk + q2);
 #pragma unroll
-                for (int k3 = 0; k3 < 4; ++k3) {
-                    float2 y = c4[k3];
-                    if constexpr (DT != AFC_I8)
-                        if (!live) y = make_float2(0.0f, 0.0f);
-                    store_sample<DT>(zs, (int64_t)(k2u + 16 * k3) * ch_stride, lane_zoff, y, g);
+                for (int t = 0; t < 2; ++t) {
+                    const int k2 = wv + 8 * t;
+                    const float2* src = lds + (q2 * 16 + k2) * kXR + rc2;
+                    const int sw = q2 & 1;
+                    float2 v[4][4];
+#pragma unroll
+                    for (int m = 0; m < 16; ++m) v[m >> 2][m & 3] = src[(m ^ sw) * kNiF];
+                    float2 c4[4];
+#pragma unroll
+                    for (int k3 = 0; k3 < 4; ++k3) c4[k3] = make_float2(0.0f, 0.0f);
+#pragma unroll
+                    for (int k1 = 0; k1 < kRF; ++k1) {
+                        dft4(v[k1][0], v[k1][1], v[k1][2], v[k1][3]);
+#pragma unroll
+                        for (int k3 = 0; k3 < 4; ++k3)
+                            c4[k3] = c4[k3] + cmul(v[k1][k3], comp2[k1 + 4 * k2 + 64 * k3]);
+                    }
+                    if (rf < N && blk < a.Sb) {
+#pragma unroll
+                        for (int k3 = 0; k3 < 4; ++k3) {
+                            float2 y = c4[k3];
+                            if constexpr (DT != AFC_I8)
+                                if (!live) y = make_float2(0.0f, 0.0f);
+                            store_sample<DT>(zs, (int64_t)(k2 + 16 * k3) * ch_stride, lane_zoff, y, g);
+                        }
+                    }
                 }
             }
+            lds_barrier();
         }
-        lds_barrier();
     }
 }
 
@@ -343,17 +359,19 @@ hipError_t launch_ppf_fine(const FineLaunch& l, hipStream_t stream) {
     a.total = (int)total;
     a.per_xcd = (int)ceil_div(total, 8);
     const dim3 grid((unsigned)(a.per_xcd * 8));
+    // 16-byte row loads need 16-byte aligned rows: N a multiple of 4
+    const bool vec4 = l.N % 4 == 0;
+#define AFC_FINE_LAUNCH(DT)                                                                                  \
+    if (vec4)                                                                                                \
+        hipLaunchKernelGGL((ppf_fine_kernel<DT, true>), grid, dim3(kThreadsF), 0, stream, a, tw64);           \
+    else                                                                                                     \
+        hipLaunchKernelGGL((ppf_fine_kernel<DT, false>), grid, dim3(kThreadsF), 0, stream, a, tw64);
     switch (l.dt) {
-        case AFC_F32:
-            hipLaunchKernelGGL(ppf_fine_kernel<AFC_F32>, grid, dim3(kThreadsF), 0, stream, a, tw64);
-            break;
-        case AFC_F16:
-            hipLaunchKernelGGL(ppf_fine_kernel<AFC_F16>, grid, dim3(kThreadsF), 0, stream, a, tw64);
-            break;
-        default:
-            hipLaunchKernelGGL(ppf_fine_kernel<AFC_I8>, grid, dim3(kThreadsF), 0, stream, a, tw64);
-            break;
+        case AFC_F32: AFC_FINE_LAUNCH(AFC_F32) break;
+        case AFC_F16: AFC_FINE_LAUNCH(AFC_F16) break;
+        default: AFC_FINE_LAUNCH(AFC_I8) break;
     }
+#undef AFC_FINE_LAUNCH
     return hipGetLastError();
 }
 
