@@ -111,11 +111,10 @@ __global__ __launch_bounds__(256) void grid_bound_kernel(GridArgs g, double* __r
     }
 }
 
-// one block: totals in a fixed order; scale = 2^e with bound * scale < 2^62
+// one block: totals in a fixed order; scale = 2^e with bound * scale < 2^61
 __global__ __launch_bounds__(256) void grid_total_kernel(const double* __restrict__ part_abs,
                                                          const double* __restrict__ part_w, int n_part,
-                                                         double* __restrict__ scale, double* __restrict__ norm,
-                                                         unsigned long long* __restrict__ grid, int64_t n_words) {
+                                                         double* __restrict__ scale, double* __restrict__ norm) {
     __shared__ double ra[256], rw[256];
     double sa = 0.0, sw = 0.0;
     for (int i = threadIdx.x; i < n_part; i += 256) {
@@ -138,8 +137,6 @@ __global__ __launch_bounds__(256) void grid_total_kernel(const double* __restric
         scale[0] = ldexp(1.0, 61 - e);
         norm[0] = rw[0];
     }
-    (void)grid;
-    (void)n_words;
 }
 
 __global__ void zero_words_kernel(unsigned long long* __restrict__ p, int64_t n) {
@@ -326,8 +323,7 @@ hipError_t launch_grid(const float2* vis, const int32_t* weights, const double* 
     hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(n_words, 256), 4096)), dim3(256),
                        0, stream, fixed, n_words);
     hipLaunchKernelGGL(grid_bound_kernel, dim3(n_part), dim3(256), 0, stream, g, part_abs, part_w, n_cross);
-    hipLaunchKernelGGL(grid_total_kernel, dim3(1), dim3(256), 0, stream, part_abs, part_w, n_part, scale, norm, fixed,
-                       n_words);
+    hipLaunchKernelGGL(grid_total_kernel, dim3(1), dim3(256), 0, stream, part_abs, part_w, n_part, scale, norm);
     if (n_cross > 0)
         hipLaunchKernelGGL(grid_kernel, dim3(n_part), dim3(256), 0, stream, g, scale, fixed, n_cross);
     hipLaunchKernelGGL(grid_to_float_kernel, dim3((unsigned)std::min<int64_t>(ceil_div((int64_t)N * N, 256), 4096)),

@@ -9,15 +9,15 @@
 //
 // Mapping (one workgroup = 16 receivers x a run of spectra, 16 waves):
 //  * FIR phase: wave w owns the four branches p = w + 16 j (j = 0..3).  Lane
-//    (il, jh, c) owns real component c of receiver i0 + il for the two
-//    branches j = 2 jh, 2 jh + 1.  The 16-deep window of each branch lives in
-//    registers and slides by one sample per spectrum; loads are coalesced
-//    rows of the time-major input.
-//  * The first radix-4 stage of the FFT (over j) runs in registers after two
-//    DPP exchanges inside each lane quad (partner component, partner branch
-//    pair); each quad lane then owns one k1 and applies the twiddle
-//    exp(-2 pi i p1 k1 / 64).  Results go to LDS as [spectrum][k1][p1][il]
-//    for 16 spectra.
+//    (il, j) owns both components of receiver i0 + il for branch j (one
+//    32-bit load per spectrum).  The 16-deep windows live in registers and
+//    slide by one sample per spectrum; loads are coalesced rows of the
+//    time-major input.
+//  * The first radix-4 stage of the FFT (over j) runs across each lane quad
+//    in two DPP exchanges (sums and differences with the lane at j ^ 2, then
+//    the +-1, +-i combinations with the lane at j ^ 1); quad lane j then owns
+//    k1 = the bit reverse of j and applies the twiddle exp(-2 pi i p1 k1 / 64).
+//    Results go to LDS as [spectrum][k1][p1][il] for 16 spectra.
 //  * FFT phase: a lane owns (receiver, spectrum, k1) and does the remaining
 //    16-point FFT over p1 in registers (radix-4 x radix-4), producing
 //    channels k = k1 + 4 k2.  Lanes are ordered so that each store writes
@@ -50,15 +50,16 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
 
-    // ---- FIR-phase roles: lane = il * 4 + jh * 2 + comp
-    const int comp = lane & 1, jh = (lane >> 1) & 1, il = lane >> 2;
+    // ---- FIR-phase roles: lane = il * 4 + j, branch p = p1 + 16 j of
+    // receiver i0 + il, both components (one 32-bit load per spectrum)
+    const int j = lane & 3, il = lane >> 2;
     // Receivers beyond N read receiver N-1 and spectra beyond S read the last
     // valid samples: every load is in bounds and unconditional (no load waits
     // on another); such lanes and spectra are never stored.
     const int rcv = min(i0 + il, N - 1);
     const int p1 = wv;
     const int row_stride = N * 2;
-    const int lane_off = (p1 + 32 * jh) * row_stride + rcv * 2 + comp;   // branch p1 + 16 (2 jh) at row 0
+    const int lane_off = (p1 + 16 * j) * row_stride + rcv * 2;          // branch p at row 0, re/im pair
     const int64_t spec_stride = (int64_t)kP * row_stride;               // int16 elements per spectrum row
 
     // taps staged in LDS as [branch][t]; each FIR phase reloads its 32 taps,
@@ -68,36 +69,37 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
         ltaps[p * kT + t] = taps[e];
     }
     lds_barrier();
-    const float4* tp0 = reinterpret_cast<const float4*>(ltaps + (p1 + 32 * jh) * kT);
-    const float4* tp1 = reinterpret_cast<const float4*>(ltaps + (p1 + 32 * jh + 16) * kT);
+    const float4* tp = reinterpret_cast<const float4*>(ltaps + (p1 + 16 * j) * kT);
 
-    // this quad lane produces k1 = comp + 2 jh
-    const int k1o = comp + 2 * jh;
-    // (uniform loads of the four candidates, then a per-lane select)
+    // radix-4 over j across the lane quad: step 1 (partner j ^ 2) gives
+    // u0+u2, u1+u3, u0-u2, u1-u3 in lanes 0..3, step 2 (partner j ^ 1)
+    // own * al + partner * be gives A[k1o], k1o the bit reverse of j
+    const int k1o = ((j & 1) << 1) | (j >> 1);
+    const float s1 = (j >> 1) ? -1.0f : 1.0f;
+    const float2 al = j == 0 ? make_float2(1.0f, 0.0f) : j == 1 ? make_float2(-1.0f, 0.0f)
+                    : j == 2 ? make_float2(1.0f, 0.0f) : make_float2(0.0f, 1.0f);
+    const float2 be = j == 2 ? make_float2(0.0f, -1.0f) : make_float2(1.0f, 0.0f);
+    // twiddle exp(-2 pi i p1 k1o / 64) (uniform loads of the four candidates, then a per-lane select)
     const float2 tw1 = tw.w[p1 & 63], tw2 = tw.w[(2 * p1) & 63], tw3 = tw.w[(3 * p1) & 63];
     const float2 tw_o = k1o == 0 ? make_float2(1.0f, 0.0f) : k1o == 1 ? tw1 : k1o == 2 ? tw2 : tw3;
-    // (-i)^k1 tw
-    const float2 rtw_o = k1o == 0 ? tw_o : k1o == 1 ? make_float2(tw_o.y, -tw_o.x)
-                       : k1o == 2 ? make_float2(-tw_o.x, -tw_o.y) : make_float2(-tw_o.y, tw_o.x);
-    const float sgn = (k1o & 1) ? -1.0f : 1.0f;
 
-    // sample x_p[m] of branch p1 + 16 (2 jh + jj) at spectrum-row m
-    // (wave-uniform 64-bit row pointer + 32-bit lane offset)
-    // raw int16 sample; converted to float only where it enters the window,
-    // so that a load in flight is not waited on before it is needed
-    auto ld = [&](int m, int jj) -> int {
+    // re/im pair of branch p at spectrum-row m (wave-uniform 64-bit row
+    // pointer + 32-bit lane offset); converted to float only where it enters
+    // the window, so that a load in flight is not waited on before it is needed
+    auto ld = [&](int m) -> int {
         const int16_t* rowp = xs + (int64_t)min(m, S + kT - 2) * spec_stride;
-        return rowp[jj * (16 * row_stride) + lane_off];
+        return *reinterpret_cast<const int*>(rowp + lane_off);
+    };
+    float win[2][16];
+    auto put = [&](int slot, int d) {
+        win[0][slot] = (float)(int)(short)(d & 0xFFFF);
+        win[1][slot] = (float)(d >> 16);
     };
 
     // history: window slot m % 16 holds x_p[m]; s_begin is a multiple of 16
-    float win[2][16];
 #pragma unroll
-    for (int m = 0; m < 15; ++m)
-#pragma unroll
-        for (int jj = 0; jj < 2; ++jj) win[jj][m] = (float)ld(s_begin + m, jj);
-#pragma unroll
-    for (int jj = 0; jj < 2; ++jj) win[jj][15] = 0.0f;
+    for (int m = 0; m < 15; ++m) put(m, ld(s_begin + m));
+    win[0][15] = win[1][15] = 0.0f;
 
     // ---- FFT-phase roles
     const int k1 = wv & 3, rh = (wv >> 2) & 1, bh = wv >> 3;
@@ -106,48 +108,36 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
     const int rf = i0 + ilf;
 
     // software pipeline of the per-spectrum loads, kDepth spectra ahead
-    int pf[kDepth][2];
-    auto fetch = [&](int s, int (&dst)[2]) {
+    int pf[kDepth];
 #pragma unroll
-        for (int jj = 0; jj < 2; ++jj) dst[jj] = ld(s + 15, jj);
-    };
-#pragma unroll
-    for (int d = 0; d < kDepth; ++d) fetch(s_begin + d, pf[d]);
+    for (int d = 0; d < kDepth; ++d) pf[d] = ld(s_begin + d + 15);
 
     for (int sg = s_begin; sg < s_end; sg += kSpectraPerPhase) {
-        float h[2][16];
+        float h[16];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const float4 a0 = tp0[v], a1 = tp1[v];
-            h[0][4 * v] = a0.x; h[0][4 * v + 1] = a0.y; h[0][4 * v + 2] = a0.z; h[0][4 * v + 3] = a0.w;
-            h[1][4 * v] = a1.x; h[1][4 * v + 1] = a1.y; h[1][4 * v + 2] = a1.z; h[1][4 * v + 3] = a1.w;
+            const float4 a0 = tp[v];
+            h[4 * v] = a0.x; h[4 * v + 1] = a0.y; h[4 * v + 2] = a0.z; h[4 * v + 3] = a0.w;
         }
 #pragma unroll
         for (int q = 0; q < kSpectraPerPhase; ++q) {
-#pragma unroll
-            for (int jj = 0; jj < 2; ++jj) win[jj][(q + 15) & 15] = (float)pf[q % kDepth][jj];
-            fetch(sg + q + kDepth, pf[q % kDepth]);
+            put((q + 15) & 15, pf[q % kDepth]);
+            pf[q % kDepth] = ld(sg + q + kDepth + 15);
             float u[2];
 #pragma unroll
-            for (int jj = 0; jj < 2; ++jj) {
+            for (int c = 0; c < 2; ++c) {
                 float acc = 0.0f;
 #pragma unroll
-                for (int t = 0; t < 16; ++t) acc = fmaf(h[jj][t], win[jj][(q + t) & 15], acc);
-                u[jj] = acc;
+                for (int t = 0; t < 16; ++t) acc = fmaf(h[t], win[c][(q + t) & 15], acc);
+                u[c] = acc;
             }
-            // u_j (j = 0..3) of this receiver, complex, gathered from the quad:
-            // lane (comp, jh) holds component comp of branches j = 2 jh + jj
-            const float2 u0 = make_float2(quad_bcast<0>(u[0]), quad_bcast<1>(u[0]));
-            const float2 u1 = make_float2(quad_bcast<0>(u[1]), quad_bcast<1>(u[1]));
-            const float2 u2 = make_float2(quad_bcast<2>(u[0]), quad_bcast<3>(u[0]));
-            const float2 u3 = make_float2(quad_bcast<2>(u[1]), quad_bcast<3>(u[1]));
-            // A[k1] = E + (-i)^k1 Od,  E = u0 + (-1)^k1 u2,  Od = u1 + (-1)^k1 u3;
-            // the output A[k1] tw = E tw + Od ((-i)^k1 tw)
-            const float2 E = make_float2(fmaf(sgn, u2.x, u0.x), fmaf(sgn, u2.y, u0.y));
-            const float2 Od = make_float2(fmaf(sgn, u3.x, u1.x), fmaf(sgn, u3.y, u1.y));
-            float2 o = cmul(E, tw_o);
-            o.x = fmaf(Od.x, rtw_o.x, fmaf(-Od.y, rtw_o.y, o.x));
-            o.y = fmaf(Od.x, rtw_o.y, fmaf(Od.y, rtw_o.x, o.y));
+            const float e0 = fmaf(s1, u[0], quad_xor<2>(u[0]));
+            const float e1 = fmaf(s1, u[1], quad_xor<2>(u[1]));
+            const float f0 = quad_xor<1>(e0), f1 = quad_xor<1>(e1);
+            float2 v;
+            v.x = al.x * e0 - al.y * e1 + be.x * f0 - be.y * f1;
+            v.y = al.x * e1 + al.y * e0 + be.x * f1 + be.y * f0;
+            const float2 o = cmul(v, tw_o);
             lds[q * kSStride + k1o * kKStride + p1 * 16 + il] = o;
             __builtin_amdgcn_sched_barrier(0);
         }

@@ -51,6 +51,14 @@ __device__ __forceinline__ void dft16(float2 (&a)[16]) {
     for (int ga = 0; ga < 4; ++ga) dft4(a[4 * ga], a[4 * ga + 1], a[4 * ga + 2], a[4 * ga + 3]);
 }
 
+// value of the lane at (this lane xor M) inside the quad, M = 1 or 2
+// (DPP quad_perm [1,0,3,2] or [2,3,0,1])
+template <int M>
+__device__ __forceinline__ float quad_xor(float v) {
+    constexpr int ctrl = M == 1 ? (1 | (0 << 2) | (3 << 4) | (2 << 6)) : (2 | (3 << 2) | (0 << 4) | (1 << 6));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xF, 0xF, false));
+}
+
 // value of lane L of this lane's quad (DPP quad_perm(L,L,L,L))
 template <int L>
 __device__ __forceinline__ float quad_bcast(float v) {

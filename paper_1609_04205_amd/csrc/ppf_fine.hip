@@ -66,14 +66,6 @@ struct FineArgs {
     float gain;
 };
 
-// value of lane L of this lane's quad, and of the lanes at xor 1 / xor 2
-template <int CTRL>
-__device__ __forceinline__ float dpp(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-constexpr int kQuadXor1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);   // quad_perm [1,0,3,2]
-constexpr int kQuadXor2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);   // quad_perm [2,3,0,1]
-
 template <int DT, bool kVec4>
 __global__ __launch_bounds__(kThreadsF) void ppf_fine_kernel(FineArgs a, Tw64 tw64) {
     __shared__ __attribute__((aligned(16))) float2 lds[kQF * kQS];
@@ -191,10 +183,10 @@ __global__ __launch_bounds__(kThreadsF) void ppf_fine_kernel(FineArgs a, Tw64 tw
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     // step 1: with the lane at j ^ 2
-                    const float e0 = fmaf(s1, u[r][0], dpp<kQuadXor2>(u[r][0]));
-                    const float e1 = fmaf(s1, u[r][1], dpp<kQuadXor2>(u[r][1]));
+                    const float e0 = fmaf(s1, u[r][0], quad_xor<2>(u[r][0]));
+                    const float e1 = fmaf(s1, u[r][1], quad_xor<2>(u[r][1]));
                     // step 2: with the lane at j ^ 1
-                    const float f0 = dpp<kQuadXor1>(e0), f1 = dpp<kQuadXor1>(e1);
+                    const float f0 = quad_xor<1>(e0), f1 = quad_xor<1>(e1);
                     float2 v;
                     v.x = al.x * e0 - al.y * e1 + be.x * f0 - be.y * f1;
                     v.y = al.x * e1 + al.y * e0 + be.x * f1 + be.y * f0;
