@@ -34,8 +34,11 @@ using namespace ppfk;
 
 constexpr int kNi = 16;                      // receivers per workgroup
 constexpr int kThreads = 1024;               // 16 waves
-constexpr int kKStride = 16 * 16 + 8;        // float2 per k1 row (+64 B: k1 rows start 16 banks apart)
-constexpr int kSStride = 4 * kKStride + 4;   // float2 per spectrum (+32 B: spectra start 8 banks apart)
+// LDS rows padded so that the FIR-phase stores (16 lanes: 4 receivers x 4 k1)
+// and the FFT-phase loads (16 lanes: 8 spectra x 2 receivers) hit 32
+// distinct banks: k1 rows start 8 banks apart, spectrum rows 4 banks apart
+constexpr int kKStride = 16 * 16 + 4;        // float2 per k1 row
+constexpr int kSStride = 4 * kKStride + 2;   // float2 per spectrum
 constexpr int kSpectraPerPhase = 16;
 constexpr int kChunk = 768;                  // spectra per workgroup, a multiple of 16
 constexpr int kDepth = 4;                    // spectra of loads in flight per lane (divides 16)
