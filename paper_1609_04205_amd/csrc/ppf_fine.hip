@@ -49,7 +49,7 @@ constexpr int kK1S = 64 * kNiF + 2;          // float2 per k1 row of the phase b
 constexpr int kQS = 4 * kK1S;                // float2 per spectrum of the phase buffer
 constexpr int kXR = 16 * kNiF;               // float2 per (spectrum, k2) row of the exchange buffer
 constexpr int kChunkF = 192;                 // spectra per workgroup, a multiple of 16
-constexpr int kDepthF = 4;                   // spectra of loads in flight per lane (divides 8)
+constexpr int kDepthF = 2;                   // spectra of loads in flight per lane (divides 8)
 static_assert(kQF * 16 * kXR <= kQF * kQS, "the exchange fits the phase buffer");
 static_assert(kChunkF % 16 == 0 && kQF % kDepthF == 0, "phase and pipeline shapes");
 
