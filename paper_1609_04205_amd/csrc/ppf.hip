@@ -7,22 +7,33 @@
 //   u[s][p] = sum_{t<16} h[t*64 + p] x[(s+t)*64 + p]
 //   y[s][k] = sum_{p<64} u[s][p] exp(-2 pi i k p / 64)
 //
-// Mapping (one workgroup = 16 receivers x a run of spectra, 16 waves):
-//  * FIR phase: wave w owns the four branches p = w + 16 j (j = 0..3).  Lane
-//    (il, j) owns both components of receiver i0 + il for branch j (one
-//    32-bit load per spectrum).  The 16-deep windows live in registers and
-//    slide by one sample per spectrum; loads are coalesced rows of the
-//    time-major input.
-//  * The first radix-4 stage of the FFT (over j) runs across each lane quad
-//    in two DPP exchanges (sums and differences with the lane at j ^ 2, then
-//    the +-1, +-i combinations with the lane at j ^ 1); quad lane j then owns
-//    k1 = the bit reverse of j and applies the twiddle exp(-2 pi i p1 k1 / 64).
-//    Results go to LDS as [spectrum][k1][p1][il] for 16 spectra.
+// Mapping (one workgroup = 16 receivers x a run of spectra, 8 waves):
+//  * FIR phase on the matrix cores.  For one branch p and a phase of 16
+//    spectra the filter is a banded matrix product: U[m][n] =
+//    sum_k H[m][k] X[k][n] over the 32 input times k of the phase's window
+//    (spectrum m uses times m .. m+15, so H[m][k] = h[(k-m)*64 + p] inside
+//    the band and 0 outside), n = the 16 receivers, one product for the real
+//    and one for the imaginary components.  It runs as fp16 MFMAs (16x16x32)
+//    on exact splits with float32 sums: each int16 sample is 256 hb + lo,
+//    entered as the fp16 parts hb and lo / 256 (both exact; the factor 256
+//    goes into the unscaling), and each tap, scaled by a power of two 2^E
+//    (per wave, so that the largest is near 2^15), is the sum of two fp16
+//    parts (22 significant bits, the rest below float32 rounding of the
+//    sums); 2^(8-E) is folded into the twiddles.  Wave w owns the eight
+//    branches p = p1 + 16 j, p1 in {w, w+8}; lane (n, g) keeps the band rows
+//    of H in registers and loads the int16 pairs of receiver n at 4 times per
+//    branch and phase (window slot k = 8 g + e <-> time 16 (e / 4) + 4 g +
+//    e % 4: the first half is the previous phase's second half, so every
+//    sample is loaded once).
+//  * The product leaves U for 4 spectra of receiver n in each lane, for all
+//    four branches p1 + 16 j, so the first radix-4 stage of the FFT (over j)
+//    is lane-local; then the twiddle exp(-2 pi i p1 k1 / 64).  Results go to
+//    LDS as [spectrum][k1][p1][receiver] for 16 spectra.
 //  * FFT phase: a lane owns (receiver, spectrum, k1) and does the remaining
 //    16-point FFT over p1 in registers (radix-4 x radix-4), producing
-//    channels k = k1 + 4 k2.  Lanes are ordered so that each store writes
-//    8 receivers x 8 spectra contiguously in the [k][block][receiver][slot]
-//    output layout.
+//    channels k = k1 + 4 k2; two such jobs per lane.  Lanes are ordered so
+//    that each store writes 8 receivers x 8 spectra contiguously in the
+//    [k][block][receiver][slot] output layout.
 #include <hip/hip_fp16.h>
 
 #include "afc_internal.h"
@@ -32,16 +43,30 @@ namespace afc {
 namespace {
 using namespace ppfk;
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef _Float16 v4h __attribute__((ext_vector_type(4)));
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+constexpr h2 kInv256 = {(_Float16)0.00390625f, (_Float16)0.00390625f};
+constexpr h2 kMinus4 = {(_Float16)-4.0f, (_Float16)-4.0f};
+constexpr h2 kMinus1152 = {(_Float16)-1152.0f, (_Float16)-1152.0f};
+
 constexpr int kNi = 16;                      // receivers per workgroup
-constexpr int kThreads = 1024;               // 16 waves
-// LDS rows padded so that the FIR-phase stores (16 lanes: 4 receivers x 4 k1)
+#ifndef AFC_PPF_WAVES
+#define AFC_PPF_WAVES 8
+#endif
+constexpr int kWaves = AFC_PPF_WAVES;        // 8 or 16
+constexpr int kThreads = 64 * kWaves;
+constexpr int kGrp = 16 / kWaves;            // branch groups p1 per wave
+constexpr int kFftJobs = 16 / kWaves;        // 16-point FFT jobs per lane and phase
+// LDS rows padded so that the FIR-phase stores (16 lanes: 16 receivers)
 // and the FFT-phase loads (16 lanes: 8 spectra x 2 receivers) hit 32
 // distinct banks: k1 rows start 8 banks apart, spectrum rows 4 banks apart
 constexpr int kKStride = 16 * 16 + 4;        // float2 per k1 row
 constexpr int kSStride = 4 * kKStride + 2;   // float2 per spectrum
 constexpr int kSpectraPerPhase = 16;
 constexpr int kChunk = 768;                  // spectra per workgroup, a multiple of 16
-constexpr int kDepth = 4;                    // spectra of loads in flight per lane (divides 16)
+constexpr int kTPad = 48;                    // taps of one branch with 16 zeros on each side
 
 // One workgroup: receivers [i0, i0+16) of one subband, spectra [s_begin, s_end).
 template <int DT>
@@ -53,99 +78,183 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
 
-    // ---- FIR-phase roles: lane = il * 4 + j, branch p = p1 + 16 j of
-    // receiver i0 + il, both components (one 32-bit load per spectrum)
-    const int j = lane & 3, il = lane >> 2;
-    // Receivers beyond N read receiver N-1 and spectra beyond S read the last
-    // valid samples: every load is in bounds and unconditional (no load waits
-    // on another); such lanes and spectra are never stored.
-    const int rcv = min(i0 + il, N - 1);
-    const int p1 = wv;
-    const int row_stride = N * 2;
-    const int lane_off = (p1 + 16 * j) * row_stride + rcv * 2;          // branch p at row 0, re/im pair
-    const int64_t spec_stride = (int64_t)kP * row_stride;               // int16 elements per spectrum row
+    // ---- FIR-phase roles: lane = 16 g + n; receiver n (clamped: receivers
+    // beyond N read receiver N-1 and are never stored), window k-group g
+    const int n = lane & 15, g = lane >> 4;
+    const int rcv = min(i0 + n, N - 1);
+    const unsigned row_bytes = (unsigned)N * 4u;                     // one time row of one branch
+    const unsigned time_bytes = (unsigned)kP * row_bytes;            // one time step, all branches
+    const int t_last = S + kT - 2;                                   // last input time row
+    const char* xb = reinterpret_cast<const char*>(xs);
 
-    // taps staged in LDS as [branch][t]; each FIR phase reloads its 32 taps,
-    // so they do not occupy registers during the FFT phase
-    for (int e = tid; e < kT * kP; e += kThreads) {
-        const int t = e / kP, p = e % kP;
-        ltaps[p * kT + t] = taps[e];
+    // taps staged in LDS as [branch][16 + t], zero for t outside 0..15, so
+    // that a band row of H reads straight from the table
+    for (int e = tid; e < kP * kTPad; e += kThreads) {
+        const int p = e / kTPad, t = e % kTPad - 16;
+        ltaps[e] = (t >= 0 && t < kT) ? taps[t * kP + p] : 0.0f;
     }
     lds_barrier();
-    const float4* tp = reinterpret_cast<const float4*>(ltaps + (p1 + 16 * j) * kT);
-
-    // radix-4 over j across the lane quad: step 1 (partner j ^ 2) gives
-    // u0+u2, u1+u3, u0-u2, u1-u3 in lanes 0..3, step 2 (partner j ^ 1)
-    // own * al + partner * be gives A[k1o], k1o the bit reverse of j
-    const int k1o = ((j & 1) << 1) | (j >> 1);
-    const float s1 = (j >> 1) ? -1.0f : 1.0f;
-    const float2 al = j == 0 ? make_float2(1.0f, 0.0f) : j == 1 ? make_float2(-1.0f, 0.0f)
-                    : j == 2 ? make_float2(1.0f, 0.0f) : make_float2(0.0f, 1.0f);
-    const float2 be = j == 2 ? make_float2(0.0f, -1.0f) : make_float2(1.0f, 0.0f);
-    // twiddle exp(-2 pi i p1 k1o / 64) (uniform loads of the four candidates, then a per-lane select)
-    const float2 tw1 = tw.w[p1 & 63], tw2 = tw.w[(2 * p1) & 63], tw3 = tw.w[(3 * p1) & 63];
-    const float2 tw_o = k1o == 0 ? make_float2(1.0f, 0.0f) : k1o == 1 ? tw1 : k1o == 2 ? tw2 : tw3;
-
-    // re/im pair of branch p at spectrum-row m (wave-uniform 64-bit row
-    // pointer + 32-bit lane offset); converted to float only where it enters
-    // the window, so that a load in flight is not waited on before it is needed
-    auto ld = [&](int m) -> int {
-        const int16_t* rowp = xs + (int64_t)min(m, S + kT - 2) * spec_stride;
-        return *reinterpret_cast<const int*>(rowp + lane_off);
-    };
-    float win[2][16];
-    auto put = [&](int slot, int d) {
-        win[0][slot] = (float)(int)(short)(d & 0xFFFF);
-        win[1][slot] = (float)(d >> 16);
-    };
-
-    // history: window slot m % 16 holds x_p[m]; s_begin is a multiple of 16
+    // scale 2^E for this wave's taps: the largest |h| of its eight branches
+    // lands in [2^14, 2^15), inside the fp16 range with room for the parts
+    float hmax = 0.0f;
 #pragma unroll
-    for (int m = 0; m < 15; ++m) put(m, ld(s_begin + m));
-    win[0][15] = win[1][15] = 0.0f;
+    for (int q = 0; q < kGrp; ++q) {
+        const int e = lane + 64 * q;                                 // 16 taps of each of 4 kGrp branches
+        const int br = e >> 4;
+        const int p = wv + kWaves * (br % kGrp) + 16 * (br / kGrp);
+        hmax = fmaxf(hmax, fabsf(ltaps[p * kTPad + 16 + (e & 15)]));
+    }
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) hmax = fmaxf(hmax, __shfl_xor(hmax, d));
+    int ex = 0;
+    (void)frexpf(hmax, &ex);
+    const int E = hmax > 0.0f ? min(max(15 - ex, -100), 100) : 0;
+    const float up = ldexpf(1.0f, E), down = ldexpf(1.0f, 8 - E);     // 2^8: the samples enter as x / 256
+    // band row m = n of H for this lane's k-group g, as two fp16 parts of
+    // h 2^E.  Slot e <-> time offset 16 (e / 4) + 4 g + e % 4, tap t =
+    // offset - n; for each i = e % 4 exactly one of the slots i and 4 + i is
+    // inside the band (slot i when 4 g + i >= n), so the lane keeps the 4
+    // taps of its band and a mask that places them.
+    v4h hc1[kGrp][4], hc2[kGrp][4];
+#pragma unroll
+    for (int gr = 0; gr < kGrp; ++gr)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int p = wv + kWaves * gr + 16 * j;
+                const int t = 4 * g + i - n + (4 * g + i >= n ? 0 : 16);
+                const float h = ltaps[p * kTPad + 16 + t] * up;
+                const _Float16 a = (_Float16)h;
+                hc1[gr][j][i] = a;
+                hc2[gr][j][i] = (_Float16)(h - (float)a);
+            }
+    unsigned band[2];                                               // halves of slots 0-3 inside the band
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+        band[q] = (4 * g + 2 * q >= n ? 0x0000FFFFu : 0u) | (4 * g + 2 * q + 1 >= n ? 0xFFFF0000u : 0u);
+    auto band_row = [&](v4h c) -> v8h {
+        const uint2 u = __builtin_bit_cast(uint2, c);
+        return __builtin_bit_cast(v8h, make_uint4(u.x & band[0], u.y & band[1], u.x & ~band[0], u.y & ~band[1]));
+    };
 
-    // ---- FFT-phase roles
-    const int k1 = wv & 3, rh = (wv >> 2) & 1, bh = wv >> 3;
+    // int16 (re, im) pairs of receiver rcv, branch p, at the 4 times
+    // t0 + 4 g + i of one half-window (rows beyond the input repeat the last
+    // row: they only feed spectra >= S, which are never stored as data)
+    unsigned toff[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) toff[i] = (unsigned)(4 * g + i) * time_bytes + (unsigned)rcv * 4u;
+    // One raw buffer per half-window with its scalar base at the first row:
+    // the per-lane offset (time and receiver) and the scalar one (branch)
+    // stay below 16 rows of 64 branches, far below 2^31 bytes.
+    auto load_half = [&](int (&r)[kGrp][4][4], int t0) {
+        const int tb = min(t0, t_last);
+        unsigned vo[4];
+        if (t0 + 15 <= t_last) {                                     // uniform: no row beyond the input
+#pragma unroll
+            for (int i = 0; i < 4; ++i) vo[i] = toff[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                vo[i] = (unsigned)(min(t0 + 4 * g + i, t_last) - tb) * time_bytes + (unsigned)rcv * 4u;
+        }
+#if defined(__HIP_DEVICE_COMPILE__)
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(xb + (int64_t)tb * time_bytes), (short)0, 0x7FFFFFFF, 0x00020000);
+#pragma unroll
+        for (int gr = 0; gr < kGrp; ++gr)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    r[gr][j][i] = (int)__builtin_amdgcn_raw_buffer_load_b32(
+                        rs, vo[i], (unsigned)(wv + kWaves * gr + 16 * j) * row_bytes, 0);
+#endif
+    };
+
+    // ---- FFT-phase roles (spectra 0-7 and 8-15: two jobs per lane with 8
+    // waves, one with 16)
+    const int k1 = wv & 3, rh = (wv >> 2) & 1;
     const int sl = lane & 7, ii = lane >> 3;
     const int ilf = rh * 8 + ii;
     const int rf = i0 + ilf;
 
-    // software pipeline of the per-spectrum loads, kDepth spectra ahead
-    int pf[kDepth];
+    // One phase of 16 spectra starting at sg; `lo` holds the window's first
+    // half (times sg ..), `hi` its second half (sg + 16 ..); `lo` is refilled
+    // with the next phase's second half (sg + 32 ..) once it is converted.
+    auto phase = [&](int sg, int (&lo)[kGrp][4][4], int (&hi)[kGrp][4][4]) {
+        // the masks pass through an empty asm each phase, so the expanded
+        // band rows (twice the registers of the compact taps) are formed per
+        // use instead of being hoisted out of the loop
+        __asm__ volatile("" : "+v"(band[0]), "+v"(band[1]));
 #pragma unroll
-    for (int d = 0; d < kDepth; ++d) pf[d] = ld(s_begin + d + 15);
-
-    for (int sg = s_begin; sg < s_end; sg += kSpectraPerPhase) {
-        float h[16];
+        for (int gr = 0; gr < kGrp; ++gr) {
+            const int p1 = wv + kWaves * gr;
+            v4f ur[4], ui[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const float4 a0 = tp[v];
-            h[4 * v] = a0.x; h[4 * v + 1] = a0.y; h[4 * v + 2] = a0.z; h[4 * v + 3] = a0.w;
-        }
+            for (int j = 0; j < 4; ++j) {
+                // samples x = 256 hb + lo as exact fp16 parts hb (the signed
+                // high byte) and lo / 256 (the unsigned low byte), so that the
+                // products sum to x / 256 (the 256 goes into the unscaling).
+                // Two times per register: a byte pair gathered by v_perm and
+                // placed in the mantissa of 1024 (fp16 bits 0x6400 | byte),
+                // then one packed fp16 operation, exact: lo: (1024 + lo) / 256
+                // - 4; hb: flipping the sign bit of the byte gives 1152 + hb.
+                v8h rh, rl, ih, il;
 #pragma unroll
-        for (int q = 0; q < kSpectraPerPhase; ++q) {
-            put((q + 15) & 15, pf[q % kDepth]);
-            pf[q % kDepth] = ld(sg + q + kDepth + 15);
-            float u[2];
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                float acc = 0.0f;
-#pragma unroll
-                for (int t = 0; t < 16; ++t) acc = fmaf(h[t], win[c][(q + t) & 15], acc);
-                u[c] = acc;
+                for (int q = 0; q < 4; ++q) {
+                    const unsigned wa = (unsigned)(q < 2 ? lo[gr][j][2 * q] : hi[gr][j][2 * q - 4]);
+                    const unsigned wb = (unsigned)(q < 2 ? lo[gr][j][2 * q + 1] : hi[gr][j][2 * q - 3]);
+                    const h2 vrl = __builtin_bit_cast(h2, __builtin_amdgcn_perm(wb, wa, 0x0C040C00u) | 0x64006400u);
+                    const h2 vil = __builtin_bit_cast(h2, __builtin_amdgcn_perm(wb, wa, 0x0C060C02u) | 0x64006400u);
+                    const h2 vrh = __builtin_bit_cast(h2, __builtin_amdgcn_perm(wb, wa, 0x0C050C01u) ^ 0x64806480u);
+                    const h2 vih = __builtin_bit_cast(h2, __builtin_amdgcn_perm(wb, wa, 0x0C070C03u) ^ 0x64806480u);
+                    const h2 rl2 = vrl * kInv256 + kMinus4, il2 = vil * kInv256 + kMinus4;
+                    const h2 rh2 = vrh + kMinus1152, ih2 = vih + kMinus1152;
+                    rl[2 * q] = rl2[0]; rl[2 * q + 1] = rl2[1];
+                    il[2 * q] = il2[0]; il[2 * q + 1] = il2[1];
+                    rh[2 * q] = rh2[0]; rh[2 * q + 1] = rh2[1];
+                    ih[2 * q] = ih2[0]; ih[2 * q + 1] = ih2[1];
+                }
+                const v8h a2 = band_row(hc2[gr][j]), a1 = band_row(hc1[gr][j]);
+                v4f ar = {0.0f, 0.0f, 0.0f, 0.0f}, ai = {0.0f, 0.0f, 0.0f, 0.0f};
+                ar = __builtin_amdgcn_mfma_f32_16x16x32_f16(a2, rl, ar, 0, 0, 0);
+                ai = __builtin_amdgcn_mfma_f32_16x16x32_f16(a2, il, ai, 0, 0, 0);
+                ar = __builtin_amdgcn_mfma_f32_16x16x32_f16(a2, rh, ar, 0, 0, 0);
+                ai = __builtin_amdgcn_mfma_f32_16x16x32_f16(a2, ih, ai, 0, 0, 0);
+                ar = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1, rl, ar, 0, 0, 0);
+                ai = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1, il, ai, 0, 0, 0);
+                ar = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1, rh, ar, 0, 0, 0);
+                ai = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1, ih, ai, 0, 0, 0);
+                ur[j] = ar;
+                ui[j] = ai;
+                // one branch at a time: keeps its operands' live ranges short
+                __builtin_amdgcn_sched_barrier(0);
             }
-            const float e0 = fmaf(s1, u[0], quad_xor<2>(u[0]));
-            const float e1 = fmaf(s1, u[1], quad_xor<2>(u[1]));
-            const float f0 = quad_xor<1>(e0), f1 = quad_xor<1>(e1);
-            float2 v;
-            v.x = al.x * e0 - al.y * e1 + be.x * f0 - be.y * f1;
-            v.y = al.x * e1 + al.y * e0 + be.x * f1 + be.y * f0;
-            const float2 o = cmul(v, tw_o);
-            lds[q * kSStride + k1o * kKStride + p1 * 16 + il] = o;
-            __builtin_amdgcn_sched_barrier(0);
+            if (gr == kGrp - 1) load_half(lo, sg + 32);
+            // radix-4 over j (lane-local), then the twiddle exp(-2 pi i p1 k1 / 64)
+            // times 2^(8-E) (exact)
+            const float2 w1 = tw.w[p1 & 63] * down, w2 = tw.w[(2 * p1) & 63] * down;
+            const float2 w3 = tw.w[(3 * p1) & 63] * down;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float2 u0 = make_float2(ur[0][r], ui[0][r]), u1 = make_float2(ur[1][r], ui[1][r]);
+                const float2 u2 = make_float2(ur[2][r], ui[2][r]), u3 = make_float2(ur[3][r], ui[3][r]);
+                const float2 s02 = u0 + u2, d02 = u0 - u2, s13 = u1 + u3, d13 = u1 - u3;
+                const float2 a0 = s02 + s13, a2 = s02 - s13;
+                const float2 a1 = make_float2(d02.x + d13.y, d02.y - d13.x);      // d02 - i d13
+                const float2 a3 = make_float2(d02.x - d13.y, d02.y + d13.x);      // d02 + i d13
+                float2* dst = lds + (4 * g + r) * kSStride + p1 * 16 + n;
+                dst[0] = a0 * down;
+                dst[kKStride] = cmul(a1, w1);
+                dst[2 * kKStride] = cmul(a2, w2);
+                dst[3 * kKStride] = cmul(a3, w3);
+            }
         }
         lds_barrier();
-        {
+#pragma unroll
+        for (int jb = 0; jb < kFftJobs; ++jb) {
+            const int bh = kFftJobs == 2 ? jb : wv >> 3;
             float2 a[16];
             const float2* src = lds + (8 * bh + sl) * kSStride + k1 * kKStride + ilf;
 #pragma unroll
@@ -158,7 +267,7 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
                 const unsigned lane_zoff = (blk * N + rf) * kSBlk + sl;     // samples within a channel
                 const int64_t ch_stride = (int64_t)Sb * N * kSBlk;          // samples per channel
                 // spectra >= S are stored as zeros (int8: through a zero gain)
-                const float g = live ? gain : 0.0f;
+                const float gq = live ? gain : 0.0f;
 #pragma unroll
                 for (int ga = 0; ga < 4; ++ga)
 #pragma unroll
@@ -167,11 +276,22 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
                         float2 y = a[4 * ga + de];
                         if constexpr (DT != AFC_I8)
                             if (!live) y = make_float2(0.0f, 0.0f);
-                        store_sample<DT>(zs, (int64_t)k * ch_stride, lane_zoff, y, g);
+                        store_sample<DT>(zs, (int64_t)k * ch_stride, lane_zoff, y, gq);
                     }
             }
+            __builtin_amdgcn_sched_barrier(0);
         }
         lds_barrier();
+    };
+
+    // s_begin is a multiple of 16
+    int r0[kGrp][4][4], r1[kGrp][4][4];
+    load_half(r0, s_begin);
+    load_half(r1, s_begin + 16);
+    for (int sg = s_begin; sg < s_end; sg += 2 * kSpectraPerPhase) {
+        phase(sg, r0, r1);
+        if (sg + kSpectraPerPhase >= s_end) break;
+        phase(sg + kSpectraPerPhase, r1, r0);
     }
 }
 
@@ -181,7 +301,7 @@ __global__ __launch_bounds__(kThreads) void ppf_kernel(const int16_t* __restrict
                                                        int64_t z_sb_bytes, int N, int S, int Sb, int n_groups,
                                                        int n_chunks, int total, int per_xcd, float gain) {
     __shared__ float2 lds[kSpectraPerPhase * kSStride];
-    __shared__ __attribute__((aligned(16))) float ltaps[kT * kP];
+    __shared__ __attribute__((aligned(16))) float ltaps[kP * kTPad];
     // workgroups go round-robin over the 8 XCDs: give each XCD a contiguous
     // range with neighbouring receiver groups (which share 128-byte lines of
     // the input rows) adjacent in time
@@ -203,7 +323,7 @@ __global__ __launch_bounds__(kThreads) void ppf_batched_kernel(const int16_t* __
                                                               int N, int n_groups, int n_chunks, int total,
                                                               int per_xcd) {
     __shared__ float2 lds[kSpectraPerPhase * kSStride];
-    __shared__ __attribute__((aligned(16))) float ltaps[kT * kP];
+    __shared__ __attribute__((aligned(16))) float ltaps[kP * kTPad];
     // XCD-aware order as in ppf_kernel: neighbouring receiver groups (which
     // share 128-byte lines of the input rows) run on one XCD at one time
     const int w = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
