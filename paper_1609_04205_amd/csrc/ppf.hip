@@ -7,7 +7,8 @@
 //   u[s][p] = sum_{t<16} h[t*64 + p] x[(s+t)*64 + p]
 //   y[s][k] = sum_{p<64} u[s][p] exp(-2 pi i k p / 64)
 //
-// Mapping (one workgroup = 16 receivers x a run of spectra, 8 waves):
+// Mapping (one workgroup = 16 receivers x a run of spectra, 16 waves; 8 in
+// the batched kernel):
 //  * FIR phase on the matrix cores.  For one branch p and a phase of 16
 //    spectra the filter is a banded matrix product: U[m][n] =
 //    sum_k H[m][k] X[k][n] over the 32 input times k of the phase's window
@@ -17,11 +18,12 @@
 //    on exact splits with float32 sums: each int16 sample is 256 hb + lo,
 //    entered as the fp16 parts hb and lo / 256 (both exact; the factor 256
 //    goes into the unscaling), and each tap, scaled by a power of two 2^E
-//    (per wave, so that the largest is near 2^15), is the sum of two fp16
-//    parts (22 significant bits, the rest below float32 rounding of the
-//    sums); 2^(8-E) is folded into the twiddles.  Wave w owns the eight
-//    branches p = p1 + 16 j, p1 in {w, w+8}; lane (n, g) keeps the band rows
-//    of H in registers and loads the int16 pairs of receiver n at 4 times per
+//    (per workgroup, so that the largest is near 2^15), is the sum of two
+//    fp16 parts (22 significant bits, the rest below float32 rounding of
+//    the sums); 2^(8-E) is folded into the twiddles.  Wave w owns the
+//    branches p = p1 + 16 j with p1 = w (16 waves) or p1 in {w, w+8} (8
+//    waves); lane (n, g) reads its band rows of H from tables of fp16 tap
+//    pairs in LDS and loads the int16 pairs of receiver n at 4 times per
 //    branch and phase (window slot k = 8 g + e <-> time 16 (e / 4) + 4 g +
 //    e % 4: the first half is the previous phase's second half, so every
 //    sample is loaded once).
@@ -31,9 +33,9 @@
 //    LDS as [spectrum][k1][p1][receiver] for 16 spectra.
 //  * FFT phase: a lane owns (receiver, spectrum, k1) and does the remaining
 //    16-point FFT over p1 in registers (radix-4 x radix-4), producing
-//    channels k = k1 + 4 k2; two such jobs per lane.  Lanes are ordered so
-//    that each store writes 8 receivers x 8 spectra contiguously in the
-//    [k][block][receiver][slot] output layout.
+//    channels k = k1 + 4 k2 (two such jobs per lane with 8 waves).  Lanes
+//    are ordered so that each store writes 8 receivers x 8 spectra
+//    contiguously in the [k][block][receiver][slot] output layout.
 #include <hip/hip_fp16.h>
 
 #include "afc_internal.h"
@@ -52,13 +54,10 @@ constexpr h2 kMinus4 = {(_Float16)-4.0f, (_Float16)-4.0f};
 constexpr h2 kMinus1152 = {(_Float16)-1152.0f, (_Float16)-1152.0f};
 
 constexpr int kNi = 16;                      // receivers per workgroup
-#ifndef AFC_PPF_WAVES
-#define AFC_PPF_WAVES 8
-#endif
-constexpr int kWaves = AFC_PPF_WAVES;        // 8 or 16
-constexpr int kThreads = 64 * kWaves;
-constexpr int kGrp = 16 / kWaves;            // branch groups p1 per wave
-constexpr int kFftJobs = 16 / kWaves;        // 16-point FFT jobs per lane and phase
+// Waves per workgroup: 16 (four branches per wave, 128 registers per lane)
+// for the single-type kernel; 8 (eight branches per wave, 256 registers) for
+// the batched kernel, which holds all three output types in one body.
+constexpr int kWavesMain = 16, kWavesBatched = 8;
 // LDS rows padded so that the FIR-phase stores (16 lanes: 16 receivers)
 // and the FFT-phase loads (16 lanes: 8 spectra x 2 receivers) hit 32
 // distinct banks: k1 rows start 8 banks apart, spectrum rows 4 banks apart
@@ -66,14 +65,18 @@ constexpr int kKStride = 16 * 16 + 4;        // float2 per k1 row
 constexpr int kSStride = 4 * kKStride + 2;   // float2 per spectrum
 constexpr int kSpectraPerPhase = 16;
 constexpr int kChunk = 768;                  // spectra per workgroup, a multiple of 16
-constexpr int kTPad = 48;                    // taps of one branch with 16 zeros on each side
+constexpr int kTT = 18;                      // tap pairs per branch and part (t = 0..17, cyclic)
 
 // One workgroup: receivers [i0, i0+16) of one subband, spectra [s_begin, s_end).
-template <int DT>
+template <int DT, int kWaves>
 __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const float* __restrict__ taps,
                                          void* __restrict__ zs, const Tw64& tw, int N, int S, int Sb,
                                          int i0, int s_begin, int s_end, float gain, float2* lds,
-                                         float* ltaps) {
+                                         unsigned* ltp) {
+    constexpr int kThreads = 64 * kWaves;
+    constexpr int kGrp = 16 / kWaves;            // branch groups p1 per wave
+    constexpr int kFftJobs = 16 / kWaves;        // 16-point FFT jobs per lane and phase
+    static_assert(kWaves == 8 || kWaves == 16, "8 or 16 waves");
     const int tid = threadIdx.x;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
@@ -87,88 +90,81 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
     const int t_last = S + kT - 2;                                   // last input time row
     const char* xb = reinterpret_cast<const char*>(xs);
 
-    // taps staged in LDS as [branch][16 + t], zero for t outside 0..15, so
-    // that a band row of H reads straight from the table
-    for (int e = tid; e < kP * kTPad; e += kThreads) {
-        const int p = e / kTPad, t = e % kTPad - 16;
-        ltaps[e] = (t >= 0 && t < kT) ? taps[t * kP + p] : 0.0f;
-    }
-    lds_barrier();
-    // scale 2^E for this wave's taps: the largest |h| of its eight branches
-    // lands in [2^14, 2^15), inside the fp16 range with room for the parts
+    // scale 2^E for the taps: the largest |h| lands in [2^14, 2^15), inside
+    // the fp16 range with room for the parts (one value per workgroup: each
+    // wave's maximum goes through the exchange buffer, unused until the
+    // first phase)
     float hmax = 0.0f;
-#pragma unroll
-    for (int q = 0; q < kGrp; ++q) {
-        const int e = lane + 64 * q;                                 // 16 taps of each of 4 kGrp branches
-        const int br = e >> 4;
-        const int p = wv + kWaves * (br % kGrp) + 16 * (br / kGrp);
-        hmax = fmaxf(hmax, fabsf(ltaps[p * kTPad + 16 + (e & 15)]));
-    }
+    for (int e = tid; e < kT * kP; e += kThreads) hmax = fmaxf(hmax, fabsf(taps[e]));
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) hmax = fmaxf(hmax, __shfl_xor(hmax, d));
+    float* wmax = reinterpret_cast<float*>(lds);
+    if (lane == 0) wmax[wv] = hmax;
+    lds_barrier();
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) hmax = fmaxf(hmax, wmax[w]);
     int ex = 0;
     (void)frexpf(hmax, &ex);
     const int E = hmax > 0.0f ? min(max(15 - ex, -100), 100) : 0;
     const float up = ldexpf(1.0f, E), down = ldexpf(1.0f, 8 - E);     // 2^8: the samples enter as x / 256
-    // band row m = n of H for this lane's k-group g, as two fp16 parts of
+    // Band row m = n of H for this lane's k-group g, as two fp16 parts of
     // h 2^E.  Slot e <-> time offset 16 (e / 4) + 4 g + e % 4, tap t =
     // offset - n; for each i = e % 4 exactly one of the slots i and 4 + i is
-    // inside the band (slot i when 4 g + i >= n), so the lane keeps the 4
-    // taps of its band and a mask that places them.
-    v4h hc1[kGrp][4], hc2[kGrp][4];
-#pragma unroll
-    for (int gr = 0; gr < kGrp; ++gr)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int p = wv + kWaves * gr + 16 * j;
-                const int t = 4 * g + i - n + (4 * g + i >= n ? 0 : 16);
-                const float h = ltaps[p * kTPad + 16 + t] * up;
-                const _Float16 a = (_Float16)h;
-                hc1[gr][j][i] = a;
-                hc2[gr][j][i] = (_Float16)(h - (float)a);
-            }
+    // inside the band (slot i when 4 g + i >= n), and its tap is t = (4 g - n
+    // + i) mod 16.  So the lane reads the 4 taps (d + i) mod 16, d = (4 g -
+    // n) mod 16, as two dwords of tables of tap pairs (part q of h[t] and of
+    // h[(t+1) mod 16], t = 0..17) and places them with a mask.
+    for (int e = tid; e < kP * kTT; e += kThreads) {
+        const int p = e / kTT, t = e % kTT;
+        const float ha = taps[(t & 15) * kP + p] * up, hb = taps[((t + 1) & 15) * kP + p] * up;
+        const _Float16 a1 = (_Float16)ha, b1 = (_Float16)hb;
+        const _Float16 a2 = (_Float16)(ha - (float)a1), b2 = (_Float16)(hb - (float)b1);
+        ltp[e] = __builtin_bit_cast(unsigned, h2{a1, b1});
+        ltp[kP * kTT + e] = __builtin_bit_cast(unsigned, h2{a2, b2});
+    }
+    lds_barrier();
+    const unsigned* tq0 = ltp + ((4 * g - n) & 15);
     unsigned band[2];                                               // halves of slots 0-3 inside the band
 #pragma unroll
     for (int q = 0; q < 2; ++q)
         band[q] = (4 * g + 2 * q >= n ? 0x0000FFFFu : 0u) | (4 * g + 2 * q + 1 >= n ? 0xFFFF0000u : 0u);
-    auto band_row = [&](v4h c) -> v8h {
-        const uint2 u = __builtin_bit_cast(uint2, c);
+    auto band_row = [&](uint2 u) -> v8h {
         return __builtin_bit_cast(v8h, make_uint4(u.x & band[0], u.y & band[1], u.x & ~band[0], u.y & ~band[1]));
     };
 
     // int16 (re, im) pairs of receiver rcv, branch p, at the 4 times
     // t0 + 4 g + i of one half-window (rows beyond the input repeat the last
     // row: they only feed spectra >= S, which are never stored as data)
-    unsigned toff[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) toff[i] = (unsigned)(4 * g + i) * time_bytes + (unsigned)rcv * 4u;
+    const unsigned toff = (unsigned)(4 * g) * time_bytes + (unsigned)rcv * 4u;
     // One raw buffer per half-window with its scalar base at the first row:
-    // the per-lane offset (time and receiver) and the scalar one (branch)
-    // stay below 16 rows of 64 branches, far below 2^31 bytes.
+    // the per-lane offset (time 4 g, receiver) and the scalar one (branch and
+    // time i) stay below 16 rows of 64 branches, far below 2^31 bytes.
     auto load_half = [&](int (&r)[kGrp][4][4], int t0) {
         const int tb = min(t0, t_last);
-        unsigned vo[4];
-        if (t0 + 15 <= t_last) {                                     // uniform: no row beyond the input
-#pragma unroll
-            for (int i = 0; i < 4; ++i) vo[i] = toff[i];
-        } else {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                vo[i] = (unsigned)(min(t0 + 4 * g + i, t_last) - tb) * time_bytes + (unsigned)rcv * 4u;
-        }
 #if defined(__HIP_DEVICE_COMPILE__)
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
             (void*)(xb + (int64_t)tb * time_bytes), (short)0, 0x7FFFFFFF, 0x00020000);
+        if (t0 + 15 <= t_last) {                                     // uniform: no row beyond the input
 #pragma unroll
-        for (int gr = 0; gr < kGrp; ++gr)
+            for (int gr = 0; gr < kGrp; ++gr)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < 4; ++j)
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    r[gr][j][i] = (int)__builtin_amdgcn_raw_buffer_load_b32(
-                        rs, vo[i], (unsigned)(wv + kWaves * gr + 16 * j) * row_bytes, 0);
+                    for (int i = 0; i < 4; ++i)
+                        r[gr][j][i] = (int)__builtin_amdgcn_raw_buffer_load_b32(
+                            rs, toff, (unsigned)(wv + kWaves * gr + 16 * j) * row_bytes + (unsigned)i * time_bytes, 0);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const unsigned vo = (unsigned)(min(t0 + 4 * g + i, t_last) - tb) * time_bytes + (unsigned)rcv * 4u;
+#pragma unroll
+                for (int gr = 0; gr < kGrp; ++gr)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        r[gr][j][i] = (int)__builtin_amdgcn_raw_buffer_load_b32(
+                            rs, vo, (unsigned)(wv + kWaves * gr + 16 * j) * row_bytes, 0);
+            }
+        }
 #endif
     };
 
@@ -183,10 +179,11 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
     // half (times sg ..), `hi` its second half (sg + 16 ..); `lo` is refilled
     // with the next phase's second half (sg + 32 ..) once it is converted.
     auto phase = [&](int sg, int (&lo)[kGrp][4][4], int (&hi)[kGrp][4][4]) {
-        // the masks pass through an empty asm each phase, so the expanded
-        // band rows (twice the registers of the compact taps) are formed per
-        // use instead of being hoisted out of the loop
-        __asm__ volatile("" : "+v"(band[0]), "+v"(band[1]));
+        // the table pointer and masks pass through an empty asm each phase,
+        // so the band rows are read and formed per use instead of being
+        // hoisted out of the loop into registers
+        const unsigned* tq = tq0;
+        __asm__ volatile("" : "+v"(tq), "+v"(band[0]), "+v"(band[1]));
 #pragma unroll
         for (int gr = 0; gr < kGrp; ++gr) {
             const int p1 = wv + kWaves * gr;
@@ -216,7 +213,9 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
                     rh[2 * q] = rh2[0]; rh[2 * q + 1] = rh2[1];
                     ih[2 * q] = ih2[0]; ih[2 * q + 1] = ih2[1];
                 }
-                const v8h a2 = band_row(hc2[gr][j]), a1 = band_row(hc1[gr][j]);
+                const int pt = (p1 + 16 * j) * kTT;
+                const v8h a1 = band_row(make_uint2(tq[pt], tq[pt + 2]));
+                const v8h a2 = band_row(make_uint2(tq[kP * kTT + pt], tq[kP * kTT + pt + 2]));
                 v4f ar = {0.0f, 0.0f, 0.0f, 0.0f}, ai = {0.0f, 0.0f, 0.0f, 0.0f};
                 ar = __builtin_amdgcn_mfma_f32_16x16x32_f16(a2, rl, ar, 0, 0, 0);
                 ai = __builtin_amdgcn_mfma_f32_16x16x32_f16(a2, il, ai, 0, 0, 0);
@@ -296,12 +295,12 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
 }
 
 template <int DT>
-__global__ __launch_bounds__(kThreads) void ppf_kernel(const int16_t* __restrict__ x, const float* __restrict__ taps,
+__global__ __launch_bounds__(64 * kWavesMain) void ppf_kernel(const int16_t* __restrict__ x, const float* __restrict__ taps,
                                                        void* __restrict__ z, Tw64 tw, int64_t x_sb_stride,
                                                        int64_t z_sb_bytes, int N, int S, int Sb, int n_groups,
                                                        int n_chunks, int total, int per_xcd, float gain) {
     __shared__ float2 lds[kSpectraPerPhase * kSStride];
-    __shared__ __attribute__((aligned(16))) float ltaps[kP * kTPad];
+    __shared__ __attribute__((aligned(16))) unsigned ltp[2 * kP * kTT];
     // workgroups go round-robin over the 8 XCDs: give each XCD a contiguous
     // range with neighbouring receiver groups (which share 128-byte lines of
     // the input rows) adjacent in time
@@ -312,18 +311,18 @@ __global__ __launch_bounds__(kThreads) void ppf_kernel(const int16_t* __restrict
     const int sb = w / (n_groups * n_chunks);
     const int s_begin = chunk * kChunk;
     const int s_end = min(S, s_begin + kChunk);
-    ppf_body<DT>(x + sb * x_sb_stride, taps, reinterpret_cast<char*>(z) + sb * z_sb_bytes, tw, N, S, Sb,
-                 grp * kNi, s_begin, s_end, gain, lds, ltaps);
+    ppf_body<DT, kWavesMain>(x + sb * x_sb_stride, taps, reinterpret_cast<char*>(z) + sb * z_sb_bytes, tw, N, S, Sb,
+                 grp * kNi, s_begin, s_end, gain, lds, ltp);
 }
 
 // Batched form: one launch over per-subband jobs with their own S, type and gain.
-__global__ __launch_bounds__(kThreads) void ppf_batched_kernel(const int16_t* __restrict__ x,
+__global__ __launch_bounds__(64 * kWavesBatched) void ppf_batched_kernel(const int16_t* __restrict__ x,
                                                               const float* __restrict__ taps, void* __restrict__ z,
                                                               Tw64 tw, const PpfItem* __restrict__ items,
                                                               int N, int n_groups, int n_chunks, int total,
                                                               int per_xcd) {
     __shared__ float2 lds[kSpectraPerPhase * kSStride];
-    __shared__ __attribute__((aligned(16))) float ltaps[kP * kTPad];
+    __shared__ __attribute__((aligned(16))) unsigned ltp[2 * kP * kTT];
     // XCD-aware order as in ppf_kernel: neighbouring receiver groups (which
     // share 128-byte lines of the input rows) run on one XCD at one time
     const int w = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
@@ -338,11 +337,11 @@ __global__ __launch_bounds__(kThreads) void ppf_batched_kernel(const int16_t* __
     const int16_t* xs = x + item.x_off;
     void* zs = reinterpret_cast<char*>(z) + item.z_off;
     if (item.dt == AFC_F32)
-        ppf_body<AFC_F32>(xs, taps, zs, tw, N, item.S, item.Sb, grp * kNi, s_begin, s_end, item.gain, lds, ltaps);
+        ppf_body<AFC_F32, kWavesBatched>(xs, taps, zs, tw, N, item.S, item.Sb, grp * kNi, s_begin, s_end, item.gain, lds, ltp);
     else if (item.dt == AFC_F16)
-        ppf_body<AFC_F16>(xs, taps, zs, tw, N, item.S, item.Sb, grp * kNi, s_begin, s_end, item.gain, lds, ltaps);
+        ppf_body<AFC_F16, kWavesBatched>(xs, taps, zs, tw, N, item.S, item.Sb, grp * kNi, s_begin, s_end, item.gain, lds, ltp);
     else
-        ppf_body<AFC_I8>(xs, taps, zs, tw, N, item.S, item.Sb, grp * kNi, s_begin, s_end, item.gain, lds, ltaps);
+        ppf_body<AFC_I8, kWavesBatched>(xs, taps, zs, tw, N, item.S, item.Sb, grp * kNi, s_begin, s_end, item.gain, lds, ltp);
 }
 
 }  // namespace
@@ -357,15 +356,15 @@ hipError_t launch_ppf(const PpfLaunch& a, hipStream_t stream) {
     const int64_t z_sb_bytes = a.z_sb_stride * sample_bytes(a.dt);
     switch (a.dt) {
         case AFC_F32:
-            hipLaunchKernelGGL(ppf_kernel<AFC_F32>, grid, dim3(kThreads), 0, stream, a.x, a.taps, a.z, tw,
+            hipLaunchKernelGGL(ppf_kernel<AFC_F32>, grid, dim3(64 * kWavesMain), 0, stream, a.x, a.taps, a.z, tw,
                                a.x_sb_stride, z_sb_bytes, a.N, a.S, a.Sb, n_groups, n_chunks, total, per_xcd, a.gain);
             break;
         case AFC_F16:
-            hipLaunchKernelGGL(ppf_kernel<AFC_F16>, grid, dim3(kThreads), 0, stream, a.x, a.taps, a.z, tw,
+            hipLaunchKernelGGL(ppf_kernel<AFC_F16>, grid, dim3(64 * kWavesMain), 0, stream, a.x, a.taps, a.z, tw,
                                a.x_sb_stride, z_sb_bytes, a.N, a.S, a.Sb, n_groups, n_chunks, total, per_xcd, a.gain);
             break;
         default:
-            hipLaunchKernelGGL(ppf_kernel<AFC_I8>, grid, dim3(kThreads), 0, stream, a.x, a.taps, a.z, tw,
+            hipLaunchKernelGGL(ppf_kernel<AFC_I8>, grid, dim3(64 * kWavesMain), 0, stream, a.x, a.taps, a.z, tw,
                                a.x_sb_stride, z_sb_bytes, a.N, a.S, a.Sb, n_groups, n_chunks, total, per_xcd, a.gain);
             break;
     }
@@ -382,7 +381,7 @@ hipError_t launch_ppf_batched(const int16_t* x, const float* taps, void* z_ws, c
     const int total = (int)total64;
     const int per_xcd = (int)ceil_div(total, 8);
     const dim3 grid((unsigned)(per_xcd * 8));
-    hipLaunchKernelGGL(ppf_batched_kernel, grid, dim3(kThreads), 0, stream, x, taps, z_ws, tw, items_dev, N,
+    hipLaunchKernelGGL(ppf_batched_kernel, grid, dim3(64 * kWavesBatched), 0, stream, x, taps, z_ws, tw, items_dev, N,
                        n_groups, n_chunks, total, per_xcd);
     return hipGetLastError();
 }
