@@ -36,10 +36,11 @@ PEAK_HBM_GBS = 8000.0
 PEAK_INT8_TOPS = 5000.0
 PEAK_FP16_TFLOPS = 2500.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
-# fp32 vector peak: 256 CU x 4 SIMD x 32 lanes x 2 flop (FMA) x 2.4 GHz = 157.3 TFLOP/s
-# (timing copies of the channeliser without its loads issue fp32 instructions
-# faster than 16 lanes per clock would allow)
-PEAK_FP32_VALU_TFLOPS = 256 * 4 * 32 * 2 * 2.4e9 / 1e12
+# fp32 vector peak (datasheet): 256 CU x 4 SIMD x 16 lanes x 2 (packed fp32) x
+# 2 flop (FMA) x 2.4 GHz = 157.3 TFLOP/s.  Without packed fp32 instructions,
+# which this library does not use, a wave64 FMA takes 4 cycles: 78.6 TFLOP/s
+# (a plain FMA loop measures 74.5 TFLOP/s).
+PEAK_FP32_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2 * 2.4e9 / 1e12
 
 
 def log(*a):
