@@ -97,8 +97,14 @@ __device__ __forceinline__ void tile_rc(int t, int& ti, int& tj) {
 // with kDiag also rowd, cold double [P][2][n_tiles][64]: the partial sums of
 // D_a = sum_b |M_ab|^2 |g_b|^2 over the full Hermitian matrix (the diagonal
 // of the Gauss-Newton normal matrix of the row-wise least-squares problem)
+// V and M element (channel ch, polarisation pol, baseline bl) at
+// ch * ch_stride + pol * pol_off + bl * el_stride float2: the correlator's
+// [P][Nbl][2][2] layout (nbl * 4, 3, 4) or the solver's compact XX / YY
+// copy [P][2][Nbl] (2 nbl, nbl, 1).
 template <bool kDiag>
-__global__ __launch_bounds__(kThreads) void cal_tiles_kernel(int Na, int P, int n_tiles, const float2* __restrict__ V,
+__global__ __launch_bounds__(kThreads) void cal_tiles_kernel(int Na, int P, int n_tiles, int64_t ch_stride,
+                                                             int64_t pol_off, int el_stride,
+                                                             const float2* __restrict__ V,
                                                              const float2* __restrict__ M, const float2* __restrict__ g,
                                                              double2* __restrict__ rowpart, double2* __restrict__ colpart,
                                                              float* __restrict__ losspart, double* __restrict__ rowd,
@@ -112,8 +118,8 @@ __global__ __launch_bounds__(kThreads) void cal_tiles_kernel(int Na, int P, int 
     const int tid = threadIdx.x, cb = tid & 63, rg = tid >> 6;
     const int b = tj * kTileA + cb;
     const int64_t nbl = (int64_t)Na * (Na + 1) / 2;
-    const float2* Vc = V + (int64_t)ch * nbl * 4 + pol * 3;   // [bl][2][2]: XX at 0, YY at 3
-    const float2* Mc = M + (int64_t)ch * nbl * 4 + pol * 3;
+    const float2* Vc = V + (int64_t)ch * ch_stride + pol * pol_off;
+    const float2* Mc = M + (int64_t)ch * ch_stride + pol * pol_off;
     const float2* gc = g + (int64_t)ch * Na * 2 + pol;        // [a][2]
     const float2 gb = b < Na ? gc[(int64_t)b * 2] : make_float2(0.0f, 0.0f);
 
@@ -128,7 +134,7 @@ __global__ __launch_bounds__(kThreads) void cal_tiles_kernel(int Na, int P, int 
         if (a < Na) {
             const float2 ga = gc[(int64_t)a * 2];
             if (b < Na && b <= a) {
-                const int64_t e = ((int64_t)a * (a + 1) / 2 + b) * 4;
+                const int64_t e = ((int64_t)a * (a + 1) / 2 + b) * el_stride;
                 const float2 v = Vc[e], mm = Mc[e];
                 const float2 R = residual(v, mm, ga, gb);
                 const float r2 = R.x * R.x + R.y * R.y;
@@ -258,6 +264,19 @@ __global__ void cal_reference_kernel(int Na, int P, const float2* __restrict__ g
     }
 }
 
+// XX and YY of V and M from [P][Nbl][2][2] into [P][2][Nbl] (one thread per
+// channel and baseline)
+__global__ void cal_compact_kernel(int64_t total, int64_t nbl, const float2* __restrict__ V,
+                                   const float2* __restrict__ M, float2* __restrict__ Vc, float2* __restrict__ Mc) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const int64_t ch = e / nbl, bl = e - ch * nbl;
+    Vc[2 * ch * nbl + bl] = V[4 * e];                           // XX
+    Vc[(2 * ch + 1) * nbl + bl] = V[4 * e + 3];                 // YY
+    Mc[2 * ch * nbl + bl] = M[4 * e];
+    Mc[(2 * ch + 1) * nbl + bl] = M[4 * e + 3];
+}
+
 }  // namespace
 
 size_t cal_workspace_bytes(int Na, int P) {
@@ -270,10 +289,14 @@ size_t cal_solve_workspace_bytes(int Na, int P) {
     const int nT = n_tiles_side(Na);
     const size_t n_tiles = (size_t)nT * (nT + 1) / 2;
     const size_t n_g = (size_t)P * Na * 2;
+    const size_t nbl = (size_t)Na * (Na + 1) / 2;
     // gradient workspace (rounded up to 256 B), row and column partials of D,
-    // D, the gradient, two gain buffers, the per-iteration loss
-    return ((cal_workspace_bytes(Na, P) + 255) & ~(size_t)255) + (size_t)P * 2 * n_tiles * kTileA * 2 * sizeof(double)
-           + n_g * (sizeof(double) + 3 * sizeof(float2)) + (size_t)P * 2 * sizeof(double);
+    // D, the gradient, two gain buffers, the per-iteration loss (rounded up
+    // to 256 B), the compact XX / YY copies of V and M
+    const size_t solver = (size_t)P * 2 * n_tiles * kTileA * 2 * sizeof(double) + n_g * (sizeof(double) + 3 * sizeof(float2))
+                          + (size_t)P * 2 * sizeof(double);
+    return ((cal_workspace_bytes(Na, P) + 255) & ~(size_t)255) + ((solver + 255) & ~(size_t)255)
+           + 2 * (size_t)P * 2 * nbl * sizeof(float2);
 }
 
 hipError_t launch_calibrate_solve(int Na, int P, const float2* V, const float2* M, float2* g, int n_iter,
@@ -293,12 +316,26 @@ hipError_t launch_calibrate_solve(int Na, int P, const float2* V, const float2* 
     float2* ga = grad + n_g;
     float2* gb = ga + n_g;
     double* it_loss = reinterpret_cast<double*>(gb + n_g);
+    // compact XX / YY copies of V and M: every iteration reads only what it
+    // uses, contiguously
+    const int64_t nbl = (int64_t)Na * (Na + 1) / 2;
+    const size_t solver = (size_t)P * 2 * n_tiles * kTileA * 2 * sizeof(double) + n_g * (sizeof(double) + 3 * sizeof(float2))
+                          + (size_t)P * 2 * sizeof(double);
+    float2* Vc = reinterpret_cast<float2*>(w2 + ((solver + 255) & ~(size_t)255));
+    float2* Mc = Vc + (size_t)P * 2 * nbl;
     hipError_t e = hipMemcpyAsync(ga, g, n_g * sizeof(float2), hipMemcpyDeviceToDevice, stream);
     if (e != hipSuccess) return e;
+    if (n_iter > 0) {
+        const int64_t total = (int64_t)P * nbl;
+        hipLaunchKernelGGL(cal_compact_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, stream, total, nbl,
+                           V, M, Vc, Mc);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     const unsigned ug = (unsigned)ceil_div((int64_t)n_g, 256);
     for (int it = 1; it <= n_iter; ++it) {
-        hipLaunchKernelGGL(cal_tiles_kernel<true>, dim3(n_tiles, P, 2), dim3(kThreads), 0, stream, Na, P, n_tiles, V,
-                           M, ga, rowpart, colpart, losspart, rowd, cold);
+        hipLaunchKernelGGL(cal_tiles_kernel<true>, dim3(n_tiles, P, 2), dim3(kThreads), 0, stream, Na, P, n_tiles,
+                           2 * nbl, nbl, 1, Vc, Mc, ga, rowpart, colpart, losspart, rowd, cold);
         hipLaunchKernelGGL(cal_reduce_kernel<true>, dim3((unsigned)ceil_div(Na, 256), P, 2), dim3(256), 0, stream,
                            Na, P, nT, n_tiles, rowpart, colpart, losspart, it_loss, grad, rowd, cold, D);
         hipLaunchKernelGGL(cal_update_kernel, dim3(ug), dim3(256), 0, stream, (int)n_g, ga, grad, D, gb,
@@ -322,8 +359,9 @@ hipError_t launch_calibrate(int Na, int P, const float2* V, const float2* M, con
     double2* rowpart = reinterpret_cast<double2*>(w);
     double2* colpart = rowpart + (size_t)P * 2 * n_tiles * kTileA;
     float* losspart = reinterpret_cast<float*>(colpart + (size_t)P * 2 * n_tiles * kTileA);
-    hipLaunchKernelGGL(cal_tiles_kernel<false>, dim3(n_tiles, P, 2), dim3(kThreads), 0, stream, Na, P, n_tiles, V, M,
-                       g, rowpart, colpart, losspart, nullptr, nullptr);
+    const int64_t nbl = (int64_t)Na * (Na + 1) / 2;
+    hipLaunchKernelGGL(cal_tiles_kernel<false>, dim3(n_tiles, P, 2), dim3(kThreads), 0, stream, Na, P, n_tiles,
+                       nbl * 4, (int64_t)3, 4, V, M, g, rowpart, colpart, losspart, nullptr, nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(cal_reduce_kernel<false>, dim3((unsigned)ceil_div(Na, 256), P, 2), dim3(256), 0, stream, Na, P,
