@@ -12,13 +12,14 @@
 // Every stored element therefore feeds one row sum (antenna a) and one
 // column sum (antenna b).
 //
-// Pass 1: one workgroup per 64 x 64 antenna tile of the lower triangle, per
-// channel and polarisation.  Each thread owns one column antenna and 16 rows;
+// Pass 1: one workgroup per 64 x 64 antenna tile of the lower triangle and
+// channel, both polarisations.  Each thread owns 4 rows x 4 columns;
 // the residual is formed in float32 with error-free product and sum
 // transformations, so that R keeps full float32 relative accuracy even when
-// V and G M G^H cancel to a few percent.  Row sums (wave reduction) and
-// column sums (LDS reduction) are accumulated in float64 and written to the
-// workspace; the tile's loss is a float32 tree sum.
+// V and G M G^H cancel to a few percent.  Row sums (shuffles over the 16
+// lanes of a row) and column sums (shuffles, then LDS across the waves) are
+// accumulated in float64 and written to the workspace; the tile's loss is a
+// float32 tree sum.
 // Pass 2: one thread per antenna adds its row and column partials over the
 // tiles in a fixed order (float64) and writes -4 x the sum; the first block
 // of each (channel, polarisation) adds the tile losses in a fixed order.
@@ -97,10 +98,17 @@ __device__ __forceinline__ void tile_rc(int t, int& ti, int& tj) {
 // with kDiag also rowd, cold double [P][2][n_tiles][64]: the partial sums of
 // D_a = sum_b |M_ab|^2 |g_b|^2 over the full Hermitian matrix (the diagonal
 // of the Gauss-Newton normal matrix of the row-wise least-squares problem)
+//
 // V and M element (channel ch, polarisation pol, baseline bl) at
 // ch * ch_stride + pol * pol_off + bl * el_stride float2: the correlator's
 // [P][Nbl][2][2] layout (nbl * 4, 3, 4) or the solver's compact XX / YY
 // copy [P][2][Nbl] (2 nbl, nbl, 1).
+//
+// Thread (r4, c4) of the tile owns rows 4 r4 .. 4 r4 + 3 and columns c4,
+// c4 + 16, c4 + 32, c4 + 48 for both polarisations (a load of 16 lanes
+// covers 16 consecutive baselines): a row's 16 column threads are 16
+// consecutive lanes (xor-shuffle sum in 4 steps), a column's 16 row threads
+// are 4 per wave (2 steps) times 4 waves (LDS).
 template <bool kDiag>
 __global__ __launch_bounds__(kThreads) void cal_tiles_kernel(int Na, int P, int n_tiles, int64_t ch_stride,
                                                              int64_t pol_off, int el_stride,
@@ -109,80 +117,132 @@ __global__ __launch_bounds__(kThreads) void cal_tiles_kernel(int Na, int P, int 
                                                              double2* __restrict__ rowpart, double2* __restrict__ colpart,
                                                              float* __restrict__ losspart, double* __restrict__ rowd,
                                                              double* __restrict__ cold) {
-    __shared__ double2 col_lds[4][kTileA];
-    __shared__ double cold_lds[kDiag ? 4 : 1][kTileA];
-    __shared__ float loss_lds[4];
-    const int t = blockIdx.x, ch = blockIdx.y, pol = blockIdx.z;
+    constexpr int NV = kDiag ? 3 : 2;                         // re, im (and D) per sum
+    __shared__ double col_lds[4][kTileA][2][NV];
+    __shared__ float loss_lds[4][2];
+    const int t = blockIdx.x, ch = blockIdx.y;
     int ti, tj;
     tile_rc(t, ti, tj);
-    const int tid = threadIdx.x, cb = tid & 63, rg = tid >> 6;
-    const int b = tj * kTileA + cb;
-    const int64_t nbl = (int64_t)Na * (Na + 1) / 2;
-    const float2* Vc = V + (int64_t)ch * ch_stride + pol * pol_off;
-    const float2* Mc = M + (int64_t)ch * ch_stride + pol * pol_off;
-    const float2* gc = g + (int64_t)ch * Na * 2 + pol;        // [a][2]
-    const float2 gb = b < Na ? gc[(int64_t)b * 2] : make_float2(0.0f, 0.0f);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int c4 = tid & 15, r4 = tid >> 4;
+    const float2* Vc = V + (int64_t)ch * ch_stride;
+    const float2* Mc = M + (int64_t)ch * ch_stride;
+    const float2* gc = g + (int64_t)ch * Na * 2;              // [a][2]
 
-    double cre = 0.0, cim = 0.0, cd = 0.0;
-    float lsum = 0.0f;
-    const int64_t slot = ((int64_t)(ch * 2 + pol) * n_tiles + t) * kTileA;
-#pragma unroll 4
-    for (int m = 0; m < kTileA / 4; ++m) {
-        const int r = rg + 4 * m;
-        const int a = ti * kTileA + r;                            // wave-uniform
-        double rre = 0.0, rim = 0.0, rd = 0.0;
-        if (a < Na) {
-            const float2 ga = gc[(int64_t)a * 2];
-            if (b < Na && b <= a) {
+    float2 gb[4][2];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int b = tj * kTileA + c4 + 16 * q;
+#pragma unroll
+        for (int p = 0; p < 2; ++p) gb[q][p] = b < Na ? gc[(int64_t)b * 2 + p] : make_float2(0.0f, 0.0f);
+    }
+    double col[4][2][NV];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) col[q][p][k] = 0.0;
+    float lsum[2] = {0.0f, 0.0f};
+    const int64_t slot0 = ((int64_t)(ch * 2) * n_tiles + t) * kTileA;            // pol 0
+    const int64_t slot1 = ((int64_t)(ch * 2 + 1) * n_tiles + t) * kTileA;        // pol 1
+
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = 4 * r4 + i;
+        const int a = ti * kTileA + r;
+        float2 ga[2];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) ga[p] = a < Na ? gc[(int64_t)a * 2 + p] : make_float2(0.0f, 0.0f);
+        double row[2][NV];
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) row[p][k] = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int b = tj * kTileA + c4 + 16 * q;
+            if (a < Na && b < Na && b <= a) {
                 const int64_t e = ((int64_t)a * (a + 1) / 2 + b) * el_stride;
-                const float2 v = Vc[e], mm = Mc[e];
-                const float2 R = residual(v, mm, ga, gb);
-                const float r2 = R.x * R.x + R.y * R.y;
-                lsum += a == b ? r2 : 2.0f * r2;
-                // t = R conj(M)
-                float tr = R.x * mm.x + R.y * mm.y;
-                float tm = R.y * mm.x - R.x * mm.y;
-                if (a == b) tm = 0.0f;                         // diagonal: Re(t) only
-                // row a: t g_b
-                rre = (double)(tr * gb.x - tm * gb.y);
-                rim = (double)(tr * gb.y + tm * gb.x);
-                if (a != b) {                                  // column b: conj(t) g_a
-                    cre += (double)(tr * ga.x + tm * ga.y);
-                    cim += (double)(tr * ga.y - tm * ga.x);
-                }
-                if constexpr (kDiag) {
-                    // |M|^2 |g_b|^2 to row a; |M|^2 |g_a|^2 to column b off the diagonal
-                    const double m2 = (double)mm.x * mm.x + (double)mm.y * mm.y;
-                    rd = m2 * ((double)gb.x * gb.x + (double)gb.y * gb.y);
-                    if (a != b) cd += m2 * ((double)ga.x * ga.x + (double)ga.y * ga.y);
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    const float2 v = Vc[e + p * pol_off], mm = Mc[e + p * pol_off];
+                    const float2 R = residual(v, mm, ga[p], gb[q][p]);
+                    const float r2 = R.x * R.x + R.y * R.y;
+                    lsum[p] += a == b ? r2 : 2.0f * r2;
+                    // t = R conj(M)
+                    const float tr = R.x * mm.x + R.y * mm.y;
+                    const float tm = a == b ? 0.0f : R.y * mm.x - R.x * mm.y;   // diagonal: Re(t) only
+                    // row a: t g_b
+                    row[p][0] += (double)(tr * gb[q][p].x - tm * gb[q][p].y);
+                    row[p][1] += (double)(tr * gb[q][p].y + tm * gb[q][p].x);
+                    if (a != b) {                                  // column b: conj(t) g_a
+                        col[q][p][0] += (double)(tr * ga[p].x + tm * ga[p].y);
+                        col[q][p][1] += (double)(tr * ga[p].y - tm * ga[p].x);
+                    }
+                    if constexpr (kDiag) {
+                        // |M|^2 |g_b|^2 to row a; |M|^2 |g_a|^2 to column b off the diagonal
+                        const double m2 = (double)mm.x * mm.x + (double)mm.y * mm.y;
+                        row[p][2] += m2 * ((double)gb[q][p].x * gb[q][p].x + (double)gb[q][p].y * gb[q][p].y);
+                        if (a != b) col[q][p][2] += m2 * ((double)ga[p].x * ga[p].x + (double)ga[p].y * ga[p].y);
+                    }
                 }
             }
         }
-        rre = wave_sum(rre);
-        rim = wave_sum(rim);
-        if (cb == 0) rowpart[slot + r] = make_double2(rre, rim);
-        if constexpr (kDiag) {
-            rd = wave_sum(rd);
-            if (cb == 0) rowd[slot + r] = rd;
-        }
-    }
-    col_lds[rg][cb] = make_double2(cre, cim);
-    if constexpr (kDiag) cold_lds[rg][cb] = cd;
-    lsum = wave_sumf(lsum);
-    if (cb == 0) loss_lds[rg] = lsum;
-    __syncthreads();
-    if (tid < kTileA) {
-        double sr = 0.0, si = 0.0;
+        // row sums over the 16 column threads (consecutive lanes)
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            sr += col_lds[w][tid].x;
-            si += col_lds[w][tid].y;
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int k = 0; k < NV; ++k)
+#pragma unroll
+                for (int off = 1; off < 16; off <<= 1) row[p][k] += __shfl_xor(row[p][k], off, 64);
+        if (c4 == 0) {
+            rowpart[slot0 + r] = make_double2(row[0][0], row[0][1]);
+            rowpart[slot1 + r] = make_double2(row[1][0], row[1][1]);
+            if constexpr (kDiag) {
+                rowd[slot0 + r] = row[0][2];
+                rowd[slot1 + r] = row[1][2];
+            }
         }
-        colpart[slot + tid] = make_double2(sr, si);
-        if constexpr (kDiag)
-            cold[slot + tid] = (cold_lds[0][tid] + cold_lds[1][tid]) + (cold_lds[2][tid] + cold_lds[3][tid]);
     }
-    if (tid == 0) losspart[(int64_t)(ch * 2 + pol) * n_tiles + t] = (loss_lds[0] + loss_lds[1]) + (loss_lds[2] + loss_lds[3]);
+    // column sums: the 4 row threads of this wave, then the 4 waves
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                col[q][p][k] += __shfl_xor(col[q][p][k], 16, 64);
+                col[q][p][k] += __shfl_xor(col[q][p][k], 32, 64);
+            }
+    if (lane < 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int k = 0; k < NV; ++k) col_lds[wv][c4 + 16 * q][p][k] = col[q][p][k];
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const float l = wave_sumf(lsum[p]);
+        if (lane == 0) loss_lds[wv][p] = l;
+    }
+    __syncthreads();
+    if (tid < 2 * kTileA) {
+        const int c = tid & (kTileA - 1), p = tid / kTileA;
+        const int64_t slot = p ? slot1 : slot0;
+        double s[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            s[k] = (col_lds[0][c][p][k] + col_lds[1][c][p][k]) + (col_lds[2][c][p][k] + col_lds[3][c][p][k]);
+        colpart[slot + c] = make_double2(s[0], s[1]);
+        if constexpr (kDiag) cold[slot + c] = s[2];
+    }
+    if (tid < 2) {
+        const int p = tid;
+        losspart[(int64_t)(ch * 2 + p) * n_tiles + t] = (loss_lds[0][p] + loss_lds[1][p]) + (loss_lds[2][p] + loss_lds[3][p]);
+    }
 }
 
 template <bool kDiag>
@@ -334,7 +394,7 @@ hipError_t launch_calibrate_solve(int Na, int P, const float2* V, const float2* 
     }
     const unsigned ug = (unsigned)ceil_div((int64_t)n_g, 256);
     for (int it = 1; it <= n_iter; ++it) {
-        hipLaunchKernelGGL(cal_tiles_kernel<true>, dim3(n_tiles, P, 2), dim3(kThreads), 0, stream, Na, P, n_tiles,
+        hipLaunchKernelGGL(cal_tiles_kernel<true>, dim3(n_tiles, P), dim3(kThreads), 0, stream, Na, P, n_tiles,
                            2 * nbl, nbl, 1, Vc, Mc, ga, rowpart, colpart, losspart, rowd, cold);
         hipLaunchKernelGGL(cal_reduce_kernel<true>, dim3((unsigned)ceil_div(Na, 256), P, 2), dim3(256), 0, stream,
                            Na, P, nT, n_tiles, rowpart, colpart, losspart, it_loss, grad, rowd, cold, D);
@@ -360,7 +420,7 @@ hipError_t launch_calibrate(int Na, int P, const float2* V, const float2* M, con
     double2* colpart = rowpart + (size_t)P * 2 * n_tiles * kTileA;
     float* losspart = reinterpret_cast<float*>(colpart + (size_t)P * 2 * n_tiles * kTileA);
     const int64_t nbl = (int64_t)Na * (Na + 1) / 2;
-    hipLaunchKernelGGL(cal_tiles_kernel<false>, dim3(n_tiles, P, 2), dim3(kThreads), 0, stream, Na, P, n_tiles,
+    hipLaunchKernelGGL(cal_tiles_kernel<false>, dim3(n_tiles, P), dim3(kThreads), 0, stream, Na, P, n_tiles,
                        nbl * 4, (int64_t)3, 4, V, M, g, rowpart, colpart, losspart, nullptr, nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
