@@ -101,7 +101,9 @@ AFC_API size_t afc_visibility_bytes(const afc_dims* d);
  * x     int16 [B][L][N][2], L = (S + T - 1) * P rows of N receivers, re/im
  *       interleaved (time-major; all receivers of a time sample contiguous).
  *       Rows beyond L are not read.
- * taps  float [T*P], in the order taps[t*P + p].  Any real filter.
+ * taps  float [T*P], in the order taps[t*P + p].  Any real finite filter; the
+ *       FIR uses each tap to 22 significant bits (after a power-of-two scale)
+ *       with exact products summed in float32, the FFT float32.
  * out   [B][P][Sb][N][8] complex of out_dtype, Sb = ceil(S/8): spectrum s of
  *       receiver i in channel k of subband b sits at block s/8, slot s%8.
  *       Slots of spectra >= S are written as zero.  Size from
