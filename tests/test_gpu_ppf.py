@@ -63,6 +63,29 @@ def test_f32_ragged(afc, dev, Na, S, B):
     assert np.all(pad == 0)
 
 
+@pytest.mark.parametrize("tap_scale", [1.0, 3.7e-4, 2.9e3])
+def test_f32_full_scale_samples_and_tap_scales(afc, dev, tap_scale):
+    """Samples over the whole int16 range (both bytes of every sample carry
+    signal) and taps far from unit scale: the FIR's exact sample split and
+    its power-of-two tap scaling keep the float32 bound."""
+    rng = np.random.default_rng(11)
+    Na, S = 8, 40
+    N = 2 * Na
+    L = (S + 15) * 64
+    xs = rng.integers(-32768, 32768, size=(1, L, N, 2)).astype(np.int16)
+    xs[0, :64, 0, 0] = -32768                       # extremes of the range
+    xs[0, 64:128, 1, 1] = 32767
+    taps = (W.prototype_taps() * tap_scale).astype(np.float32)
+    log(f"ppf f32 full-scale samples, taps x {tap_scale}")
+    z = afc.channelise(torch.from_numpy(xs).to(dev), torch.from_numpy(taps).to(dev), S, "f32")
+    y, _ = _natural(z, S)
+    ref = oracle.ppf_subband(xs[0], taps, 64, 16, S)
+    sigma = np.sqrt(np.mean(np.abs(ref) ** 2) / 2)
+    err = np.abs(y[0] - ref).max() / sigma
+    log(f"  max |dy|/sigma_y = {err:.3e}")
+    assert err <= 1e-5
+
+
 def test_f16_cfg1(afc, dev):
     cfg = W.CONFIGS[1]
     log("ppf f16 cfg1")
