@@ -159,14 +159,28 @@ __global__ __launch_bounds__(kThreads) void cal_tiles_kernel(int Na, int P, int 
         for (int p = 0; p < 2; ++p)
 #pragma unroll
             for (int k = 0; k < NV; ++k) row[p][k] = 0.0;
+        // all loads of the row first (clamped to element 0 where the
+        // element is outside the triangle; such elements contribute nothing)
+        float2 vv[4][2], mv[4][2];
+        bool ok[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int b = tj * kTileA + c4 + 16 * q;
-            if (a < Na && b < Na && b <= a) {
-                const int64_t e = ((int64_t)a * (a + 1) / 2 + b) * el_stride;
+            ok[q] = a < Na && b < Na && b <= a;
+            const int64_t e = ok[q] ? ((int64_t)a * (a + 1) / 2 + b) * el_stride : 0;
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                vv[q][p] = Vc[e + p * pol_off];
+                mv[q][p] = Mc[e + p * pol_off];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int b = tj * kTileA + c4 + 16 * q;
+            if (ok[q]) {
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
-                    const float2 v = Vc[e + p * pol_off], mm = Mc[e + p * pol_off];
+                    const float2 v = vv[q][p], mm = mv[q][p];
                     const float2 R = residual(v, mm, ga[p], gb[q][p]);
                     const float r2 = R.x * R.x + R.y * R.y;
                     lsum[p] += a == b ? r2 : 2.0f * r2;
