@@ -112,6 +112,8 @@ __global__ __launch_bounds__(kThreadsF) void ppf_fine_kernel(FineArgs a, Tw64 tw
     const float2 al = j == 0 ? make_float2(1.0f, 0.0f) : j == 1 ? make_float2(-1.0f, 0.0f)
                     : j == 2 ? make_float2(1.0f, 0.0f) : make_float2(0.0f, 1.0f);
     const float2 be = j == 2 ? make_float2(0.0f, -1.0f) : make_float2(1.0f, 0.0f);
+    // with the twiddle folded in (al and be are 1, -1, i or -i: exact)
+    const float2 alw = cmul(al, tw_o), bew = cmul(be, tw_o);
     float h[16];
 #pragma unroll
     for (int t = 0; t < 16; ++t) h[t] = a.taps[t * kPF + p];
@@ -187,10 +189,9 @@ __global__ __launch_bounds__(kThreadsF) void ppf_fine_kernel(FineArgs a, Tw64 tw
                     const float e1 = fmaf(s1, u[r][1], quad_xor<2>(u[r][1]));
                     // step 2: with the lane at j ^ 1
                     const float f0 = quad_xor<1>(e0), f1 = quad_xor<1>(e1);
-                    float2 v;
-                    v.x = al.x * e0 - al.y * e1 + be.x * f0 - be.y * f1;
-                    v.y = al.x * e1 + al.y * e0 + be.x * f1 + be.y * f0;
-                    o[r] = cmul(v, tw_o);
+                    // (al e + be f) exp(-2 pi i p1 k1o / 256)
+                    o[r].x = alw.x * e0 - alw.y * e1 + bew.x * f0 - bew.y * f1;
+                    o[r].y = alw.x * e1 + alw.y * e0 + bew.x * f1 + bew.y * f0;
                 }
                 float4* dst = reinterpret_cast<float4*>(lds + ql * kQS + k1o * kK1S + p1 * kNiF + 4 * rh);
                 dst[0] = make_float4(o[0].x, o[0].y, o[1].x, o[1].y);
