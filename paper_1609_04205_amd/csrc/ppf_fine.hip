@@ -16,9 +16,9 @@
 // 256 = 4 x 64 with p = p1 + 64 j, k = k1 + 4 k', k' = k2 + 16 k3.
 // One workgroup = 8 receivers x a run of spectra of one subband, 512 threads
 // (8 waves, two per SIMD, so that a lane may hold 256 registers): a row of
-// the time-major input gives the workgroup 32 contiguous bytes (the rate of
-// L1-to-L2 line requests, not HBM, bounds this kernel; 8 receivers per
-// workgroup halve it against 4).
+// the time-major input gives the workgroup 32 contiguous bytes (with 4
+// receivers per workgroup the rate of L1-to-L2 line requests bounded the
+// kernel; 8 halve it, and the vector instructions bound it now).
 //  * FIR phase: lane (p1, receiver half, j) owns branch p = p1 + 64 j of 4
 //    receivers: its taps (16 registers), the 16-deep windows of 4 receivers x
 //    2 components (128 registers), one 16-byte load per spectrum.  The radix-4
