@@ -13,11 +13,13 @@
 //  * grid_bound_kernel: per (subband, baseline) the sum of 2 w (|Re I| +
 //    |Im I|) over its gridded channels (a bound on any cell) and of 2 w (the
 //    normalisation), reduced in a fixed order.
-//  * grid_kernel: one thread per (subband, baseline).  Across the 64 channels
-//    of a subband a baseline's uv point moves by a small fraction of its
-//    length, so the thread accumulates its contributions in a 3 x 3 window
-//    of cells in registers (float64) and only adds the window to the grid
-//    when the point leaves it and at the end.  The grid accumulates in
+//  * grid_kernel: one workgroup per (subband, pair of 48-antenna blocks),
+//    one thread per baseline at a time.  Across the 64 channels of a
+//    subband a baseline's uv point moves by a small fraction of its length,
+//    so the thread accumulates its contributions in a 3 x 3 window of cells
+//    in registers (float64) and only adds the window when the point leaves
+//    it and at the end: to a 64 x 64-cell window in LDS around the blocks'
+//    mean separation (added to the grid once per workgroup), or to the grid.  The grid accumulates in
 //    64-bit fixed point (2^e scaled, e from the bound so that nothing can
 //    overflow): integer atomics make the result independent of the order of
 //    the additions, so the grid is bitwise reproducible.
@@ -144,23 +146,33 @@ __global__ void zero_words_kernel(unsigned long long* __restrict__ p, int64_t n)
         p[i] = 0ull;
 }
 
+// Gridding work: one workgroup per (subband, pair of 48-antenna blocks; a
+// block is one station of the array), so that the baselines of a workgroup
+// land in a compact patch of the uv plane.  Cells inside a 64 x 64 window
+// around the blocks' mean separation are summed in LDS (64-bit fixed point,
+// the same integers as the grid's atomics) and added to the grid once per
+// workgroup with their mirrors; cells outside the window (other layouts, a
+// patch larger than the window) go to the grid directly.  Integer sums: the
+// grid is the same whatever the routing.
+constexpr int kGB = 48;                      // antennas per block
+constexpr int kGW = 64;                      // LDS window side, cells
+constexpr int kGThreads = 1024;
+
 __device__ __forceinline__ void add_fixed(unsigned long long* cell, double v, double scale) {
     if (v != 0.0) atomicAdd(cell, (unsigned long long)llrint(v * scale));
 }
 
-__global__ __launch_bounds__(256) void grid_kernel(GridArgs g, const double* __restrict__ scale_p,
-                                                   unsigned long long* __restrict__ grid, int64_t n_cross) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= n_cross * g.B) return;
-    const int b = (int)(t / n_cross);
-    int a, c;
-    pair_of(t % n_cross, a, c);
+// one baseline a > c of subband b: its 64 channels through a 3 x 3 window of
+// cells in registers (float64), flushed to the LDS window or the grid when
+// the point leaves it and at the end
+__device__ __forceinline__ void grid_baseline(const GridArgs& g, int b, int a, int c, double scale,
+                                              unsigned long long* __restrict__ grid, unsigned long long* win,
+                                              int i0w, int j0w) {
     const double dx = g.pos[a * 2] - g.pos[c * 2], dy = g.pos[a * 2 + 1] - g.pos[c * 2 + 1];
     const double w = g.weights ? (double)g.weights[(int64_t)b * ((int64_t)g.Na * (g.Na + 1) / 2) +
                                                    (int64_t)a * (a + 1) / 2 + c]
                                : 1.0;
     if (w <= 0.0) return;
-    const double scale = scale_p[0];
     const int N = g.N;
     double wr[3][3], wi[3][3];
     int ai = 0, aj = 0;
@@ -172,13 +184,20 @@ __global__ __launch_bounds__(256) void grid_kernel(GridArgs g, const double* __r
             for (int x = 0; x < 3; ++x) {
                 const int i = ai + x, j = aj + y;
                 if (wr[y][x] == 0.0 && wi[y][x] == 0.0) continue;
-                // cells of gridded visibilities: 1 <= i, j <= N-1, mirrors likewise
-                unsigned long long* d = grid + ((int64_t)j * N + i) * 2;
-                unsigned long long* m = grid + ((int64_t)(N - j) * N + (N - i)) * 2;
-                add_fixed(d, wr[y][x], scale);
-                add_fixed(d + 1, wi[y][x], scale);
-                add_fixed(m, wr[y][x], scale);
-                add_fixed(m + 1, -wi[y][x], scale);
+                const unsigned li = (unsigned)(i - i0w), lj = (unsigned)(j - j0w);
+                if (li < (unsigned)kGW && lj < (unsigned)kGW) {
+                    unsigned long long* l = win + (lj * kGW + li) * 2;
+                    if (wr[y][x] != 0.0) atomicAdd(l, (unsigned long long)llrint(wr[y][x] * scale));
+                    if (wi[y][x] != 0.0) atomicAdd(l + 1, (unsigned long long)llrint(wi[y][x] * scale));
+                } else {
+                    // cells of gridded visibilities: 1 <= i, j <= N-1, mirrors likewise
+                    unsigned long long* d = grid + ((int64_t)j * N + i) * 2;
+                    unsigned long long* m = grid + ((int64_t)(N - j) * N + (N - i)) * 2;
+                    add_fixed(d, wr[y][x], scale);
+                    add_fixed(d + 1, wi[y][x], scale);
+                    add_fixed(m, wr[y][x], scale);
+                    add_fixed(m + 1, -wi[y][x], scale);
+                }
             }
     };
     for (int k = 0; k < kP; ++k) {
@@ -210,6 +229,88 @@ __global__ __launch_bounds__(256) void grid_kernel(GridArgs g, const double* __r
         }
     }
     if (open) flush();
+}
+
+__global__ __launch_bounds__(kGThreads) void grid_kernel(GridArgs g, const double* __restrict__ scale_p,
+                                                         unsigned long long* __restrict__ grid) {
+    __shared__ unsigned long long win[kGW * kGW * 2];
+    __shared__ double msum[2];
+    const int b = blockIdx.y;
+    int ba, bc;                                               // block pair ba >= bc
+    {
+        const int t = blockIdx.x;
+        int r = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+        while (r * (r + 1) / 2 > t) --r;
+        while ((r + 1) * (r + 2) / 2 <= t) ++r;
+        ba = r;
+        bc = t - r * (r + 1) / 2;
+    }
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int a0 = ba * kGB, c0 = bc * kGB;
+    const int nA = min(kGB, g.Na - a0), nC = min(kGB, g.Na - c0);
+    for (int e = tid; e < kGW * kGW * 2; e += kGThreads) win[e] = 0ull;
+    // window origin: the mean separation of the two blocks at the subband's
+    // middle channel (wave 0 sums the positions)
+    if (wv == 0) {
+        double sx = 0.0, sy = 0.0, tx = 0.0, ty = 0.0;
+        if (lane < nA) {
+            sx = g.pos[(a0 + lane) * 2];
+            sy = g.pos[(a0 + lane) * 2 + 1];
+        }
+        if (lane < nC) {
+            tx = g.pos[(c0 + lane) * 2];
+            ty = g.pos[(c0 + lane) * 2 + 1];
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            sx += __shfl_xor(sx, off, 64);
+            sy += __shfl_xor(sy, off, 64);
+            tx += __shfl_xor(tx, off, 64);
+            ty += __shfl_xor(ty, off, 64);
+        }
+        if (lane == 0) {
+            msum[0] = sx / nA - tx / nC;
+            msum[1] = sy / nA - ty / nC;
+        }
+    }
+    __syncthreads();
+    const double nu = g.freq[b * kP + kP / 2];
+    const double ur = msum[0] * nu / kC * g.inv_du + 0.5 * g.N;
+    const double vr = msum[1] * nu / kC * g.inv_du + 0.5 * g.N;
+    const int i0w = (int)floor(ur) - kGW / 2, j0w = (int)floor(vr) - kGW / 2;
+    const double scale = scale_p[0];
+
+    const int n_bl = ba == bc ? nA * (nA - 1) / 2 : nA * nC;
+    for (int q = tid; q < n_bl; q += kGThreads) {
+        int a, c;
+        if (ba == bc) {
+            pair_of(q, a, c);
+            a += a0;
+            c += c0;
+        } else {
+            a = a0 + q / nC;
+            c = c0 + q % nC;
+        }
+        grid_baseline(g, b, a, c, scale, grid, win, i0w, j0w);
+    }
+    __syncthreads();
+    const int N = g.N;
+    for (int e = tid; e < kGW * kGW; e += kGThreads) {
+        const long long re = (long long)win[e * 2], im = (long long)win[e * 2 + 1];
+        if (re == 0 && im == 0) continue;
+        // nonzero cells are cells of gridded visibilities: 1 <= i, j <= N-1
+        const int i = i0w + e % kGW, j = j0w + e / kGW;
+        unsigned long long* d = grid + ((int64_t)j * N + i) * 2;
+        unsigned long long* m = grid + ((int64_t)(N - j) * N + (N - i)) * 2;
+        if (re != 0) {
+            atomicAdd(d, (unsigned long long)re);
+            atomicAdd(m, (unsigned long long)re);
+        }
+        if (im != 0) {
+            atomicAdd(d + 1, (unsigned long long)im);
+            atomicAdd(m + 1, (unsigned long long)(-im));
+        }
+    }
 }
 
 // fixed point -> float2 grid (un-normalised), as the gridding's output
@@ -324,8 +425,10 @@ hipError_t launch_grid(const float2* vis, const int32_t* weights, const double* 
                        0, stream, fixed, n_words);
     hipLaunchKernelGGL(grid_bound_kernel, dim3(n_part), dim3(256), 0, stream, g, part_abs, part_w, n_cross);
     hipLaunchKernelGGL(grid_total_kernel, dim3(1), dim3(256), 0, stream, part_abs, part_w, n_part, scale, norm);
-    if (n_cross > 0)
-        hipLaunchKernelGGL(grid_kernel, dim3(n_part), dim3(256), 0, stream, g, scale, fixed, n_cross);
+    const int n_blk = (int)ceil_div(Na, kGB);
+    if (n_cross > 0 && B > 0)
+        hipLaunchKernelGGL(grid_kernel, dim3((unsigned)(n_blk * (n_blk + 1) / 2), (unsigned)B), dim3(kGThreads), 0,
+                           stream, g, scale, fixed);
     hipLaunchKernelGGL(grid_to_float_kernel, dim3((unsigned)std::min<int64_t>(ceil_div((int64_t)N * N, 256), 4096)),
                        dim3(256), 0, stream, fixed, scale, grid_out, (int64_t)N * N);
     return hipGetLastError();
