@@ -182,8 +182,9 @@ AFC_API int afc_channelise_fine(const afc_dims* d, const int16_t* x, const float
  *          that touches a flagged antenna gets V = 0 and weight 0.
  * vis      [B][P][Nbl][2][2] complex: float2 for AFC_F32 / AFC_F16 (float32
  *          accumulation), int2 for AFC_I8 (exact int32 accumulation; exact
- *          while 2 * 127^2 * S_b < 2^31).  Autocorrelations (i == j) have
- *          imaginary part exactly 0.
+ *          while 2 * 127^2 * S_b < 2^31), 16-byte aligned (else
+ *          AFC_ERR_INVALID).  Autocorrelations (i == j) have imaginary part
+ *          exactly 0.
  * weights  int32 [B][Nbl] or NULL: S_b, or 0 for flagged baselines.
  * ------------------------------------------------------------------------- */
 AFC_API int afc_correlate(const afc_dims* d, afc_dtype in_dtype, const void* z,
@@ -377,7 +378,8 @@ AFC_API int afc_image_from_grid(int32_t grid_size, const void* grid, const doubl
  *                    (subband b reads its first (S_b + T - 1) * P rows);
  *                    gain_per_sb host float [B] (used for int8 subbands);
  *                    flags uint8 [B][Na] or NULL; vis [B][P][Nbl][2][2]
- *                    (float2 or int2 per subband type); weights int32 [B][Nbl]
+ *                    (float2 or int2 per subband type, 16-byte aligned);
+ *                    weights int32 [B][Nbl]
  *                    or NULL.  The first launch on a stream captures the work
  *                    into a HIP graph; later launches with the same pointers
  *                    and stream replay it.

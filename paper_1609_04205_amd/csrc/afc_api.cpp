@@ -234,6 +234,7 @@ AFC_API int afc_correlate(const afc_dims* d, afc_dtype in_dtype, const void* z, 
     int rc = check_dims(d);
     if (rc != AFC_OK) return rc;
     if (!z || !vis) return fail(AFC_ERR_INVALID, "NULL pointer (z or vis)");
+    if (reinterpret_cast<uintptr_t>(vis) % 16) return fail(AFC_ERR_INVALID, "vis is not 16-byte aligned");
     if (!dtype_ok(in_dtype)) return fail(AFC_ERR_INVALID, "unknown in_dtype %d", (int)in_dtype);
     std::vector<int32_t> S(d->n_subbands, d->n_spectra);
     if (n_spectra_per_sb) {
@@ -722,6 +723,7 @@ AFC_API int afc_plan_launch(afc_plan* p, const int16_t* x, const float* taps, co
     g_err.clear();
     if (!p) return fail(AFC_ERR_INVALID, "plan is NULL");
     if (!x || !taps || !z_workspace || !vis) return fail(AFC_ERR_INVALID, "NULL pointer (x, taps, workspace or vis)");
+    if (reinterpret_cast<uintptr_t>(vis) % 16) return fail(AFC_ERR_INVALID, "vis is not 16-byte aligned");
     const int B = p->d.n_subbands;
     std::vector<float> gains(B, 1.0f);
     for (int b = 0; b < B; ++b) {

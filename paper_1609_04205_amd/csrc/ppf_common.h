@@ -60,12 +60,6 @@ __device__ __forceinline__ float quad_xor(float v) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xF, 0xF, false));
 }
 
-// value of lane L of this lane's quad (DPP quad_perm(L,L,L,L))
-template <int L>
-__device__ __forceinline__ float quad_bcast(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), L * 0x55, 0xF, 0xF, false));
-}
-
 // clamp(rint(fp32(y * gain)), -127, 127) as a two's-complement byte in the
 // low 8 bits.  Clamping before rounding gives the same value (the bounds are
 // integers); adding 1.5 * 2^23 rounds to an integer with ties to even and

@@ -128,6 +128,12 @@ __device__ __forceinline__ int swz(int r) {
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
+// value of the lane at (this lane xor 1) (DPP quad_perm [1,0,3,2])
+__device__ __forceinline__ int pair_swap(int v) {
+    return __builtin_amdgcn_mov_dpp(v, 1 | (0 << 2) | (3 << 4) | (2 << 6), 0xF, 0xF, false);
+}
+__device__ __forceinline__ float pair_swap(float v) { return __int_as_float(pair_swap(__float_as_int(v))); }
+
 // (re, im) -> (-im, re) on packed int8 pairs: swap the bytes of each pair,
 // negate each pair as a 16-bit number (its low byte becomes -im mod 256),
 // keep the low bytes of that and the high bytes (re) of the swapped word.
@@ -459,33 +465,41 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
 #pragma unroll
                 for (int k = 0; k < 8; ++k) frow[i][k] = fr[i][k] != 0;
         }
+        // Rows r, r + 1 of a lane are the two polarisations of one antenna a
+        // and lanes lr, lr ^ 1 the two of one antenna b, so a lane pair holds
+        // the four values of baseline (a, b).  The pair swaps one value so
+        // that the even lane owns (p, q) = (0, 0), (0, 1) and the odd lane
+        // (1, 0), (1, 1): each lane then stores 16 contiguous bytes and the
+        // pair the whole 32-byte baseline.  Validity, flags and the antenna
+        // indices are uniform over the pair.
+        using E = std::conditional_t<DT == AFC_I8, int, float>;
+        const bool odd = (lr & 1) != 0;
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             const int Jc = j0 + bn[J::IB[p]] * 32 + lr;
-            if (Jc >= N) continue;
-            const int b = Jc >> 1, qq = Jc & 1;
+            const int b = Jc >> 1;
             const bool fb = fcol[J::IB[p]];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
+            for (int r = 0; r < 16; r += 2) {
+                const E r0 = accR[p][r], i0v = accI[p][r], r1 = accR[p][r + 1], i1v = accI[p][r + 1];
+                // the even lane sends its p = 1 values, the odd lane its p = 0 values
+                const E yr = pair_swap(odd ? r0 : r1), yi = pair_swap(odd ? i0v : i1v);
+                E o0 = odd ? yr : r0, o1 = odd ? yi : i0v, o2 = odd ? r1 : yr, o3 = odd ? i1v : yi;
                 const int I = i0 + am[J::IA[p]] * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
-                if (I >= N) continue;
-                const int a = I >> 1, pp = I & 1;
-                if (a < b) continue;
-                const bool flagged = fb || frow[J::IA[p]][((r >> 2) << 1) | ((r >> 1) & 1)];
-                const int64_t bl = (int64_t)a * (a + 1) / 2 + b;
-                const int64_t e = bl * 4 + pp * 2 + qq;
-                if constexpr (DT == AFC_I8) {
-                    int re = accR[p][r], im = accI[p][r];
-                    if (I == Jc) im = 0;
-                    if (flagged) re = im = 0;
-                    reinterpret_cast<int2*>(vis_ch)[e] = make_int2(re, im);
-                } else {
-                    float re = accR[p][r], im = accI[p][r];
-                    if (I == Jc) im = 0.0f;
-                    if (flagged) re = im = 0.0f;
-                    reinterpret_cast<float2*>(vis_ch)[e] = make_float2(re, im);
+                const int a = I >> 1;
+                if (Jc >= N || I >= N || a < b) continue;
+                if (a == b) {             // inputs equal for (0, 0) and (1, 1)
+                    if (odd) o3 = E(0);
+                    else o1 = E(0);
                 }
-                if (write_weights && pp == 0 && qq == 0) w_sb[bl] = flagged ? 0 : S;
+                const bool flagged = fb || frow[J::IA[p]][((r >> 2) << 1) | ((r >> 1) & 1)];
+                if (flagged) o0 = o1 = o2 = o3 = E(0);
+                const int64_t bl = (int64_t)a * (a + 1) / 2 + b;
+                if constexpr (DT == AFC_I8)
+                    reinterpret_cast<int4*>(vis_ch)[bl * 2 + (odd ? 1 : 0)] = make_int4(o0, o1, o2, o3);
+                else
+                    reinterpret_cast<float4*>(vis_ch)[bl * 2 + (odd ? 1 : 0)] = make_float4(o0, o1, o2, o3);
+                if (write_weights && !odd) w_sb[bl] = flagged ? 0 : S;
             }
         }
     }

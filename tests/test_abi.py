@@ -65,6 +65,9 @@ def test_invalid_arguments_are_rejected_on_host(afc):
     assert lib.afc_correlate(C.byref(pol1), afc.AFC_F32, dummy, None, None, dummy, None, None) == -2
     s_bad = (C.c_int32 * 1)(2000)
     assert lib.afc_correlate(C.byref(d), afc.AFC_F32, dummy, C.cast(s_bad, C.c_void_p), None, dummy, None, None) == -1
+    odd = C.c_void_p(0x1008)           # 8- but not 16-byte aligned: the visibility stores are 16 bytes wide
+    assert lib.afc_correlate(C.byref(d), afc.AFC_F32, dummy, None, None, odd, None, None) == -1
+    assert b"aligned" in lib.afc_last_error()
     big = afc.dims(48, 1, 70000)       # int8 sums could overflow int32
     assert lib.afc_correlate(C.byref(big), afc.AFC_I8, dummy, None, None, dummy, None, None) == -2
     assert lib.afc_calibrate_grad(48, 4, dummy, dummy, dummy, dummy, None, None, None) == -4
