@@ -26,7 +26,8 @@
 //    pairs in LDS and loads the int16 pairs of receiver n at 4 times per
 //    branch and phase (window slot k = 8 g + e <-> time 16 (e / 4) + 4 g +
 //    e % 4: the first half is the previous phase's second half, so every
-//    sample is loaded once).
+//    sample is loaded and converted once; odd phases swap the two halves'
+//    slots, so that the converted parts stay in place in their registers).
 //  * The product leaves U for 4 spectra of receiver n in each lane, for all
 //    four branches p1 + 16 j, so the first radix-4 stage of the FFT (over j)
 //    is lane-local; then the twiddle exp(-2 pi i p1 k1 / 64).  Results go to
@@ -37,6 +38,8 @@
 //    are ordered so that each store writes 8 receivers x 8 spectra
 //    contiguously in the [k][block][receiver][slot] output layout.
 #include <hip/hip_fp16.h>
+
+#include <type_traits>
 
 #include "afc_internal.h"
 #include "ppf_common.h"
@@ -49,6 +52,7 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef _Float16 v4h __attribute__((ext_vector_type(4)));
 typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
 constexpr h2 kInv256 = {(_Float16)0.00390625f, (_Float16)0.00390625f};
 constexpr h2 kMinus4 = {(_Float16)-4.0f, (_Float16)-4.0f};
 constexpr h2 kMinus1152 = {(_Float16)-1152.0f, (_Float16)-1152.0f};
@@ -128,8 +132,11 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
 #pragma unroll
     for (int q = 0; q < 2; ++q)
         band[q] = (4 * g + 2 * q >= n ? 0x0000FFFFu : 0u) | (4 * g + 2 * q + 1 >= n ? 0xFFFF0000u : 0u);
-    auto band_row = [&](uint2 u) -> v8h {
-        return __builtin_bit_cast(v8h, make_uint4(u.x & band[0], u.y & band[1], u.x & ~band[0], u.y & ~band[1]));
+    // (with the window's halves swapped between slots 0-3 and 4-7 when odd)
+    auto band_row = [&](uint2 u, bool odd) -> v8h {
+        const uint2 in = make_uint2(u.x & band[0], u.y & band[1]), out = make_uint2(u.x & ~band[0], u.y & ~band[1]);
+        return odd ? __builtin_bit_cast(v8h, make_uint4(out.x, out.y, in.x, in.y))
+                   : __builtin_bit_cast(v8h, make_uint4(in.x, in.y, out.x, out.y));
     };
 
     // int16 (re, im) pairs of receiver rcv, branch p, at the 4 times
@@ -175,10 +182,53 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
     const int ilf = rh * 8 + ii;
     const int rf = i0 + ilf;
 
-    // One phase of 16 spectra starting at sg; `lo` holds the window's first
-    // half (times sg ..), `hi` its second half (sg + 16 ..); `lo` is refilled
-    // with the next phase's second half (sg + 32 ..) once it is converted.
-    auto phase = [&](int sg, int (&lo)[kGrp][4][4], int (&hi)[kGrp][4][4]) {
+    // Exact fp16 parts of the int16 (re, im) words wa, wb of two times
+    // (x = 256 hb + lo): o = {re lo / 256, im lo / 256, re hb, im hb}, each
+    // packed (time a, time b).  A byte pair gathered by v_perm is placed in
+    // the mantissa of 1024 (fp16 bits 0x6400 | byte), then one packed fp16
+    // operation, exact: lo: (1024 + lo) / 256 - 4; hb: flipping the sign bit
+    // of the byte gives 1152 + hb.  The products then sum to x / 256 (the 256
+    // goes into the unscaling).
+    auto convert2 = [](unsigned wa, unsigned wb, unsigned (&o)[4]) __attribute__((always_inline)) {
+        const h2 vrl = __builtin_bit_cast(h2, __builtin_amdgcn_perm(wb, wa, 0x0C040C00u) | 0x64006400u);
+        const h2 vil = __builtin_bit_cast(h2, __builtin_amdgcn_perm(wb, wa, 0x0C060C02u) | 0x64006400u);
+        const h2 vrh = __builtin_bit_cast(h2, __builtin_amdgcn_perm(wb, wa, 0x0C050C01u) ^ 0x64806480u);
+        const h2 vih = __builtin_bit_cast(h2, __builtin_amdgcn_perm(wb, wa, 0x0C070C03u) ^ 0x64806480u);
+        o[0] = __builtin_bit_cast(unsigned, vrl * kInv256 + kMinus4);
+        o[1] = __builtin_bit_cast(unsigned, vil * kInv256 + kMinus4);
+        o[2] = __builtin_bit_cast(unsigned, vrh + kMinus1152);
+        o[3] = __builtin_bit_cast(unsigned, vih + kMinus1152);
+    };
+    // Operand tuples of branch (gr, j): op[part] (re lo, im lo, re hb, im
+    // hb) holds slots 0-1, 2-3, 4-5, 6-7 in .x .. .w.  One half-window of
+    // samples w goes into .xy (second = false) or .zw (second = true).
+    auto convert_half = [&](const int (&w)[4], v4u (&op)[4], bool second) __attribute__((always_inline)) {
+        unsigned o0[4], o1[4];
+        convert2((unsigned)w[0], (unsigned)w[1], o0);
+        convert2((unsigned)w[2], (unsigned)w[3], o1);
+#pragma unroll
+        for (int part = 0; part < 4; ++part) {
+            if (second) {
+                op[part].z = o0[part];
+                op[part].w = o1[part];
+            } else {
+                op[part].x = o0[part];
+                op[part].y = o1[part];
+            }
+        }
+    };
+
+    // One phase of 16 spectra starting at sg.  Each sample is converted once
+    // and stays in its operand tuple for two phases; the window's halves
+    // alternate between the tuple halves: in an even phase slots 0-3 hold
+    // the first half (times sg ..) and the second half (sg + 16 ..) is
+    // converted from `raw` into slots 4-7; in an odd phase slots 4-7 hold the
+    // first half and the second goes into slots 0-3, and the band rows swap
+    // their halves to match.  `raw` is then refilled with the next phase's
+    // second half (sg + 32 ..).
+    auto phase = [&](int sg, int (&raw)[kGrp][4][4], v4u (&ops)[kGrp][4][4],
+                     auto odd_tag) __attribute__((always_inline)) {
+        constexpr bool kOdd = decltype(odd_tag)::value;
         // the table pointer and masks pass through an empty asm each phase,
         // so the band rows are read and formed per use instead of being
         // hoisted out of the loop into registers
@@ -190,32 +240,14 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
             v4f ur[4], ui[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                // samples x = 256 hb + lo as exact fp16 parts hb (the signed
-                // high byte) and lo / 256 (the unsigned low byte), so that the
-                // products sum to x / 256 (the 256 goes into the unscaling).
-                // Two times per register: a byte pair gathered by v_perm and
-                // placed in the mantissa of 1024 (fp16 bits 0x6400 | byte),
-                // then one packed fp16 operation, exact: lo: (1024 + lo) / 256
-                // - 4; hb: flipping the sign bit of the byte gives 1152 + hb.
-                v8h rh, rl, ih, il;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const unsigned wa = (unsigned)(q < 2 ? lo[gr][j][2 * q] : hi[gr][j][2 * q - 4]);
-                    const unsigned wb = (unsigned)(q < 2 ? lo[gr][j][2 * q + 1] : hi[gr][j][2 * q - 3]);
-                    const h2 vrl = __builtin_bit_cast(h2, __builtin_amdgcn_perm(wb, wa, 0x0C040C00u) | 0x64006400u);
-                    const h2 vil = __builtin_bit_cast(h2, __builtin_amdgcn_perm(wb, wa, 0x0C060C02u) | 0x64006400u);
-                    const h2 vrh = __builtin_bit_cast(h2, __builtin_amdgcn_perm(wb, wa, 0x0C050C01u) ^ 0x64806480u);
-                    const h2 vih = __builtin_bit_cast(h2, __builtin_amdgcn_perm(wb, wa, 0x0C070C03u) ^ 0x64806480u);
-                    const h2 rl2 = vrl * kInv256 + kMinus4, il2 = vil * kInv256 + kMinus4;
-                    const h2 rh2 = vrh + kMinus1152, ih2 = vih + kMinus1152;
-                    rl[2 * q] = rl2[0]; rl[2 * q + 1] = rl2[1];
-                    il[2 * q] = il2[0]; il[2 * q + 1] = il2[1];
-                    rh[2 * q] = rh2[0]; rh[2 * q + 1] = rh2[1];
-                    ih[2 * q] = ih2[0]; ih[2 * q + 1] = ih2[1];
-                }
+                convert_half(raw[gr][j], ops[gr][j], !kOdd);
+                const v8h rl = __builtin_bit_cast(v8h, ops[gr][j][0]);
+                const v8h il = __builtin_bit_cast(v8h, ops[gr][j][1]);
+                const v8h rh = __builtin_bit_cast(v8h, ops[gr][j][2]);
+                const v8h ih = __builtin_bit_cast(v8h, ops[gr][j][3]);
                 const int pt = (p1 + 16 * j) * kTT;
-                const v8h a1 = band_row(make_uint2(tq[pt], tq[pt + 2]));
-                const v8h a2 = band_row(make_uint2(tq[kP * kTT + pt], tq[kP * kTT + pt + 2]));
+                const v8h a1 = band_row(make_uint2(tq[pt], tq[pt + 2]), kOdd);
+                const v8h a2 = band_row(make_uint2(tq[kP * kTT + pt], tq[kP * kTT + pt + 2]), kOdd);
                 v4f ar = {0.0f, 0.0f, 0.0f, 0.0f}, ai = {0.0f, 0.0f, 0.0f, 0.0f};
                 ar = __builtin_amdgcn_mfma_f32_16x16x32_f16(a2, rl, ar, 0, 0, 0);
                 ai = __builtin_amdgcn_mfma_f32_16x16x32_f16(a2, il, ai, 0, 0, 0);
@@ -230,7 +262,7 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
                 // one branch at a time: keeps its operands' live ranges short
                 __builtin_amdgcn_sched_barrier(0);
             }
-            if (gr == kGrp - 1) load_half(lo, sg + 32);
+            if (gr == kGrp - 1) load_half(raw, sg + 32);
             // radix-4 over j (lane-local), then the twiddle exp(-2 pi i p1 k1 / 64)
             // times 2^(8-E) (exact)
             const float2 w1 = tw.w[p1 & 63] * down, w2 = tw.w[(2 * p1) & 63] * down;
@@ -283,14 +315,20 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
         lds_barrier();
     };
 
-    // s_begin is a multiple of 16
-    int r0[kGrp][4][4], r1[kGrp][4][4];
-    load_half(r0, s_begin);
-    load_half(r1, s_begin + 16);
+    // s_begin is a multiple of 16; the loop body holds an even and an odd
+    // phase
+    int raw[kGrp][4][4];
+    v4u ops[kGrp][4][4];
+    load_half(raw, s_begin);
+#pragma unroll
+    for (int gr = 0; gr < kGrp; ++gr)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) convert_half(raw[gr][j], ops[gr][j], false);
+    load_half(raw, s_begin + 16);
     for (int sg = s_begin; sg < s_end; sg += 2 * kSpectraPerPhase) {
-        phase(sg, r0, r1);
+        phase(sg, raw, ops, std::false_type{});
         if (sg + kSpectraPerPhase >= s_end) break;
-        phase(sg + kSpectraPerPhase, r1, r0);
+        phase(sg + kSpectraPerPhase, raw, ops, std::true_type{});
     }
 }
 
