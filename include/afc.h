@@ -110,7 +110,7 @@ AFC_API size_t afc_visibility_bytes(const afc_dims* d);
  *       afc_channelised_bytes().
  * out_dtype AFC_F32: the float32 value.  AFC_F16: rounded to nearest even.
  *       AFC_I8: per real component q = clamp(rint(y * requant_gain), -127,
- *       127), the product rounded to float32 and rint ties to even
+ *       127), the exact product rounded once, ties to even
  *       (Sec. "LOFAR Digital Processing": fewer bits per sample for more
  *       subbands); requant_gain is ignored for the other types.
  * Limits: P = 64, T = 16, n_pols = 2, L*N*2 < 2^31 per subband.

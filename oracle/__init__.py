@@ -142,7 +142,8 @@ def fine_subband(x: np.ndarray, taps: np.ndarray, Pf: int, T: int, S: int, tau: 
 # requantiser (Sec. "LOFAR Digital Processing", bit modes)
 # --------------------------------------------------------------------------
 def requant(y: np.ndarray, gain: float) -> np.ndarray:
-    """float32 values (any shape) -> int8, clamp(rint(fp32(y*gain)), +-127)."""
+    """float32 values (any shape) -> int8, clamp(rint(y*gain), +-127) of the
+    exact product (rounded once, ties to even)."""
     y = _c(y, np.float32)
     q = np.empty(y.shape, np.int8)
     _load().orc_requant(_ptr(y), y.size, float(np.float32(gain)), _ptr(q))

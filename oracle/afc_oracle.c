@@ -141,17 +141,19 @@ int orc_ppf_stream_direct(const int16_t *x, int64_t n_rows, int64_t row_stride, 
 /* ------------------------------------------------------------------------
  * Requantiser to int8 (Sec. "LOFAR Digital Processing": the bit modes trade
  * word width for dynamic range).  Per real component:
- *    v = y * gain            (one float32 product, round to nearest even)
+ *    v = y * gain            (the exact product: two float32 values
+ *                             multiply exactly in float64)
  *    q = clamp(rint(v), -127, 127)   (rint: nearest, ties to even)
- * The symmetric range keeps -q representable.
+ * so the product is rounded once, to the integer.  The symmetric range
+ * keeps -q representable.
  * ---------------------------------------------------------------------- */
 void orc_requant(const float *y, int64_t n, float gain, int8_t *q)
 {
     for (int64_t i = 0; i < n; ++i) {
-        float v = y[i] * gain;
-        float r = nearbyintf(v);
-        if (r > 127.0f) r = 127.0f;
-        if (r < -127.0f) r = -127.0f;
+        double v = (double)y[i] * (double)gain;
+        double r = nearbyint(v);
+        if (r > 127.0) r = 127.0;
+        if (r < -127.0) r = -127.0;
         q[i] = (int8_t)r;
     }
 }

@@ -111,6 +111,11 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
     (void)frexpf(hmax, &ex);
     const int E = hmax > 0.0f ? min(max(15 - ex, -100), 100) : 0;
     const float up = ldexpf(1.0f, E), down = ldexpf(1.0f, 8 - E);     // 2^8: the samples enter as x / 256
+    // The unscaling 2^(8-E) rides on the twiddles; for int8 output it goes
+    // into the gain instead (exact: a power of two), and the FFT runs on the
+    // scaled values.
+    const float unscale = DT == AFC_I8 ? 1.0f : down;
+    const float gain_u = DT == AFC_I8 ? gain * down : gain;
     // Band row m = n of H for this lane's k-group g, as two fp16 parts of
     // h 2^E.  Slot e <-> time offset 16 (e / 4) + 4 g + e % 4, tap t =
     // offset - n; for each i = e % 4 exactly one of the slots i and 4 + i is
@@ -264,9 +269,9 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
             }
             if (gr == kGrp - 1) load_half(raw, sg + 32);
             // radix-4 over j (lane-local), then the twiddle exp(-2 pi i p1 k1 / 64)
-            // times 2^(8-E) (exact)
-            const float2 w1 = tw.w[p1 & 63] * down, w2 = tw.w[(2 * p1) & 63] * down;
-            const float2 w3 = tw.w[(3 * p1) & 63] * down;
+            // times the unscaling (exact)
+            const float2 w1 = tw.w[p1 & 63] * unscale, w2 = tw.w[(2 * p1) & 63] * unscale;
+            const float2 w3 = tw.w[(3 * p1) & 63] * unscale;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const float2 u0 = make_float2(ur[0][r], ui[0][r]), u1 = make_float2(ur[1][r], ui[1][r]);
@@ -276,7 +281,7 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
                 const float2 a1 = make_float2(d02.x + d13.y, d02.y - d13.x);      // d02 - i d13
                 const float2 a3 = make_float2(d02.x - d13.y, d02.y + d13.x);      // d02 + i d13
                 float2* dst = lds + (4 * g + r) * kSStride + p1 * 16 + n;
-                dst[0] = a0 * down;
+                dst[0] = DT == AFC_I8 ? a0 : a0 * down;
                 dst[kKStride] = cmul(a1, w1);
                 dst[2 * kKStride] = cmul(a2, w2);
                 dst[3 * kKStride] = cmul(a3, w3);
@@ -298,7 +303,7 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
                 const unsigned lane_zoff = (blk * N + rf) * kSBlk + sl;     // samples within a channel
                 const int64_t ch_stride = (int64_t)Sb * N * kSBlk;          // samples per channel
                 // spectra >= S are stored as zeros (int8: through a zero gain)
-                const float gq = live ? gain : 0.0f;
+                const float gq = live ? gain_u : 0.0f;
 #pragma unroll
                 for (int ga = 0; ga < 4; ++ga)
 #pragma unroll

@@ -60,14 +60,16 @@ __device__ __forceinline__ float quad_xor(float v) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xF, 0xF, false));
 }
 
-// clamp(rint(fp32(y * gain)), -127, 127) as a two's-complement byte in the
-// low 8 bits.  Clamping before rounding gives the same value (the bounds are
-// integers); adding 1.5 * 2^23 rounds to an integer with ties to even and
-// leaves it in the low mantissa bits.
+// clamp(rint(y * gain), -127, 127) of the exact product (one rounding, ties
+// to even) as a two's-complement byte in the low 8 bits.  One fused
+// multiply-add y * gain + 1.5 * 2^23 rounds the exact product to an integer
+// (the result's unit in the last place is 1 while |y * gain| < 2^22; beyond
+// that it is far outside the clamp) and leaves it in the low mantissa bits;
+// the clamp then acts on the offset value.
 __device__ __forceinline__ unsigned requant_bits(float y, float gain) {
-    const float v = __fmul_rn(y, gain);                        // one float32 product
-    const float c = __builtin_amdgcn_fmed3f(v, -127.0f, 127.0f);
-    return __float_as_uint(__fadd_rn(c, 12582912.0f));
+    constexpr float kMagic = 12582912.0f;                      // 1.5 * 2^23
+    const float v = __builtin_fmaf(y, gain, kMagic);
+    return __float_as_uint(__builtin_amdgcn_fmed3f(v, kMagic - 127.0f, kMagic + 127.0f));
 }
 
 // store at sample index base + off (base wave-uniform, off per lane) with a

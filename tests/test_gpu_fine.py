@@ -111,7 +111,8 @@ def test_i8_requant(afc, dev):
     q = z8.cpu().numpy()
     y32 = z32.cpu().numpy()
     # the int8 output is the requantised float32 output of the same kernel
-    ref_q = np.clip(np.rint(y32 * np.float32(gain)), -127, 127).astype(np.int8)
+    # (the exact product, exact in float64, rounded once)
+    ref_q = np.clip(np.rint(y32.astype(np.float64) * np.float64(np.float32(gain))), -127, 127).astype(np.int8)
     np.testing.assert_array_equal(q, ref_q)
     # against the float64 oracle: at most one step, only next to a rounding boundary
     yq, _ = _natural(z8.float(), S)

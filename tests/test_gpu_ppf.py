@@ -111,9 +111,9 @@ def test_i8_requant_cfg1(afc, dev):
     torch.cuda.synchronize()
     q = z8.cpu().numpy()
     y32 = z32.cpu().numpy()
-    # property: the int8 output is the requantised float32 output of the same kernel
-    ref_q = np.clip(np.rint(y32 * np.float32(gain)), -127, 127).astype(np.int8)
-    assert (y32 * np.float32(gain)).dtype == np.float32
+    # property: the int8 output is the requantised float32 output of the same
+    # kernel (the exact product, exact in float64, rounded once)
+    ref_q = np.clip(np.rint(y32.astype(np.float64) * np.float64(np.float32(gain))), -127, 127).astype(np.int8)
     np.testing.assert_array_equal(q, ref_q)
     assert q.min() >= -127
     # against the float64 oracle: at most one step, and only next to a rounding boundary

@@ -169,12 +169,17 @@ def test_requant_ties_and_clamp():
                           -126, -127, -127, 0, 0]
 
 
-def test_requant_matches_float32_rint():
+def test_requant_rounds_the_exact_product_once():
     rng = np.random.default_rng(5)
     y = (rng.standard_normal(200000) * 300).astype(np.float32)
     gain = np.float32(0.1273)
     q = oracle.requant(y, float(gain))
-    ref = np.clip(np.rint(y * gain), -127, 127).astype(np.int8)    # float32 * float32 in numpy
-    assert (y * gain).dtype == np.float32
+    # a float32 x float32 product is exact in float64 (48 significant bits)
+    ref = np.clip(np.rint(y.astype(np.float64) * np.float64(gain)), -127, 127).astype(np.int8)
     np.testing.assert_array_equal(q, ref)
     assert q.min() >= -127
+    # a double-rounding case: 7.5 * fp32(1/3) = 2.50000007..., which float32
+    # rounds to 2.5 (then to 2, ties to even); the exact product rounds to 3
+    g3 = np.float32(1.0 / 3.0)
+    assert np.rint(np.float32(7.5) * g3) == 2.0
+    assert oracle.requant(np.array([7.5, -7.5], np.float32), float(g3)).tolist() == [3, -3]
