@@ -132,7 +132,7 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
         ltp[kP * kTT + e] = __builtin_bit_cast(unsigned, h2{a2, b2});
     }
     lds_barrier();
-    const unsigned* tq0 = ltp + ((4 * g - n) & 15);
+    const int tq0 = (4 * g - n) & 15;                             // this lane's first tap pair
     unsigned band[2];                                               // halves of slots 0-3 inside the band
 #pragma unroll
     for (int q = 0; q < 2; ++q)
@@ -234,11 +234,15 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
     auto phase = [&](int sg, int (&raw)[kGrp][4][4], v4u (&ops)[kGrp][4][4],
                      auto odd_tag) __attribute__((always_inline)) {
         constexpr bool kOdd = decltype(odd_tag)::value;
-        // the table pointer and masks pass through an empty asm each phase,
-        // so the band rows are read and formed per use instead of being
-        // hoisted out of the loop into registers
-        const unsigned* tq = tq0;
-        __asm__ volatile("" : "+v"(tq), "+v"(band[0]), "+v"(band[1]));
+        // the table index and masks pass through an empty asm each phase, so
+        // the band rows are read and formed per use instead of being hoisted
+        // out of the loop into registers (the index, not the pointer: a
+        // pointer out of an asm loses its LDS address space, and the reads
+        // would become flat loads that wait for every outstanding global
+        // access)
+        int tqi = tq0;
+        __asm__ volatile("" : "+v"(tqi), "+v"(band[0]), "+v"(band[1]));
+        const unsigned* tq = ltp + tqi;
 #pragma unroll
         for (int gr = 0; gr < kGrp; ++gr) {
             const int p1 = wv + kWaves * gr;
