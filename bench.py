@@ -50,14 +50,17 @@ def log(*a):
 def measured_traffic(kernel_key):
     """HBM bytes per launch of a kernel from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, each scaled by a plain 1 GiB copy), or
-    None when the kernel's source has changed since the counters were taken."""
+    None when the kernel's sources (its .hip file and the headers it shares)
+    have changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     try:
         d = json.load(open(path))
         k = d["kernels"][kernel_key]
-        src = os.path.join(ROOT, "paper_1609_04205_amd", "csrc", k["source"])
-        if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != k["source_sha256_16"]:
+        h = hashlib.sha256()
+        for f in k["sources"]:
+            h.update(open(os.path.join(ROOT, "paper_1609_04205_amd", "csrc", f), "rb").read())
+        if h.hexdigest()[:16] != k["sources_sha256_16"]:
             return None
         return round(k["hbm_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
