@@ -139,37 +139,41 @@ __global__ __launch_bounds__(256) void weights_kernel(WeightArgs w) {
 }
 
 // out = vis / W per baseline (0 where W = 0); one thread = one baseline's
-// 2 x 2 block of one channel.
+// 2 x 2 block of one channel; blockIdx.y = subband * P + channel, so the
+// indices need no 64-bit division.  Every byte is touched once: loads and
+// stores are non-temporal.
+typedef int nv4i __attribute__((ext_vector_type(4)));
+typedef float nv4f __attribute__((ext_vector_type(4)));
+
 template <bool kInt>
 __global__ void normalise_kernel(const void* __restrict__ vis, const int32_t* __restrict__ W,
-                                 float2* __restrict__ out, int64_t n_blocks, int64_t nbl, int P) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_blocks;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t bl = e % nbl;
-        const int64_t b = e / (nbl * P);
-        const int32_t wt = W[b * nbl + bl];
-        float2 r[4];
-        if constexpr (kInt) {
-            const int4* src = reinterpret_cast<const int4*>(vis) + e * 2;
-            const int4 u0 = src[0], u1 = src[1];
-            const int vv[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+                                 float2* __restrict__ out, int nbl, int P) {
+    const int bl = blockIdx.x * blockDim.x + threadIdx.x;
+    if (bl >= nbl) return;
+    const int slice = blockIdx.y;                           // subband * P + channel
+    const int64_t e = (int64_t)slice * nbl + bl;
+    const int32_t wt = W[(int64_t)(slice / P) * nbl + bl];
+    float2 r[4];
+    if constexpr (kInt) {
+        const nv4i* src = reinterpret_cast<const nv4i*>(vis) + e * 2;
+        const nv4i u0 = __builtin_nontemporal_load(src), u1 = __builtin_nontemporal_load(src + 1);
+        const int vv[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                r[j] = wt > 0 ? make_float2((float)((double)vv[2 * j] / wt), (float)((double)vv[2 * j + 1] / wt))
-                              : make_float2(0.0f, 0.0f);
-        } else {
-            const float4* src = reinterpret_cast<const float4*>(vis) + e * 2;
-            const float4 f0 = src[0], f1 = src[1];
-            const float vv[8] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
-            const float fw = (float)wt;
+        for (int j = 0; j < 4; ++j)
+            r[j] = wt > 0 ? make_float2((float)((double)vv[2 * j] / wt), (float)((double)vv[2 * j + 1] / wt))
+                          : make_float2(0.0f, 0.0f);
+    } else {
+        const nv4f* src = reinterpret_cast<const nv4f*>(vis) + e * 2;
+        const nv4f f0 = __builtin_nontemporal_load(src), f1 = __builtin_nontemporal_load(src + 1);
+        const float vv[8] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
+        const float fw = (float)wt;
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                r[j] = wt > 0 ? make_float2(vv[2 * j] / fw, vv[2 * j + 1] / fw) : make_float2(0.0f, 0.0f);
-        }
-        float4* dst = reinterpret_cast<float4*>(out) + e * 2;
-        dst[0] = make_float4(r[0].x, r[0].y, r[1].x, r[1].y);
-        dst[1] = make_float4(r[2].x, r[2].y, r[3].x, r[3].y);
+        for (int j = 0; j < 4; ++j)
+            r[j] = wt > 0 ? make_float2(vv[2 * j] / fw, vv[2 * j + 1] / fw) : make_float2(0.0f, 0.0f);
     }
+    nv4f* dst = reinterpret_cast<nv4f*>(out) + e * 2;
+    __builtin_nontemporal_store(nv4f{r[0].x, r[0].y, r[1].x, r[1].y}, dst);
+    __builtin_nontemporal_store(nv4f{r[2].x, r[2].y, r[3].x, r[3].y}, dst + 1);
 }
 
 struct alignas(4) Half2Raw { uint16_t x, y; };
@@ -220,14 +224,14 @@ hipError_t launch_validity_weights(const uint32_t* v, const uint8_t* flags, int3
 hipError_t launch_normalise(const void* vis, bool is_int, const int32_t* W, void* out, int B, int Na,
                             hipStream_t stream) {
     const int64_t nbl = (int64_t)Na * (Na + 1) / 2;
-    const int64_t n = (int64_t)B * kP * nbl;
-    const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(n, 256), 65536);
+    if (nbl > (1 << 30) || (int64_t)B * kP > 65535) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)ceil_div(nbl, 256), (unsigned)(B * kP));
     if (is_int)
-        hipLaunchKernelGGL(normalise_kernel<true>, dim3(grid), dim3(256), 0, stream, vis, W,
-                           reinterpret_cast<float2*>(out), n, nbl, kP);
+        hipLaunchKernelGGL(normalise_kernel<true>, grid, dim3(256), 0, stream, vis, W,
+                           reinterpret_cast<float2*>(out), (int)nbl, kP);
     else
-        hipLaunchKernelGGL(normalise_kernel<false>, dim3(grid), dim3(256), 0, stream, vis, W,
-                           reinterpret_cast<float2*>(out), n, nbl, kP);
+        hipLaunchKernelGGL(normalise_kernel<false>, grid, dim3(256), 0, stream, vis, W,
+                           reinterpret_cast<float2*>(out), (int)nbl, kP);
     return hipGetLastError();
 }
 
