@@ -130,6 +130,32 @@ def test_i8_requant_cfg1(afc, dev):
         log(f"  off-by-one fraction {np.mean(d == 1):.2e}")
 
 
+def test_i8_requant_rounds_the_exact_product_once(afc, dev):
+    """A single unit tap (branch 0, tap 0) makes every channel of spectrum s
+    equal to the sample x[64 s] exactly; with gain fp32(1/6) the product
+    15 * gain = 2.50000007... rounds to 3 when rounded once, but a float32
+    product rounds to 2.5 first and then to 2 (ties to even).  Also the
+    clamp at +-127 and the zero pad slots."""
+    Na, S = 8, 24
+    N = 2 * Na
+    L = (S + 15) * 64
+    xs = np.zeros((1, L, N, 2), np.int16)
+    xs[0, ::64, :, 0] = 15
+    xs[0, ::64, :, 1] = -15
+    xs[0, 64 * 5, 3, 0] = 32767                     # spectrum 5, receiver 3: clamps
+    taps = np.zeros(64 * 16, np.float32)
+    taps[0] = 1.0
+    gain = float(np.float32(1.0 / 6.0))
+    assert np.rint(np.float32(15) * np.float32(gain)) == 2.0          # the float32 product's rounding
+    z8 = afc.channelise(torch.from_numpy(xs).to(dev), torch.from_numpy(taps).to(dev), S, "i8", gain)
+    q, pad = _natural(z8.float(), S)
+    q = q[0]
+    assert np.all(pad == 0)
+    expect = np.full(q.shape, 3 - 3j)
+    expect[:, 5, 3] = 127 - 3j
+    np.testing.assert_array_equal(q, expect)
+
+
 def test_f32_full_size_sampled(afc, dev):
     """AARTFAAC-12 shape (1152 receivers, 16 subbands, 3051 spectra): sampled receivers."""
     cfg = W.CONFIGS[3]
