@@ -124,7 +124,7 @@ def main():
     import workloads as W
 
     dev = torch.device("cuda:0")
-    cfg = W.CONFIGS[3]
+    cfg = W.A12
     if args.fine_only:
         print(json.dumps({"fine": run_fine(torch, afc, W, dev, cfg, reps=args.steps)}), flush=True)
         return
@@ -302,16 +302,16 @@ def main():
         del xh, xd
 
         # ---- the whole AARTFAAC-12 band: 32 subbands of the same shape
-        cfg32 = W.Config("a12-576ant-32sb", Na, 32, n_spectra=S, sigma_n=cfg.sigma_n, n_sources=cfg.n_sources,
+        cfg_band = W.Config("a12-576ant-32sb", Na, 32, n_spectra=S, sigma_n=cfg.sigma_n, n_sources=cfg.n_sources,
                          seed=cfg.seed, layout=cfg.layout)
-        x32 = W.make_voltages(cfg32, device=dev)
+        x_band = W.make_voltages(cfg_band, device=dev)
         z32b = torch.empty(afc.channelised_shape(32, S, N), dtype=torch.int8, device=dev)
         v32 = torch.empty(afc.visibility_shape(32, Na), dtype=torch.int32, device=dev)
         w32 = torch.empty((32, nbl), dtype=torch.int32, device=dev)
         t32b = Timer(torch)
         for it in range(3):
             e = t32b.rec("step") if it > 0 else None
-            afc.channelise(x32, taps, S, "i8", gain, out=z32b)
+            afc.channelise(x_band, taps, S, "i8", gain, out=z32b)
             afc.correlate(z32b, n_spectra=S, out=v32, weights=w32)
             if e is not None:
                 e.record(torch.cuda.current_stream())
@@ -320,43 +320,43 @@ def main():
         out["a12_32sb"] = {"ms": round(ms32, 3), "tcmacs": round(2 * cmac / (ms32 * 1e-3) / 1e12, 3),
                            "real_time_factor": round(data_s / (ms32 * 1e-3), 2)}
         log(f"32 subbands {ms32:.3f} ms")
-        del x32, z32b, v32, w32
+        del x_band, z32b, v32, w32
         torch.cuda.empty_cache()
 
         # ---- the paper's channeliser configuration on the same array
         out["fine"] = run_fine(torch, afc, W, dev, cfg)
 
         # ---- batching form: 32 subbands, ragged S, flags, mixed fp16/int8, one graph
-        cfg4 = W.CONFIGS[4]
-        bp = W.batch_params(cfg4)
+        cfgb = W.A12_BATCHED
+        bp = W.batch_params(cfgb)
         dts = ["f16" if d == 1 else "i8" for d in bp.dtypes]
-        x4 = W.make_voltages(cfg4, device=dev)
-        plan = afc.Plan(Na, bp.n_spectra.tolist(), dts, n_spectra=cfg4.n_spectra,
+        xbat = W.make_voltages(cfgb, device=dev)
+        plan = afc.Plan(Na, bp.n_spectra.tolist(), dts, n_spectra=cfgb.n_spectra,
                         tune_cache=os.path.join(ROOT, "paper_1609_04205_amd", "tune_cache.json"))
         ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
-        vis4 = torch.empty(afc.visibility_shape(cfg4.n_subbands, Na), dtype=torch.int32, device=dev)
-        w4 = torch.empty((cfg4.n_subbands, nbl), dtype=torch.int32, device=dev)
+        visb = torch.empty(afc.visibility_shape(cfgb.n_subbands, Na), dtype=torch.int32, device=dev)
+        wb = torch.empty((cfgb.n_subbands, nbl), dtype=torch.int32, device=dev)
         fl = torch.from_numpy(bp.flags).to(dev)
-        g4 = [W.requant_gain(cfg4, taps_np)] * cfg4.n_subbands
-        plan.launch(x4, taps, g4, ws, vis4, flags=fl, weights=w4)
+        gb = [W.requant_gain(cfgb, taps_np)] * cfgb.n_subbands
+        plan.launch(xbat, taps, gb, ws, visb, flags=fl, weights=wb)
         torch.cuda.synchronize()
         tp = Timer(torch)
         for _ in range(3):
             e = tp.rec("plan")
-            plan.launch(x4, taps, g4, ws, vis4, flags=fl, weights=w4)
+            plan.launch(xbat, taps, gb, ws, visb, flags=fl, weights=wb)
             e.record(torch.cuda.current_stream())
         torch.cuda.synchronize()
-        nprime = [2 * (Na - int(bp.flags[b].sum())) for b in range(cfg4.n_subbands)]
+        nprime = [2 * (Na - int(bp.flags[b].sum())) for b in range(cfgb.n_subbands)]
         cm4 = sum(P * n * (n + 1) // 2 * int(bp.n_spectra[b]) for b, n in enumerate(nprime))
         plan_ms = tp.ms("plan")
         info = plan.info()
-        out["batching"] = {"workload": cfg4.name, "graph_ms": round(plan_ms, 3),
+        out["batching"] = {"workload": cfgb.name, "graph_ms": round(plan_ms, 3),
                            "useful_tcmacs": round(cm4 / (plan_ms * 1e-3) / 1e12, 3),
                            "real_time_factor": round(max(bp.n_spectra) * P / W.F_SUBBAND / (plan_ms * 1e-3), 2),
                            "tile": info.tile, "workgroups": info.n_workgroups, "work_items": info.n_work_items}
         log(f"plan {plan_ms:.3f} ms")
         plan.close()
-        del x4, ws, vis4, w4
+        del xbat, ws, visb, wb
         torch.cuda.empty_cache()
 
         # ---- calibration adjoint, 576 antennas x 64 channels
@@ -522,7 +522,7 @@ def cpu_baseline(S_s):
     import oracle
     import workloads as W
 
-    cfg = W.CONFIGS[3]
+    cfg = W.A12
     N = cfg.n_inputs
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     os.environ["OMP_NUM_THREADS"] = str(threads)

@@ -57,7 +57,7 @@ def test_small_random(afc, dev):
 
 
 @pytest.mark.parametrize("at", ["true", "unit"])
-def test_cfg5_small(afc, dev, at):
+def test_grad_small(afc, dev, at):
     V, M, g = W.make_calibration(Na=48, P=4, seed=15)
     if at == "unit":
         g = np.zeros_like(g)
@@ -66,7 +66,7 @@ def test_cfg5_small(afc, dev, at):
 
 
 @pytest.mark.parametrize("at", ["true", "unit"])
-def test_cfg5_full_size(afc, dev, at):
+def test_grad_full_size(afc, dev, at):
     """576 antennas x 64 channels at SNR 20, at the true gains (residual ~ 5% of V) and at g = 1."""
     log(f"calibration full size at {at}")
     V, M, g = W.make_calibration(Na=576, P=64, seed=5)

@@ -22,8 +22,8 @@ def afc():
 
 
 @pytest.fixture(scope="module")
-def cfg1(dev):
-    cfg = W.CONFIGS[1]
+def small_case(dev):
+    cfg = W.SMALL
     x = W.make_voltages(cfg, device=dev)
     taps = W.prototype_taps()
     y = oracle.ppf_subband(x[0].cpu().numpy(), taps, 64, 16, cfg.n_spectra)       # [P][S][N]
@@ -31,9 +31,9 @@ def cfg1(dev):
 
 
 @pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("f16", 2e-3)])
-def test_chain_cfg1(afc, dev, cfg1, dtype, tol):
-    cfg, x, taps, y = cfg1
-    log(f"chain {dtype} cfg1")
+def test_chain_small(afc, dev, small_case, dtype, tol):
+    cfg, x, taps, y = small_case
+    log(f"chain {dtype} small_case")
     z = afc.channelise(x, torch.from_numpy(taps).to(dev), cfg.n_spectra, dtype)
     vis, w = afc.correlate(z, n_spectra=cfg.n_spectra)
     v = vis_to_complex(vis.cpu().numpy())[0]
@@ -47,10 +47,10 @@ def test_chain_cfg1(afc, dev, cfg1, dtype, tol):
     assert np.all(w.cpu().numpy() == cfg.n_spectra)
 
 
-def test_chain_i8_cfg1_closeness(afc, dev, cfg1):
+def test_chain_i8_small_closeness(afc, dev, small_case):
     """int8 chain: the visibility of the requantised samples, scaled back by 1/gain^2,
     stays within the quantisation noise of the float64 chain."""
-    cfg, x, taps, y = cfg1
+    cfg, x, taps, y = small_case
     gain = W.requant_gain(cfg, taps)
     z = afc.channelise(x, torch.from_numpy(taps).to(dev), cfg.n_spectra, "i8", gain)
     vis, _ = afc.correlate(z, n_spectra=cfg.n_spectra)
@@ -90,8 +90,8 @@ def test_chain_plane_wave(afc, dev):
 
 def test_chain_f32_full_size_sampled(afc, dev):
     """AARTFAAC-6 shape (576 receivers, 8 subbands, 3051 spectra), fp32 chain on sampled antennas."""
-    cfg = W.CONFIGS[2]
-    log("chain f32 cfg2 full size")
+    cfg = W.A6
+    log("chain f32 a6 full size")
     x = W.make_voltages(cfg, device=dev)
     taps = W.prototype_taps()
     z = afc.channelise(x, torch.from_numpy(taps).to(dev), cfg.n_spectra, "f32")

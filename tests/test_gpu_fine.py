@@ -181,7 +181,7 @@ def test_f32_full_size_sampled(afc, dev):
     """AARTFAAC-12 shape, 1 s of 256-sample spectra (1152 receivers, 16
     subbands, 762 spectra): sampled receivers of three subbands."""
     Na, B, S = 576, 16, 762
-    cfg = W.CONFIGS[3]
+    cfg = W.A12
     log("fine f32 full size")
     x = W.make_voltages(cfg, device=dev, n_rows=W.fine_rows(S))
     taps = W.prototype_taps(PF, T)

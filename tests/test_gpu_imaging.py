@@ -114,7 +114,7 @@ def test_full_size_aartfaac12(afc, dev):
     """576 antennas (12 stations), 8 subbands x 64 channels, 2048^2 grid,
     three point sources."""
     Na, B, N, du = 576, 8, 2048, 0.5
-    cfg = W.CONFIGS[3]
+    cfg = W.A12
     pos = W.antenna_positions(cfg)
     post = torch.from_numpy(pos).to(dev)
     freq = _freqs(B)

@@ -113,10 +113,10 @@ def test_plan_forced_small_tiles(afc, dev, tmp_path):
     assert info.tile == 64
 
 
-def test_plan_full_size_cfg4(afc, dev, tmp_path):
+def test_plan_full_size_a12_batched(afc, dev, tmp_path):
     """AARTFAAC-12 batching workload: 32 subbands, S_b in 500..3051, 0-10% flagged, mixed fp16/int8."""
-    log("plan full size cfg4")
-    cfg = W.CONFIGS[4]
+    log("plan full size a12_batched")
+    cfg = W.A12_BATCHED
     bp = W.batch_params(cfg)
     dts = ["f16" if d == 1 else "i8" for d in bp.dtypes]
     B = cfg.n_subbands

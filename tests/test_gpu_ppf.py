@@ -35,9 +35,9 @@ def _natural(z, S):
     return c[:, :, :S], c[:, :, S:]
 
 
-def test_f32_cfg1_all_outputs(afc, dev):
-    cfg = W.CONFIGS[1]
-    log("ppf f32 cfg1: Na=48 S=1024")
+def test_f32_small_all_outputs(afc, dev):
+    cfg = W.SMALL
+    log("ppf f32 small: Na=48 S=1024")
     x, taps, z = _run(afc, dev, cfg, "f32")
     y, pad = _natural(z, cfg.n_spectra)
     ref = oracle.ppf_subband(x[0].cpu().numpy(), taps, 64, 16, cfg.n_spectra)      # [P][S][N]
@@ -86,9 +86,9 @@ def test_f32_full_scale_samples_and_tap_scales(afc, dev, tap_scale):
     assert err <= 1e-5
 
 
-def test_f16_cfg1(afc, dev):
-    cfg = W.CONFIGS[1]
-    log("ppf f16 cfg1")
+def test_f16_small(afc, dev):
+    cfg = W.SMALL
+    log("ppf f16 small")
     x, taps, z = _run(afc, dev, cfg, "f16")
     y, _ = _natural(z, cfg.n_spectra)
     ref = oracle.ppf_subband(x[0].cpu().numpy(), taps, 64, 16, cfg.n_spectra)
@@ -99,11 +99,11 @@ def test_f16_cfg1(afc, dev):
         assert np.all(d <= 2.0 ** -11 * np.abs(comp(ref)) * 1.0001 + 2e-5 * sigma)
 
 
-def test_i8_requant_cfg1(afc, dev):
-    cfg = W.CONFIGS[1]
+def test_i8_requant_small(afc, dev):
+    cfg = W.SMALL
     taps = W.prototype_taps()
     gain = W.requant_gain(cfg, taps)
-    log(f"ppf i8 cfg1 gain={gain}")
+    log(f"ppf i8 small gain={gain}")
     x = W.make_voltages(cfg, device=dev)
     tt = torch.from_numpy(taps).to(dev)
     z8 = afc.channelise(x, tt, cfg.n_spectra, "i8", gain)
@@ -158,8 +158,8 @@ def test_i8_requant_rounds_the_exact_product_once(afc, dev):
 
 def test_f32_full_size_sampled(afc, dev):
     """AARTFAAC-12 shape (1152 receivers, 16 subbands, 3051 spectra): sampled receivers."""
-    cfg = W.CONFIGS[3]
-    log("ppf f32 cfg3 full size")
+    cfg = W.A12
+    log("ppf f32 AARTFAAC-12 full size")
     x, taps, z = _run(afc, dev, cfg, "f32")
     rng = np.random.default_rng(0)
     for sb in (0, 7, 15):

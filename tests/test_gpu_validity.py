@@ -143,7 +143,7 @@ def test_validity_full_size_sampled(afc, dev):
     """AARTFAAC-12 shape: 16 subbands x 576 antennas x 3051 spectra, 0.1%
     packet loss plus one dead station; sampled antennas against the oracle,
     weights of sampled baselines against the oracle's count."""
-    cfg = W.CONFIGS[3]
+    cfg = W.A12
     B, Na, S = cfg.n_subbands, cfg.n_antennas, cfg.n_spectra
     pkt = W.packet_loss(B, Na, cfg.n_rows, seed=3, dead=[(5, 7)])
     pt = torch.from_numpy(pkt).to(dev)

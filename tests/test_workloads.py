@@ -36,7 +36,7 @@ def test_prototype_response():
 
 
 def test_voltage_shape_and_range():
-    cfg = W.CONFIGS[1]
+    cfg = W.SMALL
     x = W.make_voltages(cfg, n_rows=4096)
     assert tuple(x.shape) == (1, 4096, 48, 2, 2)
     xf = x.float()
@@ -47,7 +47,7 @@ def test_voltage_shape_and_range():
 
 def test_voltage_source_coherence():
     """The injected source makes inputs correlated with the geometric phase."""
-    cfg = W.CONFIGS[1]
+    cfg = W.SMALL
     x = W.make_voltages(cfg, n_rows=65536).numpy().astype(np.float64)
     z = x[0, ..., 0] + 1j * x[0, ..., 1]                   # [L][Na][2]
     pos = W.antenna_positions(cfg)
@@ -68,7 +68,7 @@ def test_channelised_blocks_padding():
 
 
 def test_batch_params():
-    bp = W.batch_params(W.CONFIGS[4])
+    bp = W.batch_params(W.A12_BATCHED)
     assert bp.n_spectra.min() >= 500 and bp.n_spectra.max() <= 3051
     assert bp.flags.shape == (32, 576)
     assert bp.flags.sum(axis=1).max() <= round(0.1 * 576)

@@ -64,21 +64,19 @@ class Config:
         return (self.n_spectra + self.n_taps - 1) * self.n_channels
 
 
-CONFIGS = {
-    # small: 48 antennas in a 30 m disc, 1 subband, 1024 spectra
-    1: Config("small-48ant", 48, 1, n_spectra=1024, sigma_n=64.0,
-              source_sigmas=(16.0,), layout="disc", seed=1),
-    # AARTFAAC-6 shape: 6 stations x 48 antennas, 8 subbands, 1 s
-    2: Config("a6-288ant-8sb", 288, 8, n_spectra=3051, sigma_n=32.0,
-              n_sources=3, layout="stations6", seed=2),
-    # AARTFAAC-12 shape: 12 stations x 48 antennas, 16 subbands, 1 s
-    3: Config("a12-576ant-16sb", 576, 16, n_spectra=3051, sigma_n=32.0,
-              n_sources=3, layout="stations12", seed=3),
-    # batching: 32 subbands, ragged integration, flags, mixed fp16/int8
-    4: Config("a12-576ant-32sb-batched", 576, 32, n_spectra=3051, sigma_n=32.0,
-              n_sources=3, layout="stations12", seed=4,
-              ragged=True, flag_max=0.10, mixed_dtype=True),
-}
+# small: 48 antennas in a 30 m disc, 1 subband, 1024 spectra
+SMALL = Config("small-48ant", 48, 1, n_spectra=1024, sigma_n=64.0,
+               source_sigmas=(16.0,), layout="disc", seed=1)
+# AARTFAAC-6 shape: 6 stations x 48 antennas, 8 subbands, 1 s
+A6 = Config("a6-288ant-8sb", 288, 8, n_spectra=3051, sigma_n=32.0,
+            n_sources=3, layout="stations6", seed=2)
+# AARTFAAC-12 shape: 12 stations x 48 antennas, 16 subbands, 1 s
+A12 = Config("a12-576ant-16sb", 576, 16, n_spectra=3051, sigma_n=32.0,
+             n_sources=3, layout="stations12", seed=3)
+# batching: 32 subbands, ragged integration, flags, mixed fp16/int8
+A12_BATCHED = Config("a12-576ant-32sb-batched", 576, 32, n_spectra=3051, sigma_n=32.0,
+                     n_sources=3, layout="stations12", seed=4,
+                     ragged=True, flag_max=0.10, mixed_dtype=True)
 
 
 # --------------------------------------------------------------------------
