@@ -495,10 +495,10 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
                 const bool flagged = fb || frow[J::IA[p]][((r >> 2) << 1) | ((r >> 1) & 1)];
                 if (flagged) o0 = o1 = o2 = o3 = E(0);
                 const int64_t bl = (int64_t)a * (a + 1) / 2 + b;
-                if constexpr (DT == AFC_I8)
-                    reinterpret_cast<int4*>(vis_ch)[bl * 2 + (odd ? 1 : 0)] = make_int4(o0, o1, o2, o3);
-                else
-                    reinterpret_cast<float4*>(vis_ch)[bl * 2 + (odd ? 1 : 0)] = make_float4(o0, o1, o2, o3);
+                // written once and not read again by this kernel: a streaming
+                // (non-temporal) store
+                typedef E ev4 __attribute__((ext_vector_type(4)));
+                __builtin_nontemporal_store(ev4{o0, o1, o2, o3}, reinterpret_cast<ev4*>(vis_ch) + bl * 2 + (odd ? 1 : 0));
                 if (write_weights && !odd) w_sb[bl] = flagged ? 0 : S;
             }
         }
