@@ -16,8 +16,9 @@
  *       u[s][p] = sum_{t<T} h[t*P+p] * x[(s+t)*P + p]
  *       y[s][k] = sum_{p<P} u[s][p] * exp(-2 pi i k p / P)
  *   requantiser  (Sec. "LOFAR Digital Processing", bit modes trade bits for
- *                dynamic range): q = clamp(rint(y * gain), -127, 127), with
- *                the product and the rounding in float32, ties to even
+ *                dynamic range): q = clamp(rint(y * gain), -127, 127) of
+ *                float32 y and gain, the exact product rounded once to an
+ *                integer, ties to even
  *   correlator   (Sec. "Correlation Kernel": per channel, the covariance of
  *                every pair of receivers integrated over time, one triangle
  *                of the Hermitian matrix)

@@ -114,3 +114,55 @@ def test_apply_vis_flags():
     assert np.all(Z[1, 3, 1, 1] == 0) and np.all(Z[1, 3, 0, 0] == V[1, 3, 0, 0])
     Z[1, 3, 1, 1] = V[1, 3, 1, 1]
     np.testing.assert_array_equal(Z, V)
+
+
+def _ls_step(V, M, g):
+    """One simultaneous update: for every antenna a, the least-squares gain
+    gamma minimising sum_b |V_ab - gamma M_ab conj(g_b)|^2 with the other
+    gains held at g, found by numpy's least-squares solver."""
+    Na = g.size
+    out = np.empty(Na, np.complex128)
+    for a in range(Na):
+        A = (M[a, :] * np.conj(g))[:, None]
+        out[a] = np.linalg.lstsq(A, V[a, :], rcond=None)[0][0]
+    return out
+
+
+def test_first_iterations_are_least_squares_steps():
+    """Iteration 1 is the plain least-squares step, iteration 2 averages the
+    step with the previous iterate, iteration 3 is a plain step again; the
+    result is phase-referenced (the update commutes with a common phase)."""
+    rng = np.random.default_rng(8)
+    Na, P = 7, 2
+    V, M, _ = W.make_calibration(Na=Na, P=P, n_src=3, snr=4.0, seed=9)
+    g0 = rng.uniform(0.7, 1.3, (P, Na, 2)) * np.exp(1j * rng.uniform(0, 2 * np.pi, (P, Na, 2)))
+    sols = [oracle.cal_solve(V, M, g0, n) for n in (1, 2, 3)]
+    for ch in range(P):
+        for pol in range(2):
+            Vf = oracle._full(V[ch], Na, pol)
+            Mf = oracle._full(M[ch], Na, pol)
+            g1 = _ls_step(Vf, Mf, g0[ch, :, pol])
+            g2 = 0.5 * (_ls_step(Vf, Mf, g1) + g1)
+            g3 = _ls_step(Vf, Mf, g2)
+            for n, ref in enumerate((g1, g2, g3)):
+                ref = ref * np.conj(ref[0]) / abs(ref[0])
+                np.testing.assert_allclose(sols[n][ch, :, pol], ref, rtol=1e-9, atol=1e-12)
+
+
+def test_sigma_clip_stage2_rms_excludes_stage1_flags():
+    """Stage 2 computes each visibility's RMS over the channels that stage 1
+    left unflagged.  A quiet baseline with a huge spike in channel 5 (flagged
+    by stage 1) and a moderate one in channel 9 (1.5, under 5 RMS of its
+    channel): over the 63 remaining channels RMS^2 = (62 * 0.02 + 2.25) / 63
+    ~ 0.055, so 1.5 > 5 RMS ~ 1.18 is flagged; had channel 5 been kept,
+    RMS ~ 6.3 would hide it."""
+    rng = np.random.default_rng(10)
+    P, Na, k = 64, 12, 5.0
+    V = _vis(P, Na, rng)
+    bl = 40
+    V[:, bl, 0, 0] = [0.1, 0.1]
+    V[5, bl, 0, 0] = [50.0, 0.0]
+    V[9, bl, 0, 0] = [1.5, 0.0]
+    f = oracle.sigma_clip(V, k)
+    assert f[5, bl, 0] == 1 and f[9, bl, 0] == 1
+    assert f[:, bl, 0].sum() == 2

@@ -145,3 +145,19 @@ def test_pairs_match_triangle():
     assert np.allclose(out[0], V[bl(3, 0), 1, 0])
     assert np.allclose(out[1], V[bl(2, 2), 1, 1])
     assert np.allclose(out[2], V[bl(1, 1), 1, 0])
+
+
+def test_int_flags_zero_baselines_and_weights():
+    """Integer form: a baseline touching a flagged antenna is exactly 0 with
+    weight 0; the others keep their exact sums and weight S."""
+    rng = np.random.default_rng(14)
+    Na, S = 5, 12
+    z = rng.integers(-127, 128, size=(S, 2 * Na, 2)).astype(np.int8)
+    flags = np.array([1, 0, 0, 1, 0], np.uint8)
+    V, W = oracle.xcorr_int(z, flags)
+    V0, W0 = oracle.xcorr_int(z)
+    a, b = _tri(Na)
+    hit = (flags[a] == 1) | (flags[b] == 1)
+    assert np.all(V[hit] == 0) and np.all(W[hit] == 0)
+    np.testing.assert_array_equal(V[~hit], V0[~hit])
+    assert np.all(W[~hit] == S) and np.all(W0 == S)
