@@ -20,7 +20,8 @@ C_SRC = "oracle/afc_oracle.c"
 PY_SRC = "oracle/__init__.py"
 
 PIN_FILES = sorted(f for f in os.listdir(os.path.join(ROOT, "tests"))
-                   if (f.startswith("test_oracle_") and f != "test_oracle_mutations.py")
+                   if (f.startswith("test_oracle_") and f.endswith(".py")
+                       and f not in ("test_oracle_mutations.py", "test_oracle_sanitizers.py"))
                    or f == "test_workloads.py")
 
 # (name, file, text, replacement, occurrence (0-based) or None if unique)
