@@ -19,7 +19,9 @@
  * Conventions (all entry points):
  *   - Pointers are DEVICE pointers unless the comment says "host".  The caller
  *     owns every buffer; the library never allocates or frees device memory
- *     on these calls (plans allocate only at afc_plan_create).
+ *     on these calls, except the plans: afc_plan_create allocates the plan's
+ *     tables, and an afc_plan_launch that captures a new graph allocates that
+ *     graph's small item table (see afc_plan_launch).
  *   - Every call is asynchronous on `stream` (a hipStream_t; 0 = null stream).
  *     Argument errors are found on the host before anything is launched and
  *     return a negative afc_status; afc_last_error() then holds a message
@@ -29,6 +31,16 @@
  *     i = 2*a + p (p = 0 "X", 1 "Y"), N = 2*n_antennas receivers.
  *   - Baselines: antennas a >= b, bl(a, b) = a*(a+1)/2 + b,
  *     Nbl = n_antennas*(n_antennas+1)/2.
+ *
+ * Two amendments to the interface first proposed for this library:
+ *   - The channelised array z is [B][P][ceil(S/8)][N][8] (blocks of 8
+ *     spectra per receiver) instead of [B][P][S][Na][Np].  Both the
+ *     channeliser's stores and the correlator's operand loads then move whole
+ *     64-byte (int8: 16-byte) runs per receiver; spectra >= S in the last
+ *     block are zero.  Receiver i = 2a + p is the same index in both forms.
+ *   - afc_calibrate_grad takes a caller-provided workspace (per-tile partial
+ *     sums), so that the gradient is reduced in a fixed order without
+ *     atomics and the call allocates nothing.
  */
 #ifndef AFC_H
 #define AFC_H
@@ -380,10 +392,18 @@ AFC_API int afc_image_from_grid(int32_t grid_size, const void* grid, const doubl
  *                    flags uint8 [B][Na] or NULL; vis [B][P][Nbl][2][2]
  *                    (float2 or int2 per subband type, 16-byte aligned);
  *                    weights int32 [B][Nbl]
- *                    or NULL.  The first launch on a stream captures the work
- *                    into a HIP graph; later launches with the same pointers
- *                    and stream replay it.
- * afc_plan_destroy   frees the plan and its graph.
+ *                    or NULL.  A launch with new buffers or new gains
+ *                    captures the work into a new HIP graph (allocating its
+ *                    B * 32-byte item table, uploaded asynchronously on
+ *                    `stream`); launches with the same buffers and gains only
+ *                    enqueue that graph on `stream`.  A replaced graph and its
+ *                    table stay alive until its last launch has completed
+ *                    (an event recorded on the launch stream), and are freed
+ *                    by a later call or by afc_plan_destroy, so launches
+ *                    still in flight never see the new gains.  Freeing may
+ *                    synchronise the device; plans are not thread-safe.
+ * afc_plan_destroy   waits for the plan's graphs to finish, then frees them
+ *                    and the plan.
  * ------------------------------------------------------------------------- */
 typedef struct afc_plan afc_plan;
 

@@ -105,24 +105,35 @@ def _torch():
     return torch
 
 
-def _stream(device):
+def _stream(*tensors):
+    """Current stream of the first tensor's GPU, after checking that every
+    buffer of the call (None skipped) lives on that GPU.  Called last, after
+    the shape checks, right before the library call."""
     torch = _torch()
-    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    ts = [t for t in tensors if t is not None]
+    dev = ts[0].device
+    for t in ts:
+        if not t.is_cuda:
+            raise AfcError(f"every buffer must be a GPU tensor (got one on {t.device})")
+        if t.device != dev:
+            raise AfcError(f"buffers on {dev} and {t.device}: one GPU per call")
+    return C.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
 
 
 def _ptr(t) -> Optional[C.c_void_p]:
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
-def _require(t, dtype, name):
-    torch = _torch()
-    if not t.is_cuda:
-        raise AfcError(f"{name} must be a GPU tensor")
+def _require(t, dtype, name, shape=None):
+    """Type, shape and layout of a caller buffer (a buffer of the wrong size
+    is a host-side error, never an out-of-bounds device access).  Devices are
+    checked by _stream()."""
     if t.dtype != dtype:
         raise AfcError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise AfcError(f"{name} shape {tuple(t.shape)} != {tuple(shape)}")
     if not t.is_contiguous():
         raise AfcError(f"{name} must be contiguous")
-    del torch
 
 
 _TORCH_OF = {"f32": "float32", "f16": "float16", "i8": "int8"}
@@ -136,10 +147,14 @@ def channelised_shape(n_subbands, n_spectra, n_inputs):
 def channelise(x, taps, n_spectra: int, out_dtype: str = "f32", gain: float = 1.0, out=None):
     """x int16 [B][L][Na][2][2] (or [B][L][N][2]) -> z [B][P][Sb][N][8][2]."""
     torch = _torch()
+    if out_dtype not in DTYPES:
+        raise AfcError(f"out_dtype must be one of {sorted(DTYPES)}, got {out_dtype!r}")
     _require(x, torch.int16, "x")
-    _require(taps, torch.float32, "taps")
     B, L = x.shape[0], x.shape[1]
     N = x[0, 0].numel() // 2
+    if x.dim() < 3 or x.shape[-1] != 2 or N % 2:
+        raise AfcError(f"x shape {tuple(x.shape)} is not [B][L][N][2] with N even")
+    _require(taps, torch.float32, "taps", (N_TAPS * N_CHANNELS,))
     Na = N // 2
     d = dims(Na, B, n_spectra)
     if L != (n_spectra + N_TAPS - 1) * N_CHANNELS:
@@ -148,11 +163,9 @@ def channelise(x, taps, n_spectra: int, out_dtype: str = "f32", gain: float = 1.
     tdt = getattr(torch, _TORCH_OF[out_dtype])
     if out is None:
         out = torch.empty(shape, dtype=tdt, device=x.device)
-    _require(out, tdt, "out")
-    if tuple(out.shape) != shape:
-        raise AfcError(f"out shape {tuple(out.shape)} != {shape}")
+    _require(out, tdt, "out", shape)
     _check(_lib.afc_channelise(C.byref(d), _ptr(x), _ptr(taps), DTYPES[out_dtype], float(gain), _ptr(out),
-                               _stream(x.device)), "afc_channelise")
+                               _stream(x, taps, out)), "afc_channelise")
     return out
 
 
@@ -169,27 +182,27 @@ def channelise_fine(x, taps, n_spectra: int, delays, bandpass, center_hz: Sequen
     (the layout of channelise).  delays float64 [N] seconds and bandpass
     float32 [256] on the GPU; center_hz: B sky frequencies (host)."""
     torch = _torch()
+    if out_dtype not in DTYPES:
+        raise AfcError(f"out_dtype must be one of {sorted(DTYPES)}, got {out_dtype!r}")
     _require(x, torch.int16, "x")
-    _require(taps, torch.float32, "taps")
-    _require(delays, torch.float64, "delays")
-    _require(bandpass, torch.float32, "bandpass")
     B, L = x.shape[0], x.shape[1]
     N = x[0, 0].numel() // 2
+    if x.dim() < 3 or x.shape[-1] != 2 or N % 2:
+        raise AfcError(f"x shape {tuple(x.shape)} is not [B][L][N][2] with N even")
+    _require(taps, torch.float32, "taps", (N_TAPS * N_FINE,))
+    _require(delays, torch.float64, "delays", (N,))
+    _require(bandpass, torch.float32, "bandpass", (N_FINE,))
     d = dims(N // 2, B, n_spectra)
     if L != (n_spectra + N_TAPS - 1) * N_FINE:
         raise AfcError(f"x has {L} rows, expected (S+T-1)*256 = {(n_spectra + N_TAPS - 1) * N_FINE}")
-    if taps.numel() != N_TAPS * N_FINE or delays.numel() != N or bandpass.numel() != N_FINE:
-        raise AfcError("taps, delays or bandpass has the wrong size")
-    nu = (C.c_double * B)(*[float(v) for v in center_hz])
     if len(center_hz) != B:
         raise AfcError(f"center_hz has {len(center_hz)} entries, expected {B}")
+    nu = (C.c_double * B)(*[float(v) for v in center_hz])
     shape = channelised_shape(B, n_spectra, N)
     tdt = getattr(torch, _TORCH_OF[out_dtype])
     if out is None:
         out = torch.empty(shape, dtype=tdt, device=x.device)
-    _require(out, tdt, "out")
-    if tuple(out.shape) != shape:
-        raise AfcError(f"out shape {tuple(out.shape)} != {shape}")
+    _require(out, tdt, "out", shape)
     need = _lib.afc_channelise_fine_workspace_bytes(C.byref(d))
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
@@ -198,7 +211,7 @@ def channelise_fine(x, taps, n_spectra: int, delays, bandpass, center_hz: Sequen
         raise AfcError(f"workspace holds {workspace.numel()} bytes, {need} needed")
     _check(_lib.afc_channelise_fine(C.byref(d), _ptr(x), _ptr(taps), _ptr(delays), _ptr(bandpass), nu,
                                     float(subband_hz), DTYPES[out_dtype], float(gain), _ptr(workspace),
-                                    _ptr(out), _stream(x.device)), "afc_channelise_fine")
+                                    _ptr(out), _stream(x, taps, delays, bandpass, workspace, out)), "afc_channelise_fine")
     return out
 
 
@@ -211,17 +224,17 @@ def validity(packet_valid, n_spectra: int, packet_samples: int, samples_per_spec
     """packet_valid uint8 [B][n_packets][Na] -> spectrum validity bits, int32
     [B][ceil(S/32)][Na] (bit s % 32 of word s // 32 = spectrum s valid)."""
     torch = _torch()
+    if packet_valid.dim() != 3:
+        raise AfcError(f"packet_valid shape {tuple(packet_valid.shape)} is not [B][n_packets][Na]")
     _require(packet_valid, torch.uint8, "packet_valid")
     B, n_pk, Na = packet_valid.shape
     d = dims(Na, B, n_spectra)
     shape = validity_shape(B, n_spectra, Na)
     if out is None:
         out = torch.empty(shape, dtype=torch.int32, device=packet_valid.device)
-    _require(out, torch.int32, "out")
-    if tuple(out.shape) != shape:
-        raise AfcError(f"out shape {tuple(out.shape)} != {shape}")
+    _require(out, torch.int32, "out", shape)
     _check(_lib.afc_validity(C.byref(d), _ptr(packet_valid), int(n_pk), int(packet_samples),
-                             int(samples_per_spectrum), _ptr(out), _stream(packet_valid.device)), "afc_validity")
+                             int(samples_per_spectrum), _ptr(out), _stream(packet_valid, out)), "afc_validity")
     return out
 
 
@@ -229,14 +242,14 @@ def zero_invalid(z, spec_valid, n_spectra: int):
     """Zero, in place, the samples of z [B][64][Sb][N][8][2] whose spectrum is
     invalid for their antenna."""
     torch = _torch()
-    dt = {torch.float32: "f32", torch.float16: "f16", torch.int8: "i8"}[z.dtype]
-    _require(z, z.dtype, "z")
-    _require(spec_valid, torch.int32, "spec_valid")
+    dt = {torch.float32: "f32", torch.float16: "f16", torch.int8: "i8"}.get(z.dtype)
+    if dt is None or z.dim() != 6:
+        raise AfcError(f"z must be float32, float16 or int8 [B][64][Sb][N][8][2], got {z.dtype} {tuple(z.shape)}")
     B, N = z.shape[0], z.shape[3]
-    if tuple(spec_valid.shape) != validity_shape(B, n_spectra, N // 2):
-        raise AfcError("spec_valid does not match z")
+    _require(z, z.dtype, "z", channelised_shape(B, n_spectra, N))
+    _require(spec_valid, torch.int32, "spec_valid", validity_shape(B, n_spectra, N // 2))
     d = dims(N // 2, B, n_spectra)
-    _check(_lib.afc_zero_invalid(C.byref(d), DTYPES[dt], _ptr(spec_valid), _ptr(z), _stream(z.device)),
+    _check(_lib.afc_zero_invalid(C.byref(d), DTYPES[dt], _ptr(spec_valid), _ptr(z), _stream(z, spec_valid)),
            "afc_zero_invalid")
     return z
 
@@ -245,39 +258,43 @@ def validity_weights(spec_valid, n_spectra: int, n_spectra_per_sb: Optional[Sequ
                      out=None):
     """Weighting matrix int32 [B][Nbl]: spectra valid for both antennas of each baseline."""
     torch = _torch()
-    _require(spec_valid, torch.int32, "spec_valid")
     B, _, Na = spec_valid.shape
+    _require(spec_valid, torch.int32, "spec_valid", validity_shape(B, n_spectra, Na))
     d = dims(Na, B, n_spectra)
     if out is None:
         out = torch.empty((B, Na * (Na + 1) // 2), dtype=torch.int32, device=spec_valid.device)
-    _require(out, torch.int32, "out")
+    _require(out, torch.int32, "out", (B, Na * (Na + 1) // 2))
     if flags is not None:
-        _require(flags, torch.uint8, "flags")
+        _require(flags, torch.uint8, "flags", (B, Na))
     sp = None
     if n_spectra_per_sb is not None:
+        if len(n_spectra_per_sb) != B:
+            raise AfcError(f"n_spectra_per_sb has {len(n_spectra_per_sb)} entries, expected {B}")
         arr = (C.c_int32 * B)(*[int(v) for v in n_spectra_per_sb])
         sp = C.cast(arr, C.c_void_p)
     _check(_lib.afc_validity_weights(C.byref(d), _ptr(spec_valid), sp, _ptr(flags), _ptr(out),
-                                     _stream(spec_valid.device)), "afc_validity_weights")
+                                     _stream(spec_valid, flags, out)), "afc_validity_weights")
     return out
 
 
 def normalise_visibilities(vis, weights, out=None):
     """vis [B][64][Nbl][2][2][2] (int32 or float32) / weights [B][Nbl] -> float32, 0 where W = 0."""
     torch = _torch()
-    _require(weights, torch.int32, "weights")
-    _require(vis, vis.dtype, "vis")
+    if vis.dtype not in (torch.int32, torch.float32):
+        raise AfcError(f"vis must be int32 or float32, got {vis.dtype}")
     dt = "i8" if vis.dtype == torch.int32 else "f32"
-    B, P, nbl = vis.shape[0], vis.shape[1], vis.shape[2]
+    B, nbl = vis.shape[0], vis.shape[2]
     Na = int(round(((8 * nbl + 1) ** 0.5 - 1) / 2))
-    if P != N_CHANNELS or Na * (Na + 1) // 2 != nbl or tuple(weights.shape) != (B, nbl):
-        raise AfcError("vis / weights shapes do not match")
+    _require(vis, vis.dtype, "vis", visibility_shape(B, Na))
+    _require(weights, torch.int32, "weights", (B, nbl))
     if out is None:
         out = torch.empty(vis.shape, dtype=torch.float32, device=vis.device)
-    _require(out, torch.float32, "out")
+    _require(out, torch.float32, "out", vis.shape)
+    if out.data_ptr() == vis.data_ptr():
+        raise AfcError("out may not alias vis")
     d = dims(Na, B, 1)
     _check(_lib.afc_normalise_visibilities(C.byref(d), DTYPES[dt], _ptr(vis), _ptr(weights), _ptr(out),
-                                           _stream(vis.device)), "afc_normalise_visibilities")
+                                           _stream(vis, weights, out)), "afc_normalise_visibilities")
     return out
 
 
@@ -289,11 +306,13 @@ def correlate(z, n_spectra: Optional[int] = None, n_spectra_per_sb: Optional[Seq
               flags=None, want_weights: bool = True, out=None, weights=None):
     """z [B][P][Sb][N][8][2] -> (vis [B][P][Nbl][2][2][2] float32 or int32, weights [B][Nbl] int32)."""
     torch = _torch()
-    dt = {torch.float32: "f32", torch.float16: "f16", torch.int8: "i8"}[z.dtype]
-    _require(z, z.dtype, "z")
+    dt = {torch.float32: "f32", torch.float16: "f16", torch.int8: "i8"}.get(z.dtype)
+    if dt is None or z.dim() != 6:
+        raise AfcError(f"z must be float32, float16 or int8 [B][64][Sb][N][8][2], got {z.dtype} {tuple(z.shape)}")
     B, P, Sb, N = z.shape[0], z.shape[1], z.shape[2], z.shape[3]
-    if P != N_CHANNELS or z.shape[4] != SPECTRUM_BLOCK or z.shape[5] != 2:
-        raise AfcError(f"z shape {tuple(z.shape)} is not [B][64][Sb][N][8][2]")
+    if P != N_CHANNELS or z.shape[4] != SPECTRUM_BLOCK or z.shape[5] != 2 or N % 2:
+        raise AfcError(f"z shape {tuple(z.shape)} is not [B][64][Sb][N][8][2] with N even")
+    _require(z, z.dtype, "z")
     S = n_spectra if n_spectra is not None else Sb * SPECTRUM_BLOCK
     if (S + SPECTRUM_BLOCK - 1) // SPECTRUM_BLOCK != Sb:
         raise AfcError("n_spectra does not match the number of spectrum blocks")
@@ -302,40 +321,58 @@ def correlate(z, n_spectra: Optional[int] = None, n_spectra_per_sb: Optional[Seq
     vdt = torch.int32 if dt == "i8" else torch.float32
     if out is None:
         out = torch.empty(visibility_shape(B, Na), dtype=vdt, device=z.device)
-    _require(out, vdt, "out")
+    _require(out, vdt, "out", visibility_shape(B, Na))
     if want_weights and weights is None:
         weights = torch.empty((B, Na * (Na + 1) // 2), dtype=torch.int32, device=z.device)
     if weights is not None:
-        _require(weights, torch.int32, "weights")
+        _require(weights, torch.int32, "weights", (B, Na * (Na + 1) // 2))
     if flags is not None:
-        _require(flags, torch.uint8, "flags")
-        if tuple(flags.shape) != (B, Na):
-            raise AfcError(f"flags shape {tuple(flags.shape)} != {(B, Na)}")
+        _require(flags, torch.uint8, "flags", (B, Na))
     sp = None
     if n_spectra_per_sb is not None:
+        if len(n_spectra_per_sb) != B:
+            raise AfcError(f"n_spectra_per_sb has {len(n_spectra_per_sb)} entries, expected {B}")
         arr = (C.c_int32 * B)(*[int(v) for v in n_spectra_per_sb])
         sp = C.cast(arr, C.c_void_p)
     _check(_lib.afc_correlate(C.byref(d), DTYPES[dt], _ptr(z), sp, _ptr(flags), _ptr(out), _ptr(weights),
-                              _stream(z.device)), "afc_correlate")
+                              _stream(z, flags, out, weights)), "afc_correlate")
     return out, weights
+
+
+def _cal_shapes(V, M, g):
+    """(P, Na) of calibration buffers V, M [P][Nbl][2][2][2] and g [P][Na][2][2]."""
+    torch = _torch()
+    if g.dim() != 4:
+        raise AfcError(f"g shape {tuple(g.shape)} is not [P][Na][2][2]")
+    P, Na = g.shape[0], g.shape[1]
+    nbl = Na * (Na + 1) // 2
+    _require(g, torch.float32, "g", (P, Na, 2, 2))
+    _require(V, torch.float32, "V", (P, nbl, 2, 2, 2))
+    _require(M, torch.float32, "M", (P, nbl, 2, 2, 2))
+    return P, Na
+
+
+def _workspace(ws, nbytes: int, device):
+    """A caller's workspace (uint8, at least nbytes) or a new one."""
+    torch = _torch()
+    if ws is None:
+        return torch.empty(max(1, nbytes), dtype=torch.uint8, device=device)
+    _require(ws, torch.uint8, "workspace")
+    if ws.numel() < nbytes:
+        raise AfcError(f"workspace holds {ws.numel()} bytes, {nbytes} needed")
+    return ws
 
 
 def calibrate_grad(V, M, g, want_grad: bool = True, workspace=None):
     """V, M float32 [P][Nbl][2][2][2]; g float32 [P][Na][2][2] -> (loss float64 [P][2], grad [P][Na][2][2])."""
     torch = _torch()
-    for t, n in ((V, "V"), (M, "M"), (g, "g")):
-        _require(t, torch.float32, n)
-    P, Na = g.shape[0], g.shape[1]
-    nbl = Na * (Na + 1) // 2
-    if tuple(V.shape) != (P, nbl, 2, 2, 2) or tuple(M.shape) != tuple(V.shape) or tuple(g.shape) != (P, Na, 2, 2):
-        raise AfcError("calibrate_grad: V, M must be [P][Nbl][2][2][2] and g [P][Na][2][2]")
+    P, Na = _cal_shapes(V, M, g)
     loss = torch.empty((P, 2), dtype=torch.float64, device=V.device)
     grad = torch.empty_like(g) if want_grad else None
     wsb = _lib.afc_calibrate_workspace_bytes(Na, P)
-    if workspace is None or workspace.numel() < wsb:
-        workspace = torch.empty(wsb, dtype=torch.uint8, device=V.device)
+    workspace = _workspace(workspace, wsb, V.device)
     _check(_lib.afc_calibrate_grad(Na, P, _ptr(V), _ptr(M), _ptr(g), _ptr(loss), _ptr(grad), _ptr(workspace),
-                                   _stream(V.device)), "afc_calibrate_grad")
+                                   _stream(V, M, g, loss, grad, workspace)), "afc_calibrate_grad")
     return loss, grad
 
 
@@ -344,36 +381,31 @@ def calibrate_solve(V, M, g, n_iter: int = 40, want_loss: bool = True, workspace
     [P][Na][2][2] is updated in place (initial gains in, phase-referenced
     solution out).  Returns the loss float64 [P][2] of the solution (or None)."""
     torch = _torch()
-    for t, n in ((V, "V"), (M, "M"), (g, "g")):
-        _require(t, torch.float32, n)
-    P, Na = g.shape[0], g.shape[1]
-    nbl = Na * (Na + 1) // 2
-    if tuple(V.shape) != (P, nbl, 2, 2, 2) or tuple(M.shape) != tuple(V.shape) or tuple(g.shape) != (P, Na, 2, 2):
-        raise AfcError("calibrate_solve: V, M must be [P][Nbl][2][2][2] and g [P][Na][2][2]")
+    P, Na = _cal_shapes(V, M, g)
     loss = torch.empty((P, 2), dtype=torch.float64, device=V.device) if want_loss else None
     wsb = _lib.afc_calibrate_solve_workspace_bytes(Na, P)
-    if workspace is None or workspace.numel() < wsb:
-        workspace = torch.empty(wsb, dtype=torch.uint8, device=V.device)
+    workspace = _workspace(workspace, wsb, V.device)
     _check(_lib.afc_calibrate_solve(Na, P, _ptr(V), _ptr(M), _ptr(g), int(n_iter), _ptr(loss), _ptr(workspace),
-                                    _stream(V.device)), "afc_calibrate_solve")
+                                    _stream(V, M, g, loss, workspace)), "afc_calibrate_solve")
     return loss
 
 
 def sigma_clip(V, threshold: float = 5.0, out=None, workspace=None):
     """Two-stage sigma clipping of XX / YY: V float32 [P][Nbl][2][2][2] -> uint8 flags [P][Nbl][2]."""
     torch = _torch()
-    _require(V, torch.float32, "V")
+    if V.dim() != 5:
+        raise AfcError("sigma_clip: V must be [P][Nbl][2][2][2]")
     P, nbl = V.shape[0], V.shape[1]
     Na = int(round(((8 * nbl + 1) ** 0.5 - 1) / 2))
-    if Na * (Na + 1) // 2 != nbl or tuple(V.shape[2:]) != (2, 2, 2):
-        raise AfcError("sigma_clip: V must be [P][Nbl][2][2][2]")
+    if Na * (Na + 1) // 2 != nbl:
+        raise AfcError(f"sigma_clip: {nbl} is not a baseline count Na(Na+1)/2")
+    _require(V, torch.float32, "V", (P, nbl, 2, 2, 2))
     if out is None:
         out = torch.empty((P, nbl, 2), dtype=torch.uint8, device=V.device)
-    _require(out, torch.uint8, "out")
+    _require(out, torch.uint8, "out", (P, nbl, 2))
     wsb = _lib.afc_sigma_clip_workspace_bytes(Na, P)
-    if workspace is None or workspace.numel() < wsb:
-        workspace = torch.empty(wsb, dtype=torch.uint8, device=V.device)
-    _check(_lib.afc_sigma_clip(Na, P, _ptr(V), float(threshold), _ptr(out), _ptr(workspace), _stream(V.device)),
+    workspace = _workspace(workspace, wsb, V.device)
+    _check(_lib.afc_sigma_clip(Na, P, _ptr(V), float(threshold), _ptr(out), _ptr(workspace), _stream(V, out, workspace)),
            "afc_sigma_clip")
     return out
 
@@ -381,15 +413,17 @@ def sigma_clip(V, threshold: float = 5.0, out=None, workspace=None):
 def apply_vis_flags(flags, V=None, M=None):
     """Zero, in place, the flagged XX / YY entries of V and / or M."""
     torch = _torch()
-    _require(flags, torch.uint8, "flags")
+    if flags.dim() != 3:
+        raise AfcError(f"flags shape {tuple(flags.shape)} is not [P][Nbl][2]")
     P, nbl = flags.shape[0], flags.shape[1]
     Na = int(round(((8 * nbl + 1) ** 0.5 - 1) / 2))
+    if Na * (Na + 1) // 2 != nbl:
+        raise AfcError(f"apply_vis_flags: {nbl} is not a baseline count Na(Na+1)/2")
+    _require(flags, torch.uint8, "flags", (P, nbl, 2))
     for t, n in ((V, "V"), (M, "M")):
         if t is not None:
-            _require(t, torch.float32, n)
-            if tuple(t.shape) != (P, nbl, 2, 2, 2):
-                raise AfcError(f"apply_vis_flags: {n} does not match the flags")
-    _check(_lib.afc_apply_vis_flags(Na, P, _ptr(flags), _ptr(V), _ptr(M), _stream(flags.device)),
+            _require(t, torch.float32, n, (P, nbl, 2, 2, 2))
+    _check(_lib.afc_apply_vis_flags(Na, P, _ptr(flags), _ptr(V), _ptr(M), _stream(flags, V, M)),
            "afc_apply_vis_flags")
 
 
@@ -400,7 +434,9 @@ class Imager:
 
     def __init__(self, positions, n_subbands: int, grid_size: int, cell_wavelengths: float = 0.5):
         torch = _torch()
-        _require(positions, torch.float64, "positions")
+        if positions.dim() != 2:
+            raise AfcError(f"positions shape {tuple(positions.shape)} is not [Na][2]")
+        _require(positions, torch.float64, "positions", (positions.shape[0], 2))
         self.Na = positions.shape[0]
         self.B = int(n_subbands)
         self.N = int(grid_size)
@@ -415,30 +451,30 @@ class Imager:
     def grid(self, vis, freq_hz, weights=None, out=None):
         """vis float32 [B][64][Nbl][2][2][2], freq_hz float64 [B][64] -> complex grid float32 [N][N][2]."""
         torch = _torch()
-        _require(vis, torch.float32, "vis")
-        _require(freq_hz, torch.float64, "freq_hz")
         nbl = self.Na * (self.Na + 1) // 2
-        if tuple(vis.shape) != (self.B, N_CHANNELS, nbl, 2, 2, 2) or tuple(freq_hz.shape) != (self.B, N_CHANNELS):
-            raise AfcError("imaging: vis must be [B][64][Nbl][2][2][2] and freq_hz [B][64]")
+        dev = self.pos.device
+        _require(vis, torch.float32, "vis", (self.B, N_CHANNELS, nbl, 2, 2, 2))
+        _require(freq_hz, torch.float64, "freq_hz", (self.B, N_CHANNELS))
         if weights is not None:
-            _require(weights, torch.int32, "weights")
+            _require(weights, torch.int32, "weights", (self.B, nbl))
         if out is None:
-            out = torch.empty((self.N, self.N, 2), dtype=torch.float32, device=vis.device)
-        _require(out, torch.float32, "out")
+            out = torch.empty((self.N, self.N, 2), dtype=torch.float32, device=dev)
+        _require(out, torch.float32, "out", (self.N, self.N, 2))
         _check(_lib.afc_grid_visibilities(self.Na, self.B, _ptr(vis), _ptr(weights), _ptr(self.pos), _ptr(freq_hz),
                                           self.N, self.du, _ptr(out), _ptr(self.norm), _ptr(self.ws),
-                                          _stream(vis.device)), "afc_grid_visibilities")
+                                          _stream(self.pos, vis, weights, freq_hz, out)), "afc_grid_visibilities")
         return out
 
     def image(self, grid, out=None):
         """grid float32 [N][N][2] (from grid()) -> image float32 [N][N], normalised by the gridded weight."""
         torch = _torch()
-        _require(grid, torch.float32, "grid")
+        dev = self.pos.device
+        _require(grid, torch.float32, "grid", (self.N, self.N, 2))
         if out is None:
-            out = torch.empty((self.N, self.N), dtype=torch.float32, device=grid.device)
-        _require(out, torch.float32, "out")
+            out = torch.empty((self.N, self.N), dtype=torch.float32, device=dev)
+        _require(out, torch.float32, "out", (self.N, self.N))
         _check(_lib.afc_image_from_grid(self.N, _ptr(grid), _ptr(self.norm), _ptr(out), _ptr(self.ws),
-                                        _stream(grid.device)), "afc_image_from_grid")
+                                        _stream(self.pos, grid, out)), "afc_image_from_grid")
         return out
 
 
@@ -515,19 +551,34 @@ class Plan:
         return PlanInfo(a.value, c.value, d.value)
 
     def launch(self, x, taps, gains, workspace, vis, flags=None, weights=None):
+        """x int16 [B][L][Na][2][2]; gains host [B] (int8 subbands); workspace
+        uint8 of workspace_bytes; vis int32 or float32 [B][64][Nbl][2][2][2]
+        (8 bytes per complex value whatever each subband's type); flags uint8
+        [B][Na] or None; weights int32 [B][Nbl] or None."""
         torch = _torch()
-        _require(x, torch.int16, "x")
-        _require(taps, torch.float32, "taps")
-        _require(workspace, torch.uint8, "workspace")
+        if not getattr(self, "_h", None):
+            raise AfcError("plan is closed")
+        B, Na = len(self.S), self.n_antennas
+        nbl = Na * (Na + 1) // 2
         rows = (self.dims.n_spectra + N_TAPS - 1) * N_CHANNELS
-        if x.shape[0] != len(self.S) or x.shape[1] != rows:
-            raise AfcError(f"x must be [{len(self.S)}][{rows}][..]: got {tuple(x.shape)}")
-        if workspace.numel() < self.workspace_bytes:
-            raise AfcError("workspace too small")
-        B = len(self.S)
+        if x.dim() < 3 or x.shape[0] != B or x.shape[1] != rows or x[0, 0].numel() != 4 * Na:
+            raise AfcError(f"x must be [{B}][{rows}][{Na}][2][2]: got {tuple(x.shape)}")
+        _require(x, torch.int16, "x")
+        dev = x.device
+        _require(taps, torch.float32, "taps", (N_TAPS * N_CHANNELS,))
+        if vis.dtype not in (torch.int32, torch.float32):
+            raise AfcError(f"vis must be int32 or float32, got {vis.dtype}")
+        _require(vis, vis.dtype, "vis", visibility_shape(B, Na))
+        if flags is not None:
+            _require(flags, torch.uint8, "flags", (B, Na))
+        if weights is not None:
+            _require(weights, torch.int32, "weights", (B, nbl))
+        _workspace(workspace, self.workspace_bytes, dev)
+        if len(gains) != B:
+            raise AfcError(f"gains has {len(gains)} entries, expected {B}")
         g = (C.c_float * B)(*[float(v) for v in gains])
         _check(_lib.afc_plan_launch(self._h, _ptr(x), _ptr(taps), C.cast(g, C.c_void_p), _ptr(workspace),
-                                    _ptr(flags), _ptr(vis), _ptr(weights), _stream(x.device)), "afc_plan_launch")
+                                    _ptr(flags), _ptr(vis), _ptr(weights), _stream(x, taps, workspace, flags, vis, weights)), "afc_plan_launch")
 
     def close(self):
         if getattr(self, "_h", None):

@@ -401,8 +401,7 @@ struct afc_plan {
     size_t ws_bytes = 0;
     int N = 0, Na = 0;
     int64_t L = 0;
-    // device tables
-    PpfItem* d_items = nullptr;
+    // device tables (d_sbs and the work lists never change after creation)
     XSubband* d_sbs = nullptr;
     struct Mode {
         bool used = false;
@@ -413,12 +412,22 @@ struct afc_plan {
         XcdRanges ranges{};
     } mode[2];
     std::vector<PpfItem> items;
-    // graph
+    // A captured graph with the channeliser's item table it reads (the table
+    // holds the int8 gains, so each capture has its own).  `done` is recorded
+    // on the caller's stream after every launch of the graph: a retired
+    // capture is freed once its last launch has completed.
+    struct Capture {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        PpfItem* d_items = nullptr;
+        std::vector<PpfItem> h_items;   // source of the table's async upload
+        hipEvent_t done = nullptr;
+        std::vector<const void*> key_ptrs;
+        std::vector<float> key_gains;
+    };
     hipStream_t cap_stream = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    std::vector<const void*> key_ptrs;
-    std::vector<float> key_gains;
+    Capture* cur = nullptr;
+    std::vector<Capture*> retired;
 };
 
 namespace {
@@ -595,11 +604,74 @@ int tune_mode0(afc_plan* p, int& tile_out, int& wg_per_cu_out) {
     return AFC_OK;
 }
 
-void plan_free_graph(afc_plan* p) {
-    if (p->exec) hipGraphExecDestroy(p->exec);
-    if (p->graph) hipGraphDestroy(p->graph);
-    p->exec = nullptr;
-    p->graph = nullptr;
+void free_capture(afc_plan::Capture* c) {
+    if (!c) return;
+    if (c->exec) hipGraphExecDestroy(c->exec);
+    if (c->graph) hipGraphDestroy(c->graph);
+    if (c->d_items) hipFree(c->d_items);
+    if (c->done) hipEventDestroy(c->done);
+    delete c;
+}
+
+// Free the retired captures whose last launch has completed (or, with
+// wait, all of them after their last launch).
+void reap_captures(afc_plan* p, bool wait) {
+    std::vector<afc_plan::Capture*> keep;
+    for (afc_plan::Capture* c : p->retired) {
+        if (wait) hipEventSynchronize(c->done);
+        if (wait || hipEventQuery(c->done) == hipSuccess)
+            free_capture(c);
+        else
+            keep.push_back(c);
+    }
+    p->retired.swap(keep);
+}
+
+// Capture the plan's launches into a new graph for these buffers and gains.
+// The item table is uploaded on the caller's stream, so it is in place
+// before the graph's first launch there and no earlier launch can see it.
+int capture_plan(afc_plan* p, const int16_t* x, const float* taps, const std::vector<float>& gains, void* z_workspace,
+                 const uint8_t* flags, void* vis, int32_t* weights, hipStream_t stream,
+                 const std::vector<const void*>& key) {
+    const int B = p->d.n_subbands;
+    auto* c = new afc_plan::Capture();
+    c->h_items = p->items;
+    for (int b = 0; b < B; ++b) c->h_items[b].gain = gains[b];
+    hipError_t e = hipMalloc(&c->d_items, B * sizeof(PpfItem));
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->done, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->d_items, c->h_items.data(), B * sizeof(PpfItem), hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) {
+        free_capture(c);
+        return hip_fail(e, "plan item table upload");
+    }
+    e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        free_capture(c);
+        return hip_fail(e, "graph capture begin");
+    }
+    hipError_t le = launch_ppf_batched(x, taps, z_workspace, c->d_items, B, p->N, p->d.n_spectra, p->cap_stream);
+    for (int m = 0; m < 2 && le == hipSuccess; ++m) {
+        const afc_plan::Mode& md = p->mode[m];
+        if (!md.used) continue;
+        le = launch_xengine_list(z_workspace, vis, weights, flags, p->d_sbs, md.d_work, md.ranges, p->N, p->Na, m,
+                                 md.tile, p->cap_stream);
+    }
+    e = hipStreamEndCapture(p->cap_stream, &c->graph);
+    if (le != hipSuccess || e != hipSuccess) {
+        free_capture(c);
+        return hip_fail(le != hipSuccess ? le : e, "plan graph capture");
+    }
+    e = hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        free_capture(c);
+        return hip_fail(e, "graph instantiate");
+    }
+    c->key_ptrs = key;
+    c->key_gains = gains;
+    if (p->cur) p->retired.push_back(p->cur);
+    p->cur = c;
+    return AFC_OK;
 }
 
 }  // namespace
@@ -654,9 +726,7 @@ AFC_API int afc_plan_create(const afc_dims* d, const afc_dtype* dtype_per_sb, co
                               p->dt[b], 1.0f};
     }
     hipError_t e = hipMalloc(&p->d_sbs, B * sizeof(XSubband));
-    if (e == hipSuccess) e = hipMalloc(&p->d_items, B * sizeof(PpfItem));
     if (e == hipSuccess) e = hipMemcpy(p->d_sbs, sbs.data(), B * sizeof(XSubband), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(p->d_items, p->items.data(), B * sizeof(PpfItem), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         afc_plan_destroy(p);
@@ -735,47 +805,25 @@ AFC_API int afc_plan_launch(afc_plan* p, const int16_t* x, const float* taps, co
         }
     }
     const std::vector<const void*> key = {x, taps, z_workspace, flags, vis, weights};
-    const bool same = p->exec && key == p->key_ptrs && gains == p->key_gains;
-    hipError_t e;
+    const bool same = p->cur && key == p->cur->key_ptrs && gains == p->cur->key_gains;
+    reap_captures(p, false);
     if (!same) {
-        plan_free_graph(p);
-        for (int b = 0; b < B; ++b) p->items[b].gain = gains[b];
-        e = hipMemcpy(p->d_items, p->items.data(), B * sizeof(PpfItem), hipMemcpyHostToDevice);
-        if (e != hipSuccess) return hip_fail(e, "plan gain upload");
-        e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) return hip_fail(e, "graph capture begin");
-        hipError_t le = launch_ppf_batched(x, taps, z_workspace, p->d_items, B, p->N, p->d.n_spectra, p->cap_stream);
-        for (int m = 0; m < 2 && le == hipSuccess; ++m) {
-            const afc_plan::Mode& md = p->mode[m];
-            if (!md.used) continue;
-            le = launch_xengine_list(z_workspace, vis, weights, flags, p->d_sbs, md.d_work, md.ranges, p->N, p->Na,
-                                     m, md.tile, p->cap_stream);
-        }
-        e = hipStreamEndCapture(p->cap_stream, &p->graph);
-        if (le != hipSuccess) {
-            plan_free_graph(p);
-            return hip_fail(le, "plan kernel launch during capture");
-        }
-        if (e != hipSuccess) return hip_fail(e, "graph capture end");
-        e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            plan_free_graph(p);
-            return hip_fail(e, "graph instantiate");
-        }
-        p->key_ptrs = key;
-        p->key_gains = gains;
+        const int rc = capture_plan(p, x, taps, gains, z_workspace, flags, vis, weights, stream, key);
+        if (rc != AFC_OK) return rc;
     }
-    e = hipGraphLaunch(p->exec, stream);
+    hipError_t e = hipGraphLaunch(p->cur->exec, stream);
+    if (e == hipSuccess) e = hipEventRecord(p->cur->done, stream);
     if (e != hipSuccess) return hip_fail(e, "graph launch");
     return AFC_OK;
 }
 
 AFC_API void afc_plan_destroy(afc_plan* p) {
     if (!p) return;
-    plan_free_graph(p);
+    if (p->cur) p->retired.push_back(p->cur);
+    p->cur = nullptr;
+    reap_captures(p, true);
     for (auto& md : p->mode)
         if (md.d_work) hipFree(md.d_work);
-    if (p->d_items) hipFree(p->d_items);
     if (p->d_sbs) hipFree(p->d_sbs);
     if (p->cap_stream) hipStreamDestroy(p->cap_stream);
     delete p;

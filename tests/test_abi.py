@@ -109,3 +109,105 @@ def test_fine_channeliser_sizes_and_argument_checks(afc):
     huge = afc.dims(576, 1, 4000)
     assert call(dims=huge) == -2
     assert b"2^31" in lib.afc_last_error()
+
+
+def _meta(shape, dtype):
+    import torch
+    return torch.empty(shape, dtype=dtype, device="meta")
+
+
+def _raises(afc, fn, *words):
+    with pytest.raises(afc.AfcError) as e:
+        fn()
+    msg = str(e.value)
+    for w in words:
+        assert w in msg, msg
+    return msg
+
+
+def test_binding_rejects_wrong_buffer_sizes_on_host(afc):
+    """Every caller buffer's size is checked before its device: a buffer of
+    the wrong shape is an AfcError naming the shape, never a launch.  (Meta
+    tensors carry shapes without memory; a buffer of the right shape then
+    fails only because it is not on a GPU.)"""
+    import torch
+    B, Na, S = 2, 6, 20
+    N, nbl = 2 * Na, Na * (Na + 1) // 2
+    z = _meta(afc.channelised_shape(B, S, N), torch.int8)
+    vis_ok = _meta(afc.visibility_shape(B, Na), torch.int32)
+    # correlate: out, weights, flags, per-subband S
+    _raises(afc, lambda: afc.correlate(z, S, out=_meta(afc.visibility_shape(B, Na - 1), torch.int32)), "out shape")
+    _raises(afc, lambda: afc.correlate(z, S, out=vis_ok, weights=_meta((B, nbl + 1), torch.int32)), "weights shape")
+    _raises(afc, lambda: afc.correlate(z, S, out=vis_ok, flags=_meta((B, Na + 1), torch.uint8)), "flags shape")
+    _raises(afc, lambda: afc.correlate(z, S, n_spectra_per_sb=[S], out=vis_ok), "entries")
+    _raises(afc, lambda: afc.correlate(z, S, out=_meta(afc.visibility_shape(B, Na), torch.float32)), "int32")
+    _raises(afc, lambda: afc.correlate(z, S + 8), "blocks")
+    _raises(afc, lambda: afc.correlate(z, S, out=vis_ok), "GPU tensor")          # right sizes: only the device
+    # zero_invalid: block count of z against n_spectra, validity words
+    sv = _meta(afc.validity_shape(B, S, Na), torch.int32)
+    _raises(afc, lambda: afc.zero_invalid(z, sv, S + 16), "z shape")
+    _raises(afc, lambda: afc.zero_invalid(z, _meta(afc.validity_shape(B, S + 40, Na), torch.int32), S),
+            "spec_valid shape")
+    # validity weights and normalisation
+    _raises(afc, lambda: afc.validity_weights(sv, S, out=_meta((B, nbl - 1), torch.int32)), "out shape")
+    _raises(afc, lambda: afc.validity_weights(sv, S, out=_meta((B, nbl), torch.int32),
+                                              flags=_meta((B, 3), torch.uint8)), "flags shape")
+    _raises(afc, lambda: afc.normalise_visibilities(vis_ok, _meta((B, nbl - 1), torch.int32)), "weights shape")
+    _raises(afc, lambda: afc.normalise_visibilities(vis_ok, _meta((B, nbl), torch.int32),
+                                                    out=_meta(afc.visibility_shape(B + 1, Na), torch.float32)),
+            "out shape")
+    # channelise: taps and out
+    x = _meta((B, (S + 15) * 64, Na, 2, 2), torch.int16)
+    _raises(afc, lambda: afc.channelise(x, _meta((1000,), torch.float32), S), "taps shape")
+    _raises(afc, lambda: afc.channelise(x, _meta((1024,), torch.float32), S, "i8",
+                                        out=_meta(afc.channelised_shape(B, S + 8, N), torch.int8)), "out shape")
+    # calibration: V, M, g, workspace
+    P = 3
+    g = _meta((P, Na, 2, 2), torch.float32)
+    V = _meta((P, nbl, 2, 2, 2), torch.float32)
+    _raises(afc, lambda: afc.calibrate_grad(_meta((P, nbl + 1, 2, 2, 2), torch.float32), V, g), "V shape")
+    _raises(afc, lambda: afc.calibrate_grad(V, _meta((P - 1, nbl, 2, 2, 2), torch.float32), g), "M shape")
+    _raises(afc, lambda: afc.calibrate_solve(V, V, _meta((P, Na, 2), torch.float32)), "g shape")
+    _raises(afc, lambda: afc.sigma_clip(V, out=_meta((P, nbl, 3), torch.uint8)), "out shape")
+    _raises(afc, lambda: afc.apply_vis_flags(_meta((P, nbl, 2), torch.uint8), V=_meta((P, nbl, 2, 2), torch.float32)),
+            "V shape")
+
+
+def test_plan_launch_rejects_wrong_buffer_sizes_on_host(afc):
+    """Plan.launch checks x, taps, vis, weights, flags, gains and the
+    workspace before calling the library (the plan's handle is never reached
+    here: every call below fails first)."""
+    import torch
+    B, Na, S = 2, 6, 40
+    nbl = Na * (Na + 1) // 2
+
+    class FakePlan(afc.Plan):
+        workspace_bytes = 1000
+
+        def __init__(self):
+            self._h = C.c_void_p(1)
+            self.n_antennas, self.S, self.dims = Na, [S, S], afc.dims(Na, B, S)
+
+        def close(self):
+            self._h = None
+
+    plan = FakePlan()
+    try:
+        x = _meta((B, (S + 15) * 64, Na, 2, 2), torch.int16)
+        taps = _meta((1024,), torch.float32)
+        ws = _meta((1000,), torch.uint8)
+        vis = _meta(afc.visibility_shape(B, Na), torch.int32)
+        g = [1.0, 1.0]
+        _raises(afc, lambda: plan.launch(_meta((B, (S + 15) * 64 - 1, Na, 2, 2), torch.int16), taps, g, ws, vis),
+                "x must be")
+        _raises(afc, lambda: plan.launch(x, _meta((512,), torch.float32), g, ws, vis), "taps shape")
+        _raises(afc, lambda: plan.launch(x, taps, g, ws, _meta(afc.visibility_shape(B, Na + 1), torch.int32)),
+                "vis shape")
+        _raises(afc, lambda: plan.launch(x, taps, g, ws, vis, flags=_meta((B, Na - 1), torch.uint8)), "flags shape")
+        _raises(afc, lambda: plan.launch(x, taps, g, ws, vis, weights=_meta((B + 1, nbl), torch.int32)),
+                "weights shape")
+        _raises(afc, lambda: plan.launch(x, taps, g, _meta((999,), torch.uint8), vis), "workspace holds")
+        _raises(afc, lambda: plan.launch(x, taps, [1.0], ws, vis), "gains has")
+        _raises(afc, lambda: plan.launch(x, taps, g, ws, vis), "GPU tensor")     # right sizes: only the device
+    finally:
+        plan.close()

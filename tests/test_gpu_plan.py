@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 import workloads as W
-from gpu_util import log, normalised_error, vis_to_complex
+from gpu_util import gather_rows, log, normalised_error, vis_to_complex
 
 pytestmark = pytest.mark.gpu
 
@@ -64,19 +64,34 @@ def _run_plan(afc, dev, Na, S_list, dts, flags_np, tune_cache=None, check_oracle
             got = got.view(torch.float32)
         assert torch.equal(got, vr[0]), f"subband {b} differs from the plain path"
         assert torch.equal(w[b], wr[0])
-        if check_oracle and dts[b] == "f16" and b < 2:
-            y = oracle.ppf_subband(x[b].cpu().numpy(), taps_np, 64, 16, S_list[b])
-            v = vis_to_complex(got.cpu().numpy())
-            for ch in (0, 31):
-                Vref, Wref = oracle.xcorr(y[ch], flags_np[b])
-                e = normalised_error(v[ch], Vref, Na)
-                a_, b_ = np.tril_indices(Na)
-                hit = (flags_np[b][a_] == 1) | (flags_np[b][b_] == 1)
-                assert np.all(v[ch][hit] == 0)
-                assert e[~hit].max() <= 2e-3
-            np.testing.assert_array_equal(w[b].cpu().numpy(), Wref)
+        if check_oracle and b < 3:
+            _check_subband_against_oracle(x[b], zr, got, w[b], S_list[b], dts[b], flags_np[b], Na, taps_np)
     plan.close()
     return return_info
+
+
+def _check_subband_against_oracle(xb, zr, got, wb, S_b, dt, flags_b, Na, taps_np, channels=(0, 31)):
+    """One subband of the plan against the oracle: int8 exactly against the
+    integer correlator on the int8 samples the channeliser produced; fp32
+    (<= 1e-5) and fp16 (<= 2e-3) against the FP64 chain, normalised by
+    sqrt(V_ii V_jj).  Flagged baselines are exactly zero."""
+    a_, b_ = np.tril_indices(Na)
+    hit = (flags_b[a_] == 1) | (flags_b[b_] == 1)
+    if dt == "i8":
+        for ch in channels:
+            rows = gather_rows(zr, 0, ch, range(2 * Na), S_b)
+            Vref, Wref = oracle.xcorr_int(rows, flags_b)
+            np.testing.assert_array_equal(got[ch].cpu().numpy(), Vref.astype(np.int32))
+    else:
+        y = oracle.ppf_subband(xb.cpu().numpy(), taps_np, 64, 16, S_b)
+        v = vis_to_complex(got.cpu().numpy())
+        for ch in channels:
+            Vref, Wref = oracle.xcorr(y[ch], flags_b)
+            e = normalised_error(v[ch], Vref, Na)
+            assert np.all(v[ch][hit] == 0)
+            tol = 1e-5 if dt == "f32" else 2e-3
+            assert e[~hit].max() <= tol, (dt, ch, float(e[~hit].max()))
+    np.testing.assert_array_equal(wb.cpu().numpy(), Wref)
 
 
 def test_plan_small_mixed(afc, dev, tmp_path):
@@ -135,12 +150,77 @@ def test_plan_full_size_a12_batched(afc, dev, tmp_path):
     plan.launch(x, taps, [gain] * B, ws, vis, flags=fl, weights=w)
     torch.cuda.synchronize()
     log(f"  plan info {plan.info()}")
+    rng = np.random.default_rng(5)
     for b in (0, 13, 31):
-        zr, vr, wr = _plain(afc, x[b:b + 1], taps, int(bp.n_spectra[b]), dts[b], gain, fl[b:b + 1], Na)
+        S_b = int(bp.n_spectra[b])
+        zr, vr, wr = _plain(afc, x[b:b + 1], taps, S_b, dts[b], gain, fl[b:b + 1], Na)
         got = vis[b] if dts[b] == "i8" else vis[b].view(torch.float32)
         assert torch.equal(got, vr[0])
         assert torch.equal(w[b], wr[0])
+        # sampled baselines against the oracle: int8 exactly on the GPU's own
+        # int8 samples, fp16 against the FP64 chain (<= 2e-3 normalised)
+        ants = np.sort(rng.choice(Na, size=12, replace=False))
+        inputs = np.stack([2 * ants, 2 * ants + 1], 1).reshape(-1)
+        fl_b = bp.flags[b]
+        y = None if dts[b] == "i8" else oracle.ppf_subband(x[b].cpu().numpy(), taps_np, 64, 16, S_b, inputs=inputs)
+        for ch in (3, 40):
+            g = got[ch].cpu().numpy()
+            if dts[b] == "i8":
+                rows = gather_rows(zr, 0, ch, inputs, S_b)
+            for ia in range(len(ants)):
+                for ib in range(ia + 1):
+                    a, c = ants[ia], ants[ib]
+                    blx = a * (a + 1) // 2 + c
+                    if fl_b[a] or fl_b[c]:
+                        assert np.all(g[blx] == 0) and int(w[b, blx]) == 0
+                        continue
+                    assert int(w[b, blx]) == S_b
+                    pairs = [(2 * ia + p, 2 * ib + q) for p in range(2) for q in range(2)]
+                    if dts[b] == "i8":
+                        ref = oracle.xcorr_pairs_int(rows, np.array(pairs)).reshape(2, 2, 2)
+                        np.testing.assert_array_equal(g[blx], ref.astype(np.int32))
+                    else:
+                        ref = oracle.xcorr_pairs(y[ch], np.array(pairs)).reshape(2, 2)
+                        auto_a = oracle.xcorr_pairs(y[ch], np.array([(2 * ia, 2 * ia), (2 * ia + 1, 2 * ia + 1)])).real
+                        auto_c = oracle.xcorr_pairs(y[ch], np.array([(2 * ib, 2 * ib), (2 * ib + 1, 2 * ib + 1)])).real
+                        den = np.sqrt(np.outer(auto_a, auto_c))
+                        e = np.abs(vis_to_complex(g[blx]) - ref) / den
+                        assert e.max() <= 2e-3, (b, ch, a, c, float(e.max()))
         del zr, vr, wr
     plan.close()
     del x, ws, vis
     torch.cuda.empty_cache()
+
+
+def test_plan_relaunch_new_gains_on_side_stream(afc, dev):
+    """Two launches on a side stream with different int8 gains and different
+    output buffers, back to back without synchronisation, then a third with
+    the first gains again: each result equals the plain channelise +
+    correlate path with its own gains (a launch in flight never sees the
+    next launch's gains)."""
+    log("plan relaunch with new gains on a side stream")
+    Na, S_list, dts = 20, [400, 90, 257], ["i8", "f16", "i8"]
+    B = len(S_list)
+    cfg = W.Config("plan2", Na, B, n_spectra=max(S_list), sigma_n=32.0, n_sources=1, seed=33)
+    x = W.make_voltages(cfg, device=dev)
+    taps_np = W.prototype_taps()
+    taps = torch.from_numpy(taps_np).to(dev)
+    g1 = W.requant_gain(cfg, taps_np)
+    gains = [[g1] * B, [g1 * 0.37] * B, [g1] * B]
+    plan = afc.Plan(Na, S_list, dts)
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    nbl = Na * (Na + 1) // 2
+    outs = [torch.full((B, 64, nbl, 2, 2, 2), -1, dtype=torch.int32, device=dev) for _ in range(3)]
+    side = torch.cuda.Stream(device=dev)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        for k in range(3):
+            plan.launch(x, taps, gains[k], ws, outs[k])
+    side.synchronize()
+    for k in range(3):
+        for b in range(B):
+            _, vr, _ = _plain(afc, x[b:b + 1], taps, S_list[b], dts[b], gains[k][b], None, Na)
+            got = outs[k][b] if dts[b] == "i8" else outs[k][b].view(torch.float32)
+            assert torch.equal(got, vr[0]), f"launch {k} subband {b} differs from the plain path"
+    assert not torch.equal(outs[0][0], outs[1][0])        # the gains really differ
+    plan.close()

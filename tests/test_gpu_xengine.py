@@ -111,7 +111,7 @@ def test_int8_extreme_values_exact(afc, dev):
         np.testing.assert_array_equal(v[0, ch].astype(np.int64), Vref)
 
 
-@pytest.mark.parametrize("dtype", ["i8", "f16"])
+@pytest.mark.parametrize("dtype", ["i8", "f16", "f32"])
 def test_full_size_sampled(afc, dev, dtype):
     """AARTFAAC-12 shape: 1152 receivers, 16 subbands, 3051 spectra, sampled baselines."""
     Na, B, S = 576, 16, 3051
