@@ -279,6 +279,26 @@ AFC_API int afc_calibrate_grad(int32_t n_antennas, int32_t n_channels, const voi
                                void* workspace, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * afc_calibrate_grad_noalloc -- afc_calibrate_grad without a workspace, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation).  Same arguments,
+ * kernels and results as afc_calibrate_grad; it calls no allocator.
+ *
+ * The per-tile partial sums live in a fixed array of
+ * AFC_CAL_NOALLOC_MAX_BYTES bytes of device memory that the library holds on
+ * every GPU it runs on until the process ends (its address is looked up once
+ * per device, on the first call there).  Shapes whose
+ * afc_calibrate_workspace_bytes exceeds that size return AFC_ERR_UNSUPPORTED
+ * (576 antennas x 64 channels need 11.8 MB).  Nothing in the array has to
+ * start at zero, but all calls on one GPU share it: calls that overlap on
+ * one GPU (two streams or two threads) race and must be serialised.
+ * ------------------------------------------------------------------------- */
+#define AFC_CAL_NOALLOC_MAX_BYTES (16u << 20)
+AFC_API int afc_calibrate_grad_noalloc(int32_t n_antennas, int32_t n_channels, const void* V,
+                                       const void* M, const void* g, double* loss, void* grad,
+                                       hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * afc_calibrate_solve -- per-channel gains for XX and YY (Sec. "Calibration
  * Pipeline": amplitude and phase calibration at the channel level against
  * a point-source model), minimising the afc_calibrate_grad loss.

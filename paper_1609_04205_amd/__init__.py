@@ -56,6 +56,7 @@ _lib.afc_channelise_fine.argtypes = [C.POINTER(Dims), _vp, _vp, _vp, _vp, C.POIN
 _lib.afc_calibrate_workspace_bytes.argtypes = [_i32, _i32]
 _lib.afc_calibrate_workspace_bytes.restype = _sz
 _lib.afc_calibrate_grad.argtypes = [_i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.afc_calibrate_grad_noalloc.argtypes = [_i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.afc_calibrate_solve_workspace_bytes.argtypes = [_i32, _i32]
 _lib.afc_calibrate_solve_workspace_bytes.restype = _sz
 _lib.afc_calibrate_solve.argtypes = [_i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp]
@@ -81,7 +82,7 @@ EXPORTS = ["afc_channelised_bytes", "afc_visibility_bytes", "afc_channelise",
            "afc_normalise_visibilities", "afc_calibrate_solve_workspace_bytes", "afc_calibrate_solve",
            "afc_sigma_clip_workspace_bytes", "afc_sigma_clip", "afc_apply_vis_flags",
            "afc_imaging_workspace_bytes", "afc_grid_visibilities", "afc_image_from_grid",
-           "afc_calibrate_workspace_bytes", "afc_calibrate_grad", "afc_plan_create",
+           "afc_calibrate_workspace_bytes", "afc_calibrate_grad", "afc_calibrate_grad_noalloc", "afc_plan_create",
            "afc_plan_workspace_bytes", "afc_plan_launch", "afc_plan_info", "afc_plan_destroy",
            "afc_last_error"]
 
@@ -373,6 +374,24 @@ def calibrate_grad(V, M, g, want_grad: bool = True, workspace=None):
     workspace = _workspace(workspace, wsb, V.device)
     _check(_lib.afc_calibrate_grad(Na, P, _ptr(V), _ptr(M), _ptr(g), _ptr(loss), _ptr(grad), _ptr(workspace),
                                    _stream(V, M, g, loss, grad, workspace)), "afc_calibrate_grad")
+    return loss, grad
+
+
+CAL_NOALLOC_MAX_BYTES = 16 << 20
+
+
+def calibrate_grad_noalloc(V, M, g, loss, grad=None):
+    """afc_calibrate_grad_noalloc: as calibrate_grad into caller-provided
+    loss float64 [P][2] and grad float32 [P][Na][2][2] (or None), with the
+    library's fixed per-GPU scratch instead of a workspace.  Allocates
+    nothing; calls that overlap on one GPU race."""
+    torch = _torch()
+    P, Na = _cal_shapes(V, M, g)
+    _require(loss, torch.float64, "loss", (P, 2))
+    if grad is not None:
+        _require(grad, torch.float32, "grad", (P, Na, 2, 2))
+    _check(_lib.afc_calibrate_grad_noalloc(Na, P, _ptr(V), _ptr(M), _ptr(g), _ptr(loss), _ptr(grad),
+                                           _stream(V, M, g, loss, grad)), "afc_calibrate_grad_noalloc")
     return loss, grad
 
 

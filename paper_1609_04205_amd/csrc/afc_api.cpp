@@ -289,6 +289,25 @@ AFC_API int afc_calibrate_grad(int32_t n_antennas, int32_t n_channels, const voi
     return AFC_OK;
 }
 
+AFC_API int afc_calibrate_grad_noalloc(int32_t n_antennas, int32_t n_channels, const void* V, const void* M,
+                                       const void* g, double* loss, void* grad, hipStream_t stream) {
+    g_err.clear();
+    if (n_antennas < 1 || n_antennas > 4096) return fail(AFC_ERR_INVALID, "n_antennas = %d outside 1..4096", n_antennas);
+    if (n_channels < 1 || n_channels > 65535) return fail(AFC_ERR_INVALID, "n_channels = %d outside 1..65535", n_channels);
+    if (!V || !M || !g || !loss) return fail(AFC_ERR_INVALID, "NULL pointer (V, M, g or loss)");
+    const size_t need = cal_workspace_bytes(n_antennas, n_channels);
+    if (need > kCalScratchBytes)
+        return fail(AFC_ERR_UNSUPPORTED, "%d antennas x %d channels need %zu bytes of scratch, more than the %zu built in",
+                    n_antennas, n_channels, need, kCalScratchBytes);
+    void* scratch = nullptr;
+    hipError_t e = cal_scratch_address(&scratch);
+    if (e != hipSuccess) return hip_fail(e, "scratch address");
+    e = launch_calibrate(n_antennas, n_channels, reinterpret_cast<const float2*>(V), reinterpret_cast<const float2*>(M),
+                         reinterpret_cast<const float2*>(g), loss, reinterpret_cast<float2*>(grad), scratch, stream);
+    if (e != hipSuccess) return hip_fail(e, "calibration launch");
+    return AFC_OK;
+}
+
 AFC_API size_t afc_calibrate_solve_workspace_bytes(int32_t n_antennas, int32_t n_channels) {
     if (n_antennas < 1 || n_antennas > 4096 || n_channels < 1 || n_channels > 65535) return 0;
     return cal_solve_workspace_bytes(n_antennas, n_channels);

@@ -130,6 +130,10 @@ hipError_t launch_image(const float2* grid, const double* norm, float* image, in
 
 // ---------------------------------------------------------------- calibration
 size_t cal_workspace_bytes(int Na, int P);
+// Fixed device scratch of afc_calibrate_grad_noalloc (one per GPU) and its
+// address on the current device.
+constexpr size_t kCalScratchBytes = (size_t)AFC_CAL_NOALLOC_MAX_BYTES;
+hipError_t cal_scratch_address(void** out);
 hipError_t launch_calibrate(int Na, int P, const float2* V, const float2* M, const float2* g,
                             double* loss, float2* grad, void* ws, hipStream_t stream);
 // gain solver: n_iter preconditioned-gradient (alternating least-squares)

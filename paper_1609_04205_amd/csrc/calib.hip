@@ -24,7 +24,9 @@
 // tiles in a fixed order (float64) and writes -4 x the sum; the first block
 // of each (channel, polarisation) adds the tile losses in a fixed order.
 // No atomics: the result is bitwise reproducible.
+#include <mutex>
 #include <utility>
+#include <vector>
 
 #include "afc_internal.h"
 
@@ -422,6 +424,32 @@ hipError_t launch_calibrate_solve(int Na, int P, const float2* V, const float2* 
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (loss) return launch_calibrate(Na, P, V, M, g, loss, nullptr, ws, stream);
+    return hipSuccess;
+}
+
+// Scratch of the allocation-free gradient entry point: the per-tile partial
+// sums (every element read is written earlier in the same call, so nothing
+// has to start at zero).  Each GPU the library runs on holds its own copy
+// until the process ends.  Host code never passes `cal_scratch` itself to a
+// kernel (on the host it names a stand-in, not the device address): it uses
+// the address hipGetSymbolAddress returns for the current device.
+__device__ __align__(256) unsigned char cal_scratch[kCalScratchBytes];
+
+hipError_t cal_scratch_address(void** out) {
+    static std::mutex mu;
+    static std::vector<void*> ptrs;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)ptrs.size() <= dev) ptrs.resize(dev + 1, nullptr);
+    if (!ptrs[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(cal_scratch));
+        if (e != hipSuccess) return e;
+        ptrs[dev] = p;
+    }
+    *out = ptrs[dev];
     return hipSuccess;
 }
 
