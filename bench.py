@@ -25,7 +25,9 @@ bounded sample on the host cores.
 import argparse
 import json
 import os
+import subprocess
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -74,7 +76,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="time only the int8 step")
-    ap.add_argument("--cpu-sample-spectra", type=int, default=512)
+    ap.add_argument("--cpu-sample-spectra", type=int, default=3051)
+    ap.add_argument("--cpu-one-thread-spectra", type=int, default=64)
     ap.add_argument("--fine-only", action="store_true",
                     help="only time the 256-channel configuration (fine channeliser + X-engine on its output)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -278,7 +281,36 @@ def main():
                        "real_time_factor": round(data_s / ((f32_xe + t32.ms("ppf")) * 1e-3), 2)}
         out["int8_speedup_over_fp32_xengine"] = round(f32_xe / xe_ms, 2)
         log(f"fp32 xengine {f32_xe:.3f} ms")
-        del z32, vis32, x, vis
+        parity_vis = {"f32": _sampled_vis(torch, vis32, 0, PARITY_ANTENNAS)}
+        del z32, vis32
+
+        # ---- fp16 path on the same input (fp16 samples, float32 accumulation)
+        z16 = torch.empty(afc.channelised_shape(B, S, N), dtype=torch.float16, device=dev)
+        vis16 = torch.empty(afc.visibility_shape(B, Na), dtype=torch.float32, device=dev)
+        t16 = Timer(torch)
+        for it in range(3):
+            tm = t16 if it > 0 else None
+            if tm:
+                e = tm.rec("ppf")
+            afc.channelise(x, taps, S, "f16", out=z16)
+            if tm:
+                e.record(torch.cuda.current_stream())
+                e = tm.rec("xengine")
+            afc.correlate(z16, n_spectra=S, out=vis16, weights=wts)
+            if tm:
+                e.record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        f16_xe = t16.ms("xengine")
+        f16_tf = 8.0 * cmac / (f16_xe * 1e-3) / 1e12
+        out["fp16"] = {"xengine_ms": round(f16_xe, 3), "xengine_tcmacs": round(cmac / (f16_xe * 1e-3) / 1e12, 3),
+                       "xengine_fp16_mfma_frac": round(f16_tf / PEAK_FP16_TFLOPS, 4),
+                       "ppf_ms": round(t16.ms("ppf"), 3),
+                       "ppf_gbs": round((float(B) * L * N * 4 + float(B) * P * S * N * 4) / (t16.ms("ppf") * 1e-3) / 1e9, 1),
+                       "real_time_factor": round(data_s / ((f16_xe + t16.ms("ppf")) * 1e-3), 2)}
+        log(f"fp16 xengine {f16_xe:.3f} ms")
+        parity_vis["f16"] = _sampled_vis(torch, vis16, 0, PARITY_ANTENNAS)
+        parity_x0 = x[0].cpu().numpy()
+        del z16, vis16, x, vis
         torch.cuda.empty_cache()
 
         # ---- host-to-device copy of the int16 input (not part of the step:
@@ -331,8 +363,9 @@ def main():
         bp = W.batch_params(cfgb)
         dts = ["f16" if d == 1 else "i8" for d in bp.dtypes]
         xbat = W.make_voltages(cfgb, device=dev)
+        tune_dir = tempfile.mkdtemp(prefix="afc_tune_")             # tuned afresh every run
         plan = afc.Plan(Na, bp.n_spectra.tolist(), dts, n_spectra=cfgb.n_spectra,
-                        tune_cache=os.path.join(ROOT, "paper_1609_04205_amd", "tune_cache.json"))
+                        tune_cache=os.path.join(tune_dir, "tune_cache.json"))
         ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
         visb = torch.empty(afc.visibility_shape(cfgb.n_subbands, Na), dtype=torch.int32, device=dev)
         wb = torch.empty((cfgb.n_subbands, nbl), dtype=torch.int32, device=dev)
@@ -410,7 +443,9 @@ def main():
         out["imaging"] = run_imaging(torch, afc, W, dev, cfg)
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_spectra)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_spectra, args.cpu_one_thread_spectra)
+        if not args.no_extras:
+            out["chain_error_vs_fp64"] = chain_error(parity_x0, parity_vis)
     print(json.dumps(out), flush=True)
 
 
@@ -513,10 +548,32 @@ def run_imaging(torch, afc, W, dev, cfg, B_img=8, N=2048, reps=3):
     return res
 
 
-def cpu_baseline(S_s):
-    """Oracle chain (float64 PPF -> requant -> exact int correlator) on a bounded sample:
-    subband 0 of the same workload, all 1152 receivers, the first S_s spectra, all 64
-    channels; TCMAC/s = useful CMACs of the sample / oracle wall time."""
+# antennas whose baselines the chain-error comparison samples (subband 0, all channels)
+PARITY_ANTENNAS = [0, 1, 47, 48, 95, 150, 199, 240, 287, 288, 333, 400, 431, 480, 529, 575]
+
+
+def _sampled_vis(torch, vis, sb, ants):
+    """Visibilities of the baselines among `ants` (a >= b) of subband sb, all
+    channels, as complex128 numpy [P][n][2][2]."""
+    bls = [a * (a + 1) // 2 + b for ia, a in enumerate(ants) for b in ants[: ia + 1]]
+    v = vis[sb][:, torch.as_tensor(bls, device=vis.device)].double().cpu().numpy()
+    return v[..., 0] + 1j * v[..., 1]
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_chain_int(x, S_s, threads):
+    """Oracle chain of one subband (float64 PPF -> requant -> exact integer
+    correlator over all 64 channels) on the first S_s spectra; returns the
+    seconds of each stage and the useful CMACs."""
     import numpy as np
 
     import oracle
@@ -524,24 +581,156 @@ def cpu_baseline(S_s):
 
     cfg = W.A12
     N = cfg.n_inputs
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    os.environ["OMP_NUM_THREADS"] = str(threads)
-    x = W.make_voltages(cfg, subbands=[0], n_rows=(S_s + 15) * 64).numpy()[0]
     taps = W.prototype_taps()
     gain = W.requant_gain(cfg, taps)
+    xs = np.ascontiguousarray(x[: (S_s + 15) * 64])
     t0 = time.perf_counter()
-    y = oracle.ppf_subband(x, taps, 64, 16, S_s)                          # [P][S][N]
+    y = oracle.ppf_subband(xs, taps, 64, 16, S_s)                         # [P][S][N]
     t1 = time.perf_counter()
     q = oracle.requant(np.stack([y.real, y.imag], -1).astype(np.float32), gain)
     t2 = time.perf_counter()
     for ch in range(64):
         oracle.xcorr_int(np.ascontiguousarray(q[ch]))
     t3 = time.perf_counter()
-    cmac = 64.0 * (N * (N + 1) // 2) * S_s
-    return {"value": round(cmac / (t3 - t0) / 1e12, 6), "unit": "TCMAC/s", "cores": threads, "kind": "oracle",
-            "sample": f"subband 0 of the same workload, all {N} receivers, first {S_s} of 3051 spectra, 64 channels: "
-                      f"float64 PPF {t1 - t0:.1f} s + requant {t2 - t1:.1f} s + exact-int correlator {t3 - t2:.1f} s"}
+    return {"ppf_s": t1 - t0, "requant_s": t2 - t1, "correlator_s": t3 - t2, "total_s": t3 - t0,
+            "cmac": 64.0 * (N * (N + 1) // 2) * S_s, "threads": threads}
+
+
+def _one_thread_child(S_s, n_ch):
+    """Entry of the child process that times the oracle on one thread (the
+    OpenMP thread count is fixed when the oracle library loads); it never
+    touches the GPU.  The channeliser and requantiser run on the first S_s
+    spectra of all receivers; the correlator on n_ch channels of 3051 int8
+    spectra (the same working set per channel as the full sample; its cost
+    does not depend on the values).  Both are scaled to the full sample."""
+    import numpy as np
+
+    import oracle
+    import workloads as W
+
+    N = W.A12.n_inputs
+    x = W.make_voltages(W.A12, subbands=[0], n_rows=(S_s + 15) * 64).numpy()[0]
+    r = _oracle_chain_int(x, S_s, 1)
+    q = np.random.default_rng(1).integers(-127, 128, size=(3051, N, 2)).astype(np.int8)
+    t0 = time.perf_counter()
+    for _ in range(n_ch):
+        oracle.xcorr_int(q)
+    t1 = time.perf_counter()
+    full = (r["ppf_s"] + r["requant_s"]) * 3051 / S_s + (t1 - t0) * 64 / n_ch
+    print(json.dumps({"full_sample_s": full, "ppf_requant_s": r["ppf_s"] + r["requant_s"], "corr_s": t1 - t0,
+                      "cmac": 64.0 * (N * (N + 1) // 2) * 3051}), flush=True)
+
+
+def cpu_baseline(S_s, S_1):
+    """The oracle timed on the host cores, on bounded samples of the same
+    workload and on two whole small configurations:
+      value         oracle chain (float64 PPF -> requant -> exact-integer
+                    correlator) of subband 0 of the AARTFAAC-12 workload, all
+                    1152 receivers, the first S_s spectra, all 64 channels,
+                    every host thread; TCMAC/s = useful CMACs / wall time
+      one_thread    the same chain on the first S_1 spectra on one thread
+      small_whole   the whole 48-antenna configuration (float64 PPF + float64
+                    correlator, 3.05e8 CMAC)
+      calibration_whole  the loss and gradient of 576 antennas x 64 channels
+                    (XX, YY) at the true gains and at unit gains
+    The input is drawn on the host with the same generator recipe (the
+    device's draws differ); the oracle's cost does not depend on the values."""
+    import numpy as np
+
+    import oracle
+    import workloads as W
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    os.environ["OMP_NUM_THREADS"] = str(threads)
+    x = W.make_voltages(W.A12, subbands=[0], n_rows=(S_s + 15) * 64).numpy()[0]
+    main = _oracle_chain_int(x, S_s, threads)
+    del x
+    full_s = main["total_s"] * (3051 / S_s) * W.A12.n_subbands
+    res = {"value": round(main["cmac"] / main["total_s"] / 1e12, 6), "unit": "TCMAC/s", "cores": threads,
+           "kind": "oracle", "cpu_model": _cpu_model(),
+           "sample": f"subband 0 of the AARTFAAC-12 workload, all {W.A12.n_inputs} receivers, first {S_s} of 3051 "
+                     f"spectra, 64 channels: float64 PPF {main['ppf_s']:.1f} s + requant {main['requant_s']:.1f} s "
+                     f"+ exact-int correlator {main['correlator_s']:.1f} s on {threads} threads",
+           "workload_seconds_extrapolated": round(full_s, 1),
+           "extrapolation": "linear in spectra and subbands to the 16-subband, 3051-spectrum step"}
+    # one thread, in a child process (no GPU there), scaled to the 3051-spectrum sample
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-one-thread", str(S_1), "2"], env=env,
+                       capture_output=True, text=True, timeout=900)
+    if r.returncode == 0 and S_s == 3051:
+        one = json.loads(r.stdout.strip().splitlines()[-1])
+        res["one_thread"] = {"value": round(one["cmac"] / one["full_sample_s"] / 1e12, 7), "unit": "TCMAC/s",
+                             "cores": 1,
+                             "sample": f"the same subband on one thread: channeliser + requant on the first {S_1} "
+                                       f"spectra ({one['ppf_requant_s']:.1f} s), correlator on 2 of 64 channels of "
+                                       f"3051 spectra ({one['corr_s']:.1f} s), scaled to the full subband",
+                             "speedup_of_all_threads": round(one["full_sample_s"] / main["total_s"], 2)}
+    else:
+        res["one_thread"] = {"error": (r.stderr or "sample is not the whole subband")[-300:]}
+    # the whole 48-antenna configuration, float64 chain
+    cfg = W.SMALL
+    xs = W.make_voltages(cfg).numpy()[0]
+    taps = W.prototype_taps()
+    t0 = time.perf_counter()
+    y = oracle.ppf_subband(xs, taps, 64, 16, cfg.n_spectra)
+    t1 = time.perf_counter()
+    for ch in range(64):
+        oracle.xcorr(y[ch])
+    t2 = time.perf_counter()
+    n = cfg.n_inputs
+    cm1 = 64.0 * n * (n + 1) // 2 * cfg.n_spectra
+    res["small_whole"] = {"workload": cfg.name, "seconds": round(t2 - t0, 2), "ppf_s": round(t1 - t0, 2),
+                          "correlator_s": round(t2 - t1, 2), "tcmacs": round(cm1 / (t2 - t0) / 1e12, 6),
+                          "cmac": cm1}
+    # the whole calibration configuration: loss and gradient at two gain sets
+    Vc, Mc, gc = W.make_calibration(Na=576, P=64, seed=5)
+    g1 = np.zeros_like(gc)
+    g1[..., 0] = 1.0
+    t0 = time.perf_counter()
+    oracle.cal_loss_grad(Vc, Mc, gc)
+    oracle.cal_loss_grad(Vc, Mc, g1)
+    t1 = time.perf_counter()
+    res["calibration_whole"] = {"workload": "576 antennas x 64 channels, XX and YY, true and unit gains",
+                                "seconds": round(t1 - t0, 3), "seconds_per_evaluation": round((t1 - t0) / 2, 3)}
+    return res
+
+
+def chain_error(x0, vis_by_dtype, ants=PARITY_ANTENNAS):
+    """Error of the GPU fp32 and fp16 chains of the timed run against the
+    oracle's float64 chain on the same int16 samples (subband 0, the
+    baselines among `ants`, all 64 channels): |V - V_ref| / sqrt(V_ii V_jj),
+    max and RMS (the fp32 bar is 1e-5, the fp16 bar 2e-3)."""
+    import numpy as np
+
+    import oracle
+    import workloads as W
+
+    S = W.A12.n_spectra
+    inputs = [2 * a + p for a in ants for p in range(2)]
+    t0 = time.perf_counter()
+    y = oracle.ppf_subband(x0, W.prototype_taps(), 64, 16, S, inputs=inputs)      # [P][S][R]
+    pos = {i: k for k, i in enumerate(inputs)}
+    pairs = np.array([(pos[2 * a + p], pos[2 * b + q]) for ia, a in enumerate(ants) for b in ants[: ia + 1]
+                      for p in range(2) for q in range(2)])
+    res = {"sample": f"subband 0 of the timed AARTFAAC-12 input, {len(ants)} antennas "
+                     f"({len(pairs) // 4} baselines x 4 products), 64 channels, {S} spectra"}
+    errs = {k: [] for k in vis_by_dtype}
+    for ch in range(64):
+        ref = oracle.xcorr_pairs(y[ch], pairs)
+        pw = oracle.xcorr_pairs(y[ch], np.array([[k, k] for k in range(len(inputs))])).real
+        den = np.sqrt(pw[pairs[:, 0]] * pw[pairs[:, 1]])
+        for k, v in vis_by_dtype.items():
+            errs[k].append(np.abs(v[ch].reshape(-1) - ref) / den)
+    for k, e in errs.items():
+        e = np.concatenate(e)
+        res[k] = {"max": float(f"{e.max():.3e}"), "rms": float(f"{np.sqrt(np.mean(e * e)):.3e}"),
+                  "bar": 1e-5 if k == "f32" else 2e-3}
+    res["oracle_seconds"] = round(time.perf_counter() - t0, 2)
+    return res
 
 
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) == 4 and sys.argv[1] == "--oracle-one-thread":
+        _one_thread_child(int(sys.argv[2]), int(sys.argv[3]))
+    else:
+        main()
