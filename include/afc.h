@@ -441,6 +441,31 @@ AFC_API int afc_plan_info(const afc_plan* p, int32_t* tile_rows, int32_t* tile_c
                           int32_t* n_workgroups, int32_t* n_work_items);
 AFC_API void afc_plan_destroy(afc_plan* p);
 
+/* ---------------------------------------------------------------------------
+ * Checked (debug) mode.  With it on, every entry point first counts the
+ * non-finite values (NaN, +-Inf) of its floating-point inputs on the device
+ * and returns AFC_ERR_INVALID, naming the input and the count, if there are
+ * any: taps, bandpass and delays of the channelisers, z of afc_correlate
+ * (fp32 / fp16), vis of afc_normalise_visibilities (float), V, M and g of the
+ * calibration calls, V of afc_sigma_clip, vis, positions and freq_hz of the
+ * gridder, the grid of the imager.  A checked call reads the count back and
+ * so waits for its stream: keep the mode off under graph capture and on the
+ * hot path (it is off by default; the switch is process-wide).
+ *
+ * afc_count_nonfinite  the count behind it, for any device buffer of n
+ *                      values of the given type; *count (host) is written
+ *                      after the stream has passed the count.
+ * ------------------------------------------------------------------------- */
+typedef enum {
+    AFC_VALUES_F32 = 0,
+    AFC_VALUES_F16 = 1,
+    AFC_VALUES_F64 = 3
+} afc_value_type;
+AFC_API void afc_set_checked_mode(int on);
+AFC_API int afc_checked_mode(void);
+AFC_API int afc_count_nonfinite(const void* values, size_t n, afc_value_type type, uint64_t* count,
+                                hipStream_t stream);
+
 /* Message for the last non-OK return on this thread ("" if none). */
 AFC_API const char* afc_last_error(void);
 

@@ -75,6 +75,10 @@ _lib.afc_plan_launch.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.afc_plan_info.argtypes = [_vp, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)]
 _lib.afc_plan_destroy.argtypes = [_vp]
 _lib.afc_plan_destroy.restype = None
+_lib.afc_set_checked_mode.argtypes = [C.c_int]
+_lib.afc_set_checked_mode.restype = None
+_lib.afc_checked_mode.restype = C.c_int
+_lib.afc_count_nonfinite.argtypes = [_vp, _sz, C.c_int, C.POINTER(C.c_uint64), _vp]
 
 EXPORTS = ["afc_channelised_bytes", "afc_visibility_bytes", "afc_channelise",
            "afc_channelise_fine_workspace_bytes", "afc_channelise_fine", "afc_correlate",
@@ -84,7 +88,9 @@ EXPORTS = ["afc_channelised_bytes", "afc_visibility_bytes", "afc_channelise",
            "afc_imaging_workspace_bytes", "afc_grid_visibilities", "afc_image_from_grid",
            "afc_calibrate_workspace_bytes", "afc_calibrate_grad", "afc_calibrate_grad_noalloc", "afc_plan_create",
            "afc_plan_workspace_bytes", "afc_plan_launch", "afc_plan_info", "afc_plan_destroy",
-           "afc_last_error"]
+           "afc_set_checked_mode", "afc_checked_mode", "afc_count_nonfinite", "afc_last_error"]
+
+AFC_VALUES_F32, AFC_VALUES_F16, AFC_VALUES_F64 = 0, 1, 3
 
 
 class AfcError(RuntimeError):
@@ -94,6 +100,30 @@ class AfcError(RuntimeError):
 def _check(rc: int, what: str):
     if rc != 0:
         raise AfcError(f"{what} failed ({rc}): {_lib.afc_last_error().decode()}")
+
+
+def set_checked_mode(on: bool) -> None:
+    """Checked (debug) mode, process-wide: every entry point refuses
+    non-finite floating-point inputs (and waits for its stream to count
+    them).  Off by default."""
+    _lib.afc_set_checked_mode(1 if on else 0)
+
+
+def checked_mode() -> bool:
+    return bool(_lib.afc_checked_mode())
+
+
+def count_nonfinite(t) -> int:
+    """Number of NaN / Inf values of a float32, float16 or float64 GPU tensor."""
+    torch = _torch()
+    kinds = {torch.float32: AFC_VALUES_F32, torch.float16: AFC_VALUES_F16, torch.float64: AFC_VALUES_F64}
+    if t.dtype not in kinds:
+        raise AfcError(f"count_nonfinite: float32, float16 or float64 tensor expected, got {t.dtype}")
+    _require(t, t.dtype, "values")
+    out = C.c_uint64(0)
+    _check(_lib.afc_count_nonfinite(_ptr(t), t.numel(), kinds[t.dtype], C.byref(out), _stream(t)),
+           "afc_count_nonfinite")
+    return int(out.value)
 
 
 def dims(n_antennas: int, n_subbands: int, n_spectra: int, n_channels: int = N_CHANNELS,

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <initializer_list>
 #include <map>
 #include <queue>
 #include <sstream>
@@ -35,6 +36,26 @@ int fail(int code, const char* fmt, ...) {
 
 int hip_fail(hipError_t e, const char* what) {
     return fail(AFC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Checked mode: refuse non-finite floating-point inputs (counted on the
+// device; the call then waits for its stream).  No-op when the mode is off.
+struct FloatInput {
+    const void* p;
+    size_t n;          // values
+    int kind;          // afc_value_type
+    const char* name;
+};
+int check_inputs(std::initializer_list<FloatInput> ins, hipStream_t stream) {
+    if (!checked_mode()) return AFC_OK;
+    for (const FloatInput& in : ins) {
+        if (!in.p || in.n == 0) continue;
+        unsigned long long c = 0;
+        const hipError_t e = count_nonfinite(in.p, in.n, in.kind, &c, stream);
+        if (e != hipSuccess) return hip_fail(e, "checked mode");
+        if (c) return fail(AFC_ERR_INVALID, "checked mode: %llu non-finite values in %s", c, in.name);
+    }
+    return AFC_OK;
 }
 
 int check_dims(const afc_dims* d) {
@@ -70,6 +91,26 @@ extern "C" {
 
 AFC_API const char* afc_last_error(void) { return g_err.c_str(); }
 
+AFC_API void afc_set_checked_mode(int on) { set_checked_mode(on != 0); }
+
+AFC_API int afc_checked_mode(void) { return checked_mode() ? 1 : 0; }
+
+AFC_API int afc_count_nonfinite(const void* values, size_t n, afc_value_type type, uint64_t* count,
+                                hipStream_t stream) {
+    g_err.clear();
+    if (!count) return fail(AFC_ERR_INVALID, "count is NULL");
+    *count = 0;
+    if (n == 0) return AFC_OK;
+    if (!values) return fail(AFC_ERR_INVALID, "values is NULL");
+    if (type != AFC_VALUES_F32 && type != AFC_VALUES_F16 && type != AFC_VALUES_F64)
+        return fail(AFC_ERR_INVALID, "unknown value type %d", (int)type);
+    unsigned long long c = 0;
+    const hipError_t e = count_nonfinite(values, n, type, &c, stream);
+    if (e != hipSuccess) return hip_fail(e, "non-finite count");
+    *count = (uint64_t)c;
+    return AFC_OK;
+}
+
 AFC_API size_t afc_channelised_bytes(const afc_dims* d, afc_dtype dt) {
     if (check_dims(d) != AFC_OK || !dtype_ok(dt)) return 0;
     return (size_t)d->n_subbands * z_sb_samples(2LL * d->n_antennas, d->n_spectra) * sample_bytes(dt);
@@ -92,6 +133,8 @@ AFC_API int afc_channelise(const afc_dims* d, const int16_t* x, const float* tap
     const int64_t N = 2LL * d->n_antennas;
     const int64_t z_sb = z_sb_samples(N, d->n_spectra);
     if (z_sb * sample_bytes(out_dtype) >= (1LL << 40)) return fail(AFC_ERR_UNSUPPORTED, "output too large");
+    rc = check_inputs({{taps, (size_t)kT * kP, AFC_VALUES_F32, "taps"}}, stream);
+    if (rc != AFC_OK) return rc;
     PpfLaunch a{};
     a.x = x;
     a.taps = taps;
@@ -144,6 +187,11 @@ AFC_API int afc_channelise_fine(const afc_dims* d, const int16_t* x, const float
     const int64_t N = 2LL * d->n_antennas;
     const int64_t z_sb = z_sb_samples(N, d->n_spectra);
     if (z_sb * sample_bytes(out_dtype) >= (1LL << 40)) return fail(AFC_ERR_UNSUPPORTED, "output too large");
+    rc = check_inputs({{taps, (size_t)kT * kPFine, AFC_VALUES_F32, "taps"},
+                       {bandpass, (size_t)kPFine, AFC_VALUES_F32, "bandpass"},
+                       {delays, (size_t)N, AFC_VALUES_F64, "delays"}},
+                      stream);
+    if (rc != AFC_OK) return rc;
     FineLaunch l{};
     l.x = x;
     l.taps = taps;
@@ -223,6 +271,10 @@ AFC_API int afc_normalise_visibilities(const afc_dims* d, afc_dtype vis_dtype, c
     if (rc != AFC_OK) return rc;
     if (!vis || !weights || !out) return fail(AFC_ERR_INVALID, "NULL pointer (vis, weights or out)");
     if (!dtype_ok(vis_dtype)) return fail(AFC_ERR_INVALID, "unknown vis_dtype %d", (int)vis_dtype);
+    if (vis_dtype != AFC_I8) {
+        rc = check_inputs({{vis, (size_t)d->n_subbands * kP * nbl_of(d->n_antennas) * 8, AFC_VALUES_F32, "vis"}}, stream);
+        if (rc != AFC_OK) return rc;
+    }
     hipError_t e = launch_normalise(vis, vis_dtype == AFC_I8, weights, out, d->n_subbands, d->n_antennas, stream);
     if (e != hipSuccess) return hip_fail(e, "normalise launch");
     return AFC_OK;
@@ -251,6 +303,11 @@ AFC_API int afc_correlate(const afc_dims* d, afc_dtype in_dtype, const void* z, 
                 return fail(AFC_ERR_UNSUPPORTED, "int8 sums over %d spectra may overflow int32", S[b]);
     }
     const int64_t N = 2LL * d->n_antennas;
+    if (in_dtype != AFC_I8) {
+        const size_t nz = (size_t)d->n_subbands * z_sb_samples(N, d->n_spectra) * 2;
+        rc = check_inputs({{z, nz, in_dtype == AFC_F32 ? AFC_VALUES_F32 : AFC_VALUES_F16, "z"}}, stream);
+        if (rc != AFC_OK) return rc;
+    }
     XLaunch a{};
     a.z = z;
     a.vis = vis;
@@ -274,6 +331,15 @@ AFC_API size_t afc_calibrate_workspace_bytes(int32_t n_antennas, int32_t n_chann
     return cal_workspace_bytes(n_antennas, n_channels);
 }
 
+namespace {
+int check_cal_inputs(int32_t Na, int32_t P, const void* V, const void* M, const void* g, hipStream_t stream) {
+    const size_t nv = (size_t)P * nbl_of(Na) * 8;
+    return check_inputs({{V, nv, AFC_VALUES_F32, "V"}, {M, nv, AFC_VALUES_F32, "M"},
+                         {g, (size_t)P * Na * 4, AFC_VALUES_F32, "g"}},
+                        stream);
+}
+}  // namespace
+
 AFC_API int afc_calibrate_grad(int32_t n_antennas, int32_t n_channels, const void* V, const void* M, const void* g,
                                double* loss, void* grad, void* workspace, hipStream_t stream) {
     g_err.clear();
@@ -282,6 +348,8 @@ AFC_API int afc_calibrate_grad(int32_t n_antennas, int32_t n_channels, const voi
     if (!V || !M || !g || !loss) return fail(AFC_ERR_INVALID, "NULL pointer (V, M, g or loss)");
     if (!workspace) return fail(AFC_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)",
                                 cal_workspace_bytes(n_antennas, n_channels));
+    const int rc = check_cal_inputs(n_antennas, n_channels, V, M, g, stream);
+    if (rc != AFC_OK) return rc;
     hipError_t e = launch_calibrate(n_antennas, n_channels, reinterpret_cast<const float2*>(V),
                                     reinterpret_cast<const float2*>(M), reinterpret_cast<const float2*>(g), loss,
                                     reinterpret_cast<float2*>(grad), workspace, stream);
@@ -299,6 +367,8 @@ AFC_API int afc_calibrate_grad_noalloc(int32_t n_antennas, int32_t n_channels, c
     if (need > kCalScratchBytes)
         return fail(AFC_ERR_UNSUPPORTED, "%d antennas x %d channels need %zu bytes of scratch, more than the %zu built in",
                     n_antennas, n_channels, need, kCalScratchBytes);
+    const int rc = check_cal_inputs(n_antennas, n_channels, V, M, g, stream);
+    if (rc != AFC_OK) return rc;
     void* scratch = nullptr;
     hipError_t e = cal_scratch_address(&scratch);
     if (e != hipSuccess) return hip_fail(e, "scratch address");
@@ -322,6 +392,8 @@ AFC_API int afc_calibrate_solve(int32_t n_antennas, int32_t n_channels, const vo
     if (!V || !M || !g) return fail(AFC_ERR_INVALID, "NULL pointer (V, M or g)");
     if (!workspace) return fail(AFC_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)",
                                 cal_solve_workspace_bytes(n_antennas, n_channels));
+    const int rc = check_cal_inputs(n_antennas, n_channels, V, M, g, stream);
+    if (rc != AFC_OK) return rc;
     hipError_t e = launch_calibrate_solve(n_antennas, n_channels, reinterpret_cast<const float2*>(V),
                                           reinterpret_cast<const float2*>(M), reinterpret_cast<float2*>(g), n_iter,
                                           loss, workspace, stream);
@@ -343,6 +415,8 @@ AFC_API int afc_sigma_clip(int32_t n_antennas, int32_t n_channels, const void* V
     if (!(std::isfinite(threshold) && threshold > 0.0f)) return fail(AFC_ERR_INVALID, "threshold must be finite and > 0");
     if (!workspace) return fail(AFC_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)",
                                 sigma_clip_workspace_bytes(n_antennas, n_channels));
+    const int rc = check_inputs({{V, (size_t)n_channels * nbl_of(n_antennas) * 8, AFC_VALUES_F32, "V"}}, stream);
+    if (rc != AFC_OK) return rc;
     hipError_t e = launch_sigma_clip(n_antennas, n_channels, reinterpret_cast<const float2*>(V), threshold, vis_flags,
                                      workspace, stream);
     if (e != hipSuccess) return hip_fail(e, "sigma-clip launch");
@@ -389,6 +463,11 @@ AFC_API int afc_grid_visibilities(int32_t n_antennas, int32_t n_subbands, const 
     if (!(std::isfinite(cell_wavelengths) && cell_wavelengths > 0.0))
         return fail(AFC_ERR_INVALID, "cell_wavelengths must be finite and > 0");
     if (!workspace) return fail(AFC_ERR_WORKSPACE, "workspace is NULL");
+    rc = check_inputs({{vis, (size_t)n_subbands * kP * nbl_of(n_antennas) * 8, AFC_VALUES_F32, "vis"},
+                       {positions, (size_t)n_antennas * 2, AFC_VALUES_F64, "positions"},
+                       {freq_hz, (size_t)n_subbands * kP, AFC_VALUES_F64, "freq_hz"}},
+                      stream);
+    if (rc != AFC_OK) return rc;
     hipError_t e = launch_grid(reinterpret_cast<const float2*>(vis), weights, positions, freq_hz, n_antennas,
                                n_subbands, grid_size, cell_wavelengths, reinterpret_cast<float2*>(grid), norm,
                                workspace, stream);
@@ -403,6 +482,8 @@ AFC_API int afc_image_from_grid(int32_t grid_size, const void* grid, const doubl
     if (rc != AFC_OK) return rc;
     if (!grid || !norm || !image) return fail(AFC_ERR_INVALID, "NULL pointer (grid, norm or image)");
     if (!workspace) return fail(AFC_ERR_WORKSPACE, "workspace is NULL");
+    rc = check_inputs({{grid, (size_t)grid_size * grid_size * 2, AFC_VALUES_F32, "grid"}}, stream);
+    if (rc != AFC_OK) return rc;
     hipError_t e = launch_image(reinterpret_cast<const float2*>(grid), norm, image, grid_size, workspace, stream);
     if (e != hipSuccess) return hip_fail(e, "imaging launch");
     return AFC_OK;
@@ -422,6 +503,9 @@ struct afc_plan {
     int64_t L = 0;
     // device tables (d_sbs and the work lists never change after creation)
     XSubband* d_sbs = nullptr;
+    // antenna compaction tables, rewritten from the flags by every launch
+    // that has flags: inv, amap, flagged [B][Na] and counts [B][2]
+    int32_t* d_compact = nullptr;
     struct Mode {
         bool used = false;
         int tile = 128;
@@ -603,7 +687,7 @@ int tune_mode0(afc_plan* p, int& tile_out, int& wg_per_cu_out) {
         for (int rep = 0; rep < 3; ++rep) {
             hipEventRecord(e0, nullptr);
             launch_xengine_list(z, vis, nullptr, nullptr, p->d_sbs, md.d_work, md.ranges, p->N, p->Na, 0, md.tile,
-                                nullptr);
+                                nullptr, nullptr, nullptr);
             hipEventRecord(e1, nullptr);
             hipEventSynchronize(e1);
             float ms = 0;
@@ -669,13 +753,24 @@ int capture_plan(afc_plan* p, const int16_t* x, const float* taps, const std::ve
         free_capture(c);
         return hip_fail(e, "graph capture begin");
     }
-    hipError_t le = launch_ppf_batched(x, taps, z_workspace, c->d_items, B, p->N, p->d.n_spectra, p->cap_stream);
+    // with flags: compact the flagged antennas out of the channeliser's
+    // output and the correlator's tiles, then zero their baselines
+    const int64_t NaB = (int64_t)p->Na * B;
+    int32_t* inv = flags ? p->d_compact : nullptr;
+    int32_t* amap = flags ? p->d_compact + NaB : nullptr;
+    int32_t* flagged = flags ? p->d_compact + 2 * NaB : nullptr;
+    int32_t* counts = flags ? p->d_compact + 3 * NaB : nullptr;
+    hipError_t le = hipSuccess;
+    if (flags) le = launch_plan_compact(flags, B, p->Na, inv, amap, flagged, counts, p->cap_stream);
+    if (le == hipSuccess)
+        le = launch_ppf_batched(x, taps, z_workspace, c->d_items, B, p->N, p->d.n_spectra, inv, p->cap_stream);
     for (int m = 0; m < 2 && le == hipSuccess; ++m) {
         const afc_plan::Mode& md = p->mode[m];
         if (!md.used) continue;
         le = launch_xengine_list(z_workspace, vis, weights, flags, p->d_sbs, md.d_work, md.ranges, p->N, p->Na, m,
-                                 md.tile, p->cap_stream);
+                                 md.tile, counts, amap, p->cap_stream);
     }
+    if (flags && le == hipSuccess) le = launch_plan_zero_flagged(flagged, counts, B, p->Na, vis, weights, p->cap_stream);
     e = hipStreamEndCapture(p->cap_stream, &c->graph);
     if (le != hipSuccess || e != hipSuccess) {
         free_capture(c);
@@ -745,6 +840,7 @@ AFC_API int afc_plan_create(const afc_dims* d, const afc_dtype* dtype_per_sb, co
                               p->dt[b], 1.0f};
     }
     hipError_t e = hipMalloc(&p->d_sbs, B * sizeof(XSubband));
+    if (e == hipSuccess) e = hipMalloc(&p->d_compact, ((size_t)3 * B * p->Na + 2 * B) * sizeof(int32_t));
     if (e == hipSuccess) e = hipMemcpy(p->d_sbs, sbs.data(), B * sizeof(XSubband), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -823,6 +919,8 @@ AFC_API int afc_plan_launch(afc_plan* p, const int16_t* x, const float* taps, co
             gains[b] = gain_per_sb[b];
         }
     }
+    const int rc0 = check_inputs({{taps, (size_t)kT * kP, AFC_VALUES_F32, "taps"}}, stream);
+    if (rc0 != AFC_OK) return rc0;
     const std::vector<const void*> key = {x, taps, z_workspace, flags, vis, weights};
     const bool same = p->cur && key == p->cur->key_ptrs && gains == p->cur->key_gains;
     reap_captures(p, false);
@@ -844,6 +942,7 @@ AFC_API void afc_plan_destroy(afc_plan* p) {
     for (auto& md : p->mode)
         if (md.d_work) hipFree(md.d_work);
     if (p->d_sbs) hipFree(p->d_sbs);
+    if (p->d_compact) hipFree(p->d_compact);
     if (p->cap_stream) hipStreamDestroy(p->cap_stream);
     delete p;
 }

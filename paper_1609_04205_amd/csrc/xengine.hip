@@ -86,6 +86,11 @@ template <int DT, int TILE>
 constexpr int lds_bytes() {
     return (uses_dma<DT>() ? kDmaBuffers : 2) * 2 * stage_blocks<DT, TILE>() * TILE * XT<DT>::RB;
 }
+// the one-workgroup-per-CU kernel: 128-row A panel and 256-row B panel per stage
+template <int DT>
+constexpr int wide_lds_bytes() {
+    return kDmaBuffers * 3 * stage_blocks<DT, 128>() * 128 * XT<DT>::RB;
+}
 
 // Workgroup barrier for the DMA pipeline: no memory fence (which would wait
 // for every outstanding global-to-LDS load); a compiler-level memory clobber
@@ -192,61 +197,81 @@ __device__ __forceinline__ void tile_rc(int t, int& ti, int& tj) {
 // Work of one wave in an int8 / fp16 tile: NP blocks of 32 x 32 outputs,
 // block p pairing row block am[IA[p]] of panel A with column block
 // bn[IB[p]] of panel B (am, bn hold NA and NB block indices).
+struct JobRows4x2 {    // off-diagonal 128 x 256 tile: every row block x this wave's two column blocks
+    static constexpr int NA = 4, NB = 2, NP = 8;
+    static constexpr int IA[8] = {0, 1, 2, 3, 0, 1, 2, 3}, IB[8] = {0, 0, 0, 0, 1, 1, 1, 1};
+};
 struct JobRows4 {      // off-diagonal 128-tile: every row block x this wave's column block
     static constexpr int NA = 4, NB = 1, NP = 4;
-    static constexpr int IA[4] = {0, 1, 2, 3}, IB[4] = {0, 0, 0, 0};
+    static constexpr int IA[8] = {0, 1, 2, 3}, IB[8] = {0, 0, 0, 0};
 };
 // diagonal 128-tile: its ten lower-triangle blocks (m >= n) split 3/3/2/2
 struct JobDiag0 {      // (0,0) (1,0) (2,0)
     static constexpr int NA = 3, NB = 1, NP = 3;
-    static constexpr int IA[4] = {0, 1, 2, 0}, IB[4] = {0, 0, 0, 0};
+    static constexpr int IA[8] = {0, 1, 2, 0}, IB[8] = {0, 0, 0, 0};
     static constexpr int AM[4] = {0, 1, 2, 0}, BN[2] = {0, 0};
 };
 struct JobDiag1 {      // (3,0) (1,1) (2,1)
     static constexpr int NA = 3, NB = 2, NP = 3;
-    static constexpr int IA[4] = {0, 1, 2, 0}, IB[4] = {0, 1, 1, 0};
+    static constexpr int IA[8] = {0, 1, 2, 0}, IB[8] = {0, 1, 1, 0};
     static constexpr int AM[4] = {3, 1, 2, 0}, BN[2] = {0, 1};
 };
 struct JobDiag2 {      // (3,1) (2,2)
     static constexpr int NA = 2, NB = 2, NP = 2;
-    static constexpr int IA[4] = {0, 1, 0, 0}, IB[4] = {0, 1, 0, 0};
+    static constexpr int IA[8] = {0, 1, 0, 0}, IB[8] = {0, 1, 0, 0};
     static constexpr int AM[4] = {3, 2, 0, 0}, BN[2] = {1, 2};
 };
 struct JobDiag3 {      // (3,2) (3,3)
     static constexpr int NA = 1, NB = 2, NP = 2;
-    static constexpr int IA[4] = {0, 0, 0, 0}, IB[4] = {0, 1, 0, 0};
+    static constexpr int IA[8] = {0, 0, 0, 0}, IB[8] = {0, 1, 0, 0};
     static constexpr int AM[4] = {3, 0, 0, 0}, BN[2] = {2, 3};
 };
 struct JobOne {        // 64-tile: one block per wave
     static constexpr int NA = 1, NB = 1, NP = 1;
-    static constexpr int IA[4] = {0, 0, 0, 0}, IB[4] = {0, 0, 0, 0};
+    static constexpr int IA[8] = {0, 0, 0, 0}, IB[8] = {0, 0, 0, 0};
 };
 struct JobIdle {       // 64-tile, the wave above the diagonal
     static constexpr int NA = 1, NB = 1, NP = 0;
-    static constexpr int IA[4] = {0, 0, 0, 0}, IB[4] = {0, 0, 0, 0};
+    static constexpr int IA[8] = {0, 0, 0, 0}, IB[8] = {0, 0, 0, 0};
 };
 
 // One int8 / fp16 tile of one (subband, channel) for one wave's job.  All
 // waves of the workgroup stage the panels together; `z` points at channel ch
 // of subband sb.
-template <int DT, int TILE, class J>
+//
+// The row panel A is TILE receivers tall (rows ti*TILE ..), the column panel B
+// TB receivers (columns tj*TILE ..; TB = TILE for square tiles, 2*TILE for
+// the 128 x 256 tiles of the one-workgroup-per-CU kernel).  A stage buffer
+// holds A then B; a diagonal tile (ti == tj, TB == TILE) stages A only and
+// reads both operands from it.
+//
+// N receivers hold data (rows N and above read row N - 1 and are never
+// stored); Nz is the receiver stride of z (N, or more when the rows of
+// flagged antennas have been compacted away: then amap maps a compact
+// antenna index to the antenna's index in the visibility layout, and fl_sb
+// is not needed).
+template <int DT, int TILE, class J, int TB = TILE>
 __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __restrict__ vis_ch,
                                          int32_t* __restrict__ w_sb, const uint8_t* __restrict__ fl_sb,
                                          int N, int Na, int S, int ti, int tj, bool write_weights,
-                                         char* lds_raw, const int (&am)[4], const int (&bn)[2]) {
+                                         char* lds_raw, const int (&am)[4], const int (&bn)[2], int Nz = -1,
+                                         const int32_t* __restrict__ amap = nullptr) {
     using Tr = XT<DT>;
     using acc_t = typename Tr::acc_t;
     using V = std::conditional_t<DT == AFC_I8, v4i, v8h>;
     constexpr int RB = Tr::RB, PLANES = Tr::PLANES, kStg = stage_blocks<DT, TILE>();
-    constexpr int PANEL = kStg * TILE * RB;                  // bytes of one panel in one stage
-    constexpr int CHUNKS = kStg * TILE * PLANES;             // 16-byte chunks per panel per stage
-    constexpr int CPT = CHUNKS / kThreads;
-    static_assert(CHUNKS % kThreads == 0, "a stage must split evenly over the threads");
+    constexpr int PANEL = kStg * TILE * RB;                  // bytes of panel A in one stage
+    constexpr int PANEL_B = kStg * TB * RB;                  // bytes of panel B in one stage
+    constexpr int CPT = kStg * TILE * PLANES / kThreads;     // 16-byte chunks of A per thread per stage
+    constexpr int CPT_B = kStg * TB * PLANES / kThreads;     // of B
+    static_assert((kStg * TILE * PLANES) % kThreads == 0, "a stage must split evenly over the threads");
+    static_assert(TB == TILE || TB == 2 * TILE, "column panel of one or two tile widths");
     // k-steps per stage (int8: 16 spectra, fp16: 8 spectra each)
     constexpr int NKK = DT == AFC_I8 ? kStg / 2 : kStg;
     static_assert(NKK % 2 == 0, "k-steps per stage must be even");
     constexpr int NA = J::NA, NBO = J::NB, NP = J::NP;
     constexpr int NB = kDmaBuffers;
+    constexpr int BUF = PANEL + PANEL_B;                     // bytes of one stage buffer
 
     const int tid = threadIdx.x, lane = tid & 63, lr = lane & 31, lh = lane >> 5;
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -263,18 +288,21 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
         accI[p] = acc_t{};
     }
 
-    auto rd = [&](const char* panel, int bl, int row, int q) -> uint4 {
-        return *reinterpret_cast<const uint4*>(panel + bl * TILE * RB + row * RB + ((q ^ swz<RB, PLANES>(row)) * 16));
+    // a panel of `rows` receivers holds block bl at bl * rows * RB
+    auto rd = [&](const char* panel, int rows, int bl, int row, int q) -> uint4 {
+        return *reinterpret_cast<const uint4*>(panel + bl * rows * RB + row * RB + ((q ^ swz<RB, PLANES>(row)) * 16));
     };
     // this wave's operands of k-step kk (unconditional, so that the LDS
-    // wait counts stay exact across branches)
+    // wait counts stay exact across branches); a diagonal tile's B operands
+    // come from panel A
+    const int rows_b = diag ? TILE : TB;
     auto load_ops = [&](const char* PA, const char* PB, int kk, uint4 (&oa)[NA], uint4 (&ob)[NBO]) {
         const int bl = DT == AFC_I8 ? 2 * kk + lh : kk;
         const int q = DT == AFC_I8 ? 0 : lh;
 #pragma unroll
-        for (int i = 0; i < NA; ++i) oa[i] = rd(PA, bl, am[i] * 32 + lr, q);
+        for (int i = 0; i < NA; ++i) oa[i] = rd(PA, TILE, bl, am[i] * 32 + lr, q);
 #pragma unroll
-        for (int i = 0; i < NBO; ++i) ob[i] = rd(PB, bl, bn[i] * 32 + lr, q);
+        for (int i = 0; i < NBO; ++i) ob[i] = rd(PB, rows_b, bl, bn[i] * 32 + lr, q);
     };
     auto cvt = [](uint4 u) -> V {
         if constexpr (DT == AFC_I8) return v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
@@ -294,29 +322,39 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
     // MFMAs of one k-step.  `mid` runs after the first block's two MFMAs
     // have been issued (the scheduler may not move work across it): loads
     // of the next operands issued there overlap the remaining MFMAs.
-    auto mma = [&](const uint4 (&oa)[NA], const uint4 (&ob)[NBO], auto&& mid) {
-        V bv[NBO], bj[NBO];
-#pragma unroll
-        for (int i = 0; i < NBO; ++i) {
-            bv[i] = cvt(ob[i]);
-            bj[i] = jsw(ob[i]);
-        }
+    // MFMAs of one k-step from A operands oa and the prepared B operands
+    // (bv as loaded, bj J-swapped).  `mid1` runs after the first block's two
+    // MFMAs have been issued (it issues the next k-step's LDS reads), `mid2`
+    // after about half of the blocks (it masks and J-swaps the next k-step's
+    // B operands, whose reads have had those MFMAs to land), so that the
+    // VALU work of the next k-step overlaps this one's MFMAs instead of
+    // standing between two k-steps.  The scheduler may not move work across
+    // the fences.
+    constexpr int SPLIT = NP >= 4 ? NP / 2 + 1 : (NP > 1 ? NP - 1 : 1);
+    auto mma = [&](const uint4 (&oa)[NA], const V (&bv)[NBO], const V (&bj)[NBO], auto&& mid1, auto&& mid2) {
         if constexpr (NP > 0) {
             const V a0 = cvt(oa[J::IA[0]]);
             op(accR[0], a0, bv[J::IB[0]]);
             op(accI[0], a0, bj[J::IB[0]]);
         }
         __builtin_amdgcn_sched_barrier(0);
-        mid();
+        mid1();
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int p = 1; p < NP; ++p) {
+        for (int p = 1; p < SPLIT && p < NP; ++p) {
             const V a = cvt(oa[J::IA[p]]);
             op(accR[p], a, bv[J::IB[p]]);
             op(accI[p], a, bj[J::IB[p]]);
         }
-        // keep the next k-step's J-swaps (which wait for its operand loads)
-        // behind these MFMAs
+        __builtin_amdgcn_sched_barrier(0);
+        mid2();
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int p = SPLIT; p < NP; ++p) {
+            const V a = cvt(oa[J::IA[p]]);
+            op(accR[p], a, bv[J::IB[p]]);
+            op(accI[p], a, bj[J::IB[p]]);
+        }
         __builtin_amdgcn_sched_barrier(0);
     };
     // zero the spectra >= S of this lane's operands of k-step kk of stage st
@@ -349,38 +387,40 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
     // Offsets within the channel: voffset = this thread's chunk in stage 0,
     // soffset = the stage (a channel of samples is far below 2 GiB: the entry
     // points bound one subband of input to 2^31 values).
-    const int z_bytes = nb * N * RB;
-    int src_off[2][CPT];
+    if (Nz < 0) Nz = N;
+    const int z_bytes = nb * Nz * RB;
+    // source offset of chunk c of a panel of `rows` receivers starting at r0
+    auto chunk_src = [&](int c, int rows, int r0) {
+        const int chunk = tid + c * kThreads;
+        const int bl = chunk / (rows * PLANES);
+        const int rem = chunk % (rows * PLANES);
+        const int row = rem / PLANES, sl = rem % PLANES;
+        const int q = sl ^ swz<RB, PLANES>(row);
+        return (bl * Nz + min(r0 + row, N - 1)) * RB + q * 16;
+    };
+    int src_a[CPT], src_b[CPT_B];
 #pragma unroll
-    for (int pn = 0; pn < 2; ++pn)
+    for (int c = 0; c < CPT; ++c) src_a[c] = chunk_src(c, TILE, i0);
 #pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-            const int chunk = tid + c * kThreads;
-            const int bl = chunk / (TILE * PLANES);
-            const int rem = chunk % (TILE * PLANES);
-            const int row = rem / PLANES, sl = rem % PLANES;
-            const int q = sl ^ swz<RB, PLANES>(row);
-            const int r0 = pn == 0 ? i0 : j0;
-            src_off[pn][c] = (bl * N + min(r0 + row, N - 1)) * RB + q * 16;
+    for (int c = 0; c < CPT_B; ++c) src_b[c] = chunk_src(c, TB, j0);
+    const int stage_bytes = kStg * Nz * RB;
+    auto issue_panel = [&](int st, char* panel, int c, int src, int rows) {
+        char* dst = panel + (c * kThreads + wid * 64) * 16;
+        int voff = src, soff = st * stage_bytes;
+        if ((st + 1) * kStg > nb) {   // past the end (uniform): whole offset in voffset, block clamped to nb - 1
+            const int bl = (tid + c * kThreads) / (rows * PLANES);
+            voff += (min(st * kStg + bl, nb - 1) - bl) * Nz * RB;
+            soff = 0;
         }
-    const int stage_bytes = kStg * N * RB;
+        buffer_load_lds16(z, z_bytes, dst, voff, soff);
+    };
     auto issue = [&](int st) {
-        const int bq = st % NB;
-        const bool past_end = (st + 1) * kStg > nb;          // uniform
+        char* buf = lds_raw + (st % NB) * BUF;
 #pragma unroll
-        for (int pn = 0; pn < 2; ++pn) {
-            if (pn == 1 && diag) break;
+        for (int c = 0; c < CPT; ++c) issue_panel(st, buf, c, src_a[c], TILE);
+        if (!diag) {
 #pragma unroll
-            for (int c = 0; c < CPT; ++c) {
-                char* dst = lds_raw + (bq * 2 + pn) * PANEL + (c * kThreads + wid * 64) * 16;
-                int voff = src_off[pn][c], soff = st * stage_bytes;
-                if (past_end) {   // whole offset in voffset, block clamped to nb - 1
-                    const int bl = (tid + c * kThreads) / (TILE * PLANES);
-                    voff += (min(st * kStg + bl, nb - 1) - bl) * N * RB;
-                    soff = 0;
-                }
-                buffer_load_lds16(z, z_bytes, dst, voff, soff);
-            }
+            for (int c = 0; c < CPT_B; ++c) issue_panel(st, buf + PANEL, c, src_b[c], TB);
         }
     };
     // wait until this wave's loads of stage s have landed, given that the
@@ -388,37 +428,56 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
     auto wait_landed = [&](int s) {
         const int later = min(n_st - 1 - s, kDmaDepth - 1);
         if (diag) wait_vmcnt_runtime<CPT>(later);
-        else wait_vmcnt_runtime<2 * CPT>(later);
+        else wait_vmcnt_runtime<CPT + CPT_B>(later);
     };
     auto panels = [&](int st, const char*& PA, const char*& PB) {
-        const int bq = st % NB;
-        PA = lds_raw + (bq * 2) * PANEL;
-        PB = lds_raw + (bq * 2 + (diag ? 0 : 1)) * PANEL;
+        const char* buf = lds_raw + (st % NB) * BUF;
+        PA = buf;
+        PB = diag ? buf : buf + PANEL;
     };
     // operand set kk & 1 holds k-step kk of the current stage; the last
     // stage is peeled off so that the loop body has no branch around LDS
     // reads and the compiler's LDS wait counts stay exact
     uint4 oa[2][NA], ob[2][NBO];
+    V bv[2][NBO], bj[2][NBO];
+    // B operands of slot `slot` as MFMA values: as loaded and J-swapped
+    auto prep = [&](uint4 (&b)[NBO], V (&v)[NBO], V (&j)[NBO]) {
+#pragma unroll
+        for (int i = 0; i < NBO; ++i) {
+            v[i] = cvt(b[i]);
+            j[i] = jsw(b[i]);
+        }
+    };
     auto run_stage = [&](int st, auto has_next_tag) {
         constexpr bool kNext = decltype(has_next_tag)::value;
         const char *PA, *PB;
         panels(st, PA, PB);
 #pragma unroll
         for (int kk = 0; kk + 1 < NKK; ++kk) {
-            if constexpr (!kNext) mask_tail_ops(st, kk, oa[kk & 1], ob[kk & 1]);
-            mma(oa[kk & 1], ob[kk & 1], [&] { load_ops(PA, PB, kk + 1, oa[(kk + 1) & 1], ob[(kk + 1) & 1]); });
+            mma(oa[kk & 1], bv[kk & 1], bj[kk & 1],
+                [&] { load_ops(PA, PB, kk + 1, oa[(kk + 1) & 1], ob[(kk + 1) & 1]); },
+                [&] {
+                    if constexpr (!kNext) mask_tail_ops(st, kk + 1, oa[(kk + 1) & 1], ob[(kk + 1) & 1]);
+                    prep(ob[(kk + 1) & 1], bv[(kk + 1) & 1], bj[(kk + 1) & 1]);
+                });
         }
-        if constexpr (!kNext) mask_tail_ops(st, NKK - 1, oa[(NKK - 1) & 1], ob[(NKK - 1) & 1]);
-        mma(oa[(NKK - 1) & 1], ob[(NKK - 1) & 1], [&] {
-            if constexpr (kNext) {
-                wait_landed(st + 1);
-                dma_barrier();
-                if (st + 1 + kDmaDepth < n_st) issue(st + 1 + kDmaDepth);
-                const char *NA_, *NB_;
-                panels(st + 1, NA_, NB_);
-                load_ops(NA_, NB_, 0, oa[0], ob[0]);
-            }
-        });
+        mma(oa[(NKK - 1) & 1], bv[(NKK - 1) & 1], bj[(NKK - 1) & 1],
+            [&] {
+                if constexpr (kNext) {
+                    wait_landed(st + 1);
+                    dma_barrier();
+                    if (st + 1 + kDmaDepth < n_st) issue(st + 1 + kDmaDepth);
+                    const char *NA_, *NB_;
+                    panels(st + 1, NA_, NB_);
+                    load_ops(NA_, NB_, 0, oa[0], ob[0]);
+                }
+            },
+            [&] {
+                if constexpr (kNext) {
+                    if (st + 2 == n_st) mask_tail_ops(st + 1, 0, oa[0], ob[0]);
+                    prep(ob[0], bv[0], bj[0]);
+                }
+            });
     };
     // scalar loads still in flight would turn every LDS wait in the loop
     // into lgkmcnt(0): settle them here
@@ -433,6 +492,8 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
         const char *PA, *PB;
         panels(0, PA, PB);
         load_ops(PA, PB, 0, oa[0], ob[0]);
+        if (n_st == 1) mask_tail_ops(0, 0, oa[0], ob[0]);
+        prep(ob[0], bv[0], bj[0]);
     }
     for (int st = 0; st + 1 < n_st; ++st) run_stage(st, std::true_type{});
     run_stage(n_st - 1, std::false_type{});
@@ -477,7 +538,8 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             const int Jc = j0 + bn[J::IB[p]] * 32 + lr;
-            const int b = Jc >> 1;
+            const int bc = Jc >> 1;                          // column antenna (compact index)
+            const int b = amap && Jc < N ? amap[bc] : bc;     // ... in the visibility layout
             const bool fb = fcol[J::IB[p]];
 #pragma unroll
             for (int r = 0; r < 16; r += 2) {
@@ -486,8 +548,9 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
                 const E yr = pair_swap(odd ? r0 : r1), yi = pair_swap(odd ? i0v : i1v);
                 E o0 = odd ? yr : r0, o1 = odd ? yi : i0v, o2 = odd ? r1 : yr, o3 = odd ? i1v : yi;
                 const int I = i0 + am[J::IA[p]] * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
-                const int a = I >> 1;
-                if (Jc >= N || I >= N || a < b) continue;
+                const int ac = I >> 1;
+                if (Jc >= N || I >= N || ac < bc) continue;
+                const int a = amap ? amap[ac] : ac;          // monotone: a >= b as ac >= bc
                 if (a == b) {             // inputs equal for (0, 0) and (1, 1)
                     if (odd) o3 = E(0);
                     else o1 = E(0);
@@ -512,7 +575,7 @@ template <int DT, int TILE>
 __device__ __forceinline__ void xtile_f32(const char* __restrict__ z, char* __restrict__ vis_ch,
                                       int32_t* __restrict__ w_sb, const uint8_t* __restrict__ fl_sb,
                                       int N, int Na, int S, int ti, int tj, bool write_weights,
-                                      char* lds_raw) {
+                                      char* lds_raw, int Nz = -1, const int32_t* __restrict__ amap = nullptr) {
     using Tr = XT<DT>;
     constexpr int RB = Tr::RB, PLANES = Tr::PLANES, kStg = stage_blocks<DT, TILE>();
     constexpr int WT = TILE / 2, MB = WT / 32;
@@ -523,6 +586,7 @@ __device__ __forceinline__ void xtile_f32(const char* __restrict__ z, char* __re
     static_assert(DT == AFC_F32, "fp32 only");
     using acc_t = typename Tr::acc_t;
 
+    if (Nz < 0) Nz = N;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr = wid >> 1, wc = wid & 1;
@@ -566,7 +630,7 @@ __device__ __forceinline__ void xtile_f32(const char* __restrict__ z, char* __re
                 const int row = rem / PLANES, q = rem % PLANES;
                 const int blk = min(st * kStg + bl, nb - 1);
                 const int rg = min(r0 + row, N - 1);
-                pre[slot][pn][c] = *reinterpret_cast<const uint4*>(z + ((int64_t)blk * N + rg) * RB + q * 16);
+                pre[slot][pn][c] = *reinterpret_cast<const uint4*>(z + ((int64_t)blk * Nz + rg) * RB + q * 16);
             }
         }
     };
@@ -727,14 +791,16 @@ __device__ __forceinline__ void xtile_f32(const char* __restrict__ z, char* __re
             if (diag && wr == wc && m < n) continue;
             const int J = j0 + wc * WT + n * 32 + lr;
             if (J >= N) continue;
-            const int b = J >> 1, qq = J & 1;
+            const int bc = J >> 1, qq = J & 1;
+            const int b = amap ? amap[bc] : bc;
             const bool fb = fcol[n];
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int I = i0 + wr * WT + m * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
                 if (I >= N) continue;
-                const int a = I >> 1, p = I & 1;
-                if (a < b) continue;
+                const int ac = I >> 1, p = I & 1;
+                if (ac < bc) continue;
+                const int a = amap ? amap[ac] : ac;
                 const bool flagged = fb || frow[m][((r >> 2) << 1) | ((r >> 1) & 1)];
                 const int64_t bl = (int64_t)a * (a + 1) / 2 + b;
                 const int64_t e = bl * 4 + p * 2 + qq;
@@ -753,14 +819,15 @@ __device__ __forceinline__ void xtile_f32(const char* __restrict__ z, char* __re
 template <int DT, int TILE>
 __device__ __forceinline__ void xtile(const char* __restrict__ z, char* __restrict__ vis_ch,
                                       int32_t* __restrict__ w_sb, const uint8_t* __restrict__ fl_sb,
-                                      int N, int Na, int S, int ti, int tj, bool write_weights, char* lds_raw) {
+                                      int N, int Na, int S, int ti, int tj, bool write_weights, char* lds_raw,
+                                      int Nz = -1, const int32_t* __restrict__ amap = nullptr) {
     if constexpr (DT == AFC_F32) {
-        xtile_f32<DT, TILE>(z, vis_ch, w_sb, fl_sb, N, Na, S, ti, tj, write_weights, lds_raw);
+        xtile_f32<DT, TILE>(z, vis_ch, w_sb, fl_sb, N, Na, S, ti, tj, write_weights, lds_raw, Nz, amap);
     } else {
         const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         auto run = [&](auto job, const int (&am)[4], const int (&bn)[2]) {
             xtile_mm<DT, TILE, decltype(job)>(z, vis_ch, w_sb, fl_sb, N, Na, S, ti, tj, write_weights, lds_raw,
-                                              am, bn);
+                                              am, bn, Nz, amap);
         };
         if constexpr (TILE == 128) {
             if (ti != tj) {
@@ -810,6 +877,69 @@ __global__ __launch_bounds__(kThreads, 2) void xengine_kernel(XArgs a) {
     xtile<DT, TILE>(z, vis, wsb, fl, a.N, a.Na, a.S[sb], ti, tj, wsb != nullptr && ch == 0, lds);
 }
 
+// One-workgroup-per-CU X-engine (int8 / fp16).  With one wave per SIMD a
+// wave may hold 256 accumulator registers, so an off-diagonal wave owns a
+// 4 x 2 job of 32 x 32 blocks (128 rows x 64 columns): per k-step it reads
+// 4 A and 2 B operands from LDS for 16 MFMAs, against 5 for 8 in the
+// two-workgroups-per-CU form, and each staged byte of the 128 x 256 tile
+// feeds a third more MACs.  Per channel the row tiles ti (128 receivers) are
+// covered by: ti / 2 tiles of 128 x 256 (column tiles 2k, 2k + 1), one
+// 128 x 128 tile (column tile ti - 1) when ti is odd, and the diagonal
+// 128 x 128 tile (ten lower-triangle blocks spread 3/3/2/2 over the waves).
+// Items are ordered long first: all 128 x 256 tiles of a channel, then the
+// 128 x 128 ones, then the diagonal ones.
+struct XWideArgs {
+    const char* z;              // subband 0, channel 0
+    char* vis;
+    int32_t* weights;
+    const uint8_t* flags;
+    int64_t z_ch_bytes;         // bytes between channels
+    int64_t z_sb_bytes;         // bytes between subbands
+    int N, Na, P;
+    int n_pairs, n_singles, n_items;    // items per channel
+    int total, per_xcd;
+    int S[AFC_MAX_SUBBANDS];
+};
+
+template <int DT>
+__global__ __launch_bounds__(kThreads, 1) void xengine_wide_kernel(XWideArgs a) {
+    __shared__ __attribute__((aligned(16))) char lds[wide_lds_bytes<DT>()];
+    const int bid = blockIdx.x;
+    const int w = (bid & 7) * a.per_xcd + (bid >> 3);       // XCD-contiguous ranges of items
+    if (w >= a.total) return;
+    int t = w % a.n_items;
+    const int rest = w / a.n_items;
+    const int ch = rest % a.P;
+    const int sb = rest / a.P;
+    const char* z = a.z + sb * a.z_sb_bytes + ch * a.z_ch_bytes;
+    const int64_t nbl = (int64_t)a.Na * (a.Na + 1) / 2;
+    char* vis = a.vis + ((int64_t)sb * a.P + ch) * nbl * 4 * 8;
+    int32_t* wsb = a.weights ? a.weights + (int64_t)sb * nbl : nullptr;
+    const uint8_t* fl = a.flags ? a.flags + (int64_t)sb * a.Na : nullptr;
+    const bool ww = wsb != nullptr && ch == 0;
+    const int S = a.S[sb];
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (t < a.n_pairs) {                   // 128 x 256: row tile ti holds ti / 2 of them
+        int ti = 2;
+        for (; t >= (ti >> 1); ++ti) t -= ti >> 1;
+        const int am[4] = {0, 1, 2, 3}, bn[2] = {2 * wid, 2 * wid + 1};
+        xtile_mm<DT, 128, JobRows4x2, 256>(z, vis, wsb, fl, a.N, a.Na, S, ti, 2 * t, ww, lds, am, bn);
+        return;
+    }
+    t -= a.n_pairs;
+    if (t < a.n_singles) {                 // 128 x 128 left over in an odd row tile
+        const int ti = 2 * t + 1;
+        const int am[4] = {0, 1, 2, 3}, bn[2] = {wid, 0};
+        xtile_mm<DT, 128, JobRows4>(z, vis, wsb, fl, a.N, a.Na, S, ti, ti - 1, ww, lds, am, bn);
+        return;
+    }
+    const int ti = t - a.n_singles;        // diagonal
+    if (wid == 0) xtile_mm<DT, 128, JobDiag0>(z, vis, wsb, fl, a.N, a.Na, S, ti, ti, ww, lds, JobDiag0::AM, JobDiag0::BN);
+    else if (wid == 1) xtile_mm<DT, 128, JobDiag1>(z, vis, wsb, fl, a.N, a.Na, S, ti, ti, ww, lds, JobDiag1::AM, JobDiag1::BN);
+    else if (wid == 2) xtile_mm<DT, 128, JobDiag2>(z, vis, wsb, fl, a.N, a.Na, S, ti, ti, ww, lds, JobDiag2::AM, JobDiag2::BN);
+    else xtile_mm<DT, 128, JobDiag3>(z, vis, wsb, fl, a.N, a.Na, S, ti, ti, ww, lds, JobDiag3::AM, JobDiag3::BN);
+}
+
 // Batched form: one workgroup per work item of a host-built list; each item
 // is one tile of one channel of one subband with its own sample type and
 // integration length.  MODE 0 serves int8 and fp16 subbands (mixed in one
@@ -817,11 +947,18 @@ __global__ __launch_bounds__(kThreads, 2) void xengine_kernel(XArgs a) {
 // round-robin over the 8 XCDs and the list holds each XCD's items (whole
 // channels, cost-balanced across XCDs) contiguously, so that the hardware
 // dispatcher keeps the tiles in flight on an XCD a window of few channels.
+//
+// With compaction (counts != nullptr) the channeliser has stored only the
+// receivers of unflagged antennas, in antenna order, at the front of each
+// subband's rows: subband b has 2 * counts[2 b] receivers with data, amap
+// [b][c] is the antenna of compact antenna c, and tiles wholly beyond the
+// data exit at once, so flagged baselines cost no MFMA work (their zeros
+// come from plan_zero_flagged_kernel).
 template <int MODE, int TILE, int WPC>
 __global__ __launch_bounds__(kThreads, WPC) void xengine_list_kernel(
     const char* __restrict__ z_ws, char* __restrict__ vis, int32_t* __restrict__ weights,
     const uint8_t* __restrict__ flags, const XSubband* __restrict__ sbs, const XWork* __restrict__ work,
-    XcdRanges r, int N, int Na) {
+    XcdRanges r, int N, int Na, const int32_t* __restrict__ counts, const int32_t* __restrict__ amap) {
     constexpr int kLds = MODE == 0 ? (lds_bytes<AFC_I8, TILE>() > lds_bytes<AFC_F16, TILE>() ? lds_bytes<AFC_I8, TILE>()
                                                                                             : lds_bytes<AFC_F16, TILE>())
                                    : lds_bytes<AFC_F32, TILE>();
@@ -833,19 +970,22 @@ __global__ __launch_bounds__(kThreads, WPC) void xengine_list_kernel(
     const XSubband sd = sbs[wk.sb];
     char* vis_ch = vis + sd.vis_off + (int64_t)wk.ch * nbl * 4 * 8;
     int32_t* wsb = weights ? weights + (int64_t)wk.sb * nbl : nullptr;
-    const uint8_t* fl = flags ? flags + (int64_t)wk.sb * Na : nullptr;
+    const uint8_t* fl = flags && !counts ? flags + (int64_t)wk.sb * Na : nullptr;
     const bool ww = wsb != nullptr && wk.ch == 0;
+    const int Nv = counts ? 2 * counts[2 * wk.sb] : N;        // receivers with data
+    if (wk.ti * TILE >= Nv) return;                            // uniform
+    const int32_t* am = counts ? amap + (int64_t)wk.sb * Na : nullptr;
     if constexpr (MODE == 0) {
         if (sd.dt == AFC_I8) {
             const char* z = z_ws + sd.z_off + (int64_t)wk.ch * sd.Sb * N * kSBlk * 2;
-            xtile<AFC_I8, TILE>(z, vis_ch, wsb, fl, N, Na, sd.S, wk.ti, wk.tj, ww, lds);
+            xtile<AFC_I8, TILE>(z, vis_ch, wsb, fl, Nv, Na, sd.S, wk.ti, wk.tj, ww, lds, N, am);
         } else {
             const char* z = z_ws + sd.z_off + (int64_t)wk.ch * sd.Sb * N * kSBlk * 4;
-            xtile<AFC_F16, TILE>(z, vis_ch, wsb, fl, N, Na, sd.S, wk.ti, wk.tj, ww, lds);
+            xtile<AFC_F16, TILE>(z, vis_ch, wsb, fl, Nv, Na, sd.S, wk.ti, wk.tj, ww, lds, N, am);
         }
     } else {
         const char* z = z_ws + sd.z_off + (int64_t)wk.ch * sd.Sb * N * kSBlk * 8;
-        xtile<AFC_F32, TILE>(z, vis_ch, wsb, fl, N, Na, sd.S, wk.ti, wk.tj, ww, lds);
+        xtile<AFC_F32, TILE>(z, vis_ch, wsb, fl, Nv, Na, sd.S, wk.ti, wk.tj, ww, lds, N, am);
     }
 }
 
@@ -898,6 +1038,34 @@ hipError_t launch_xengine(const XLaunch& l, hipStream_t stream) {
     a.per_xcd = (int)ceil_div(total, 8);
     for (int b = 0; b < l.B; ++b) a.S[b] = l.S_host[b];
     const dim3 grid((unsigned)(a.per_xcd * 8));
+#ifdef AFC_XENGINE_WIDE
+    if (l.dt != AFC_F32) {
+        XWideArgs w{};
+        w.z = a.z;
+        w.vis = a.vis;
+        w.weights = a.weights;
+        w.flags = a.flags;
+        w.z_ch_bytes = a.z_ch_bytes;
+        w.z_sb_bytes = a.z_sb_bytes;
+        w.N = a.N;
+        w.Na = a.Na;
+        w.P = kP;
+        const int T = (int)ceil_div(l.N, 128);
+        w.n_pairs = 0;
+        for (int ti = 0; ti < T; ++ti) w.n_pairs += ti / 2;
+        w.n_singles = T / 2;
+        w.n_items = w.n_pairs + w.n_singles + T;
+        const int64_t wt = (int64_t)w.n_items * kP * l.B;
+        if (wt > (1LL << 30)) return hipErrorInvalidValue;
+        w.total = (int)wt;
+        w.per_xcd = (int)ceil_div(wt, 8);
+        for (int b = 0; b < l.B; ++b) w.S[b] = l.S_host[b];
+        const dim3 wg((unsigned)(w.per_xcd * 8));
+        if (l.dt == AFC_I8) hipLaunchKernelGGL((xengine_wide_kernel<AFC_I8>), wg, dim3(kThreads), 0, stream, w);
+        else hipLaunchKernelGGL((xengine_wide_kernel<AFC_F16>), wg, dim3(kThreads), 0, stream, w);
+        return hipGetLastError();
+    }
+#endif
     switch (l.dt) {
         case AFC_I8: hipLaunchKernelGGL((xengine_kernel<AFC_I8, 128>), grid, dim3(kThreads), 0, stream, a); break;
         case AFC_F16: hipLaunchKernelGGL((xengine_kernel<AFC_F16, 128>), grid, dim3(kThreads), 0, stream, a); break;
@@ -914,7 +1082,8 @@ int xengine_list_grid(const XcdRanges& r) {
 
 hipError_t launch_xengine_list(const void* z_ws, void* vis, int32_t* weights, const uint8_t* flags,
                                const XSubband* sbs_dev, const XWork* work_dev, const XcdRanges& ranges, int N,
-                               int Na, int mode, int tile, hipStream_t stream) {
+                               int Na, int mode, int tile, const int32_t* counts, const int32_t* amap,
+                               hipStream_t stream) {
     const char* z = reinterpret_cast<const char*>(z_ws);
     char* v = reinterpret_cast<char*>(vis);
     const int g = xengine_list_grid(ranges);
@@ -922,13 +1091,13 @@ hipError_t launch_xengine_list(const void* z_ws, void* vis, int32_t* weights, co
     const dim3 grid((unsigned)g), block(kThreads);
     if (mode == 1)  // fp32 subbands
         hipLaunchKernelGGL((xengine_list_kernel<1, 64, 2>), grid, block, 0, stream, z, v, weights, flags, sbs_dev,
-                           work_dev, ranges, N, Na);
+                           work_dev, ranges, N, Na, counts, amap);
     else if (tile == 128)
         hipLaunchKernelGGL((xengine_list_kernel<0, 128, 2>), grid, block, 0, stream, z, v, weights, flags, sbs_dev,
-                           work_dev, ranges, N, Na);
+                           work_dev, ranges, N, Na, counts, amap);
     else
         hipLaunchKernelGGL((xengine_list_kernel<0, 64, 4>), grid, block, 0, stream, z, v, weights, flags, sbs_dev,
-                           work_dev, ranges, N, Na);
+                           work_dev, ranges, N, Na, counts, amap);
     return hipGetLastError();
 }
 
