@@ -383,13 +383,51 @@ def main():
         cm4 = sum(P * n * (n + 1) // 2 * int(bp.n_spectra[b]) for b, n in enumerate(nprime))
         plan_ms = tp.ms("plan")
         info = plan.info()
+        try:
+            choice = list(json.load(open(os.path.join(tune_dir, "tune_cache.json"))).values())[0]
+        except (OSError, ValueError, IndexError):
+            choice = None
         out["batching"] = {"workload": cfgb.name, "graph_ms": round(plan_ms, 3),
                            "useful_tcmacs": round(cm4 / (plan_ms * 1e-3) / 1e12, 3),
                            "real_time_factor": round(max(bp.n_spectra) * P / W.F_SUBBAND / (plan_ms * 1e-3), 2),
+                           "flagged_antenna_fraction": round(float(bp.flags.mean()), 4),
+                           "tuned": None if choice is None else {"tile": choice[0], "workgroups_per_cu": choice[1],
+                                                                 "int8_fp16_split": bool(choice[2])},
                            "tile": info.tile, "workgroups": info.n_workgroups, "work_items": info.n_work_items}
         log(f"plan {plan_ms:.3f} ms")
         plan.close()
-        del xbat, ws, visb, wb
+        del ws
+        # the same work as two graphs, one per sample type: parts against the whole
+        parts = {}
+        for t in ("i8", "f16"):
+            idx = [b for b in range(cfgb.n_subbands) if dts[b] == t]
+            if not idx:
+                continue
+            sel = torch.as_tensor(idx, device=dev)
+            xs = xbat.index_select(0, sel)
+            pl = afc.Plan(Na, [int(bp.n_spectra[b]) for b in idx], [t] * len(idx), n_spectra=cfgb.n_spectra,
+                          tune_cache=os.path.join(tune_dir, f"tune_{t}.json"))
+            wss = torch.empty(pl.workspace_bytes, dtype=torch.uint8, device=dev)
+            vs = torch.empty(afc.visibility_shape(len(idx), Na), dtype=torch.int32, device=dev)
+            wsb = torch.empty((len(idx), nbl), dtype=torch.int32, device=dev)
+            fs = fl.index_select(0, sel)
+            gs = [gb[b] for b in idx]
+            pl.launch(xs, taps, gs, wss, vs, flags=fs, weights=wsb)
+            torch.cuda.synchronize()
+            tt = Timer(torch)
+            for _ in range(3):
+                e = tt.rec("g")
+                pl.launch(xs, taps, gs, wss, vs, flags=fs, weights=wsb)
+                e.record(torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            parts[t] = {"subbands": len(idx), "graph_ms": round(tt.ms("g"), 3)}
+            pl.close()
+            del xs, wss, vs, wsb
+            torch.cuda.empty_cache()
+        out["batching"]["per_type_graphs"] = parts
+        out["batching"]["sum_of_parts_ms"] = round(sum(v["graph_ms"] for v in parts.values()), 3)
+        log(f"plan parts {parts}")
+        del xbat, visb, wb
         torch.cuda.empty_cache()
 
         # ---- calibration adjoint, 576 antennas x 64 channels

@@ -398,9 +398,11 @@ AFC_API int afc_image_from_grid(int32_t grid_size, const void* grid, const doubl
  *
  * afc_plan_create    d: shape with n_spectra = max S_b; dtype_per_sb host
  *                    [B] (AFC_F16 or AFC_I8 each, or AFC_F32); n_spectra_per_sb
- *                    host [B]; tune_cache_path: a JSON file of measured tile
- *                    choices (read, and written after tuning), or NULL for
- *                    the built-in default.  Tuning runs kernels on the current
+ *                    host [B]; tune_cache_path: a JSON file of measured
+ *                    choices {"key": [tile, workgroups per CU, split]} (read,
+ *                    and written after tuning; split = 1 puts int8 and fp16
+ *                    subbands in correlator launches of their own), or NULL
+ *                    for the built-in default (128, 2, 0).  Tuning runs kernels on the current
  *                    device at creation time on scratch memory it allocates
  *                    and frees there.
  * afc_plan_workspace_bytes  bytes of the caller-owned workspace that holds

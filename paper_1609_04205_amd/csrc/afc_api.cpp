@@ -513,7 +513,8 @@ struct afc_plan {
         int n_items = 0;
         XWork* d_work = nullptr;
         XcdRanges ranges{};
-    } mode[2];
+    } mode[3];    // 0: int8 and fp16 subbands (int8 only when split), 1: fp32, 2: fp16 when split
+    bool split = false;     // int8 and fp16 subbands in launches of their own
     std::vector<PpfItem> items;
     // A captured graph with the channeliser's item table it reads (the table
     // holds the int8 gains, so each capture has its own).  `done` is recorded
@@ -547,6 +548,12 @@ double tile_cost(int dt, int tile, int S, bool diag) {
 // Build the work list of one mode: the (subband, channel) groups are spread
 // over the 8 XCDs by cost (longest first onto the least loaded XCD), and each
 // XCD's items are stored contiguously, group after group, tiles in row order.
+bool in_mode(const afc_plan& p, int m, int dt) {
+    if (m == 0) return dt == AFC_I8 || (!p.split && dt == AFC_F16);
+    if (m == 1) return dt == AFC_F32;
+    return p.split && dt == AFC_F16;
+}
+
 void build_work(const afc_plan& p, int m, int tile, std::vector<XWork>& work_out, XcdRanges& ranges) {
     const int nT = (int)ceil_div(p.N, tile);
     struct G {
@@ -555,7 +562,7 @@ void build_work(const afc_plan& p, int m, int tile, std::vector<XWork>& work_out
     };
     std::vector<G> groups;
     for (int b = 0; b < p.d.n_subbands; ++b) {
-        const bool in_mode = m == 0 ? (p.dt[b] == AFC_I8 || p.dt[b] == AFC_F16) : p.dt[b] == AFC_F32;
+        if (!in_mode(p, m, p.dt[b])) continue;
         if (!in_mode) continue;
         double c = 0;
         for (int ti = 0; ti < nT; ++ti)
@@ -617,9 +624,14 @@ std::string tune_key(const afc_plan& p) {
     return o.str();
 }
 
-// The tune cache is a flat JSON object {"key": [tile, wg_per_cu], ...}.
-std::map<std::string, std::pair<int, int>> read_cache(const char* path) {
-    std::map<std::string, std::pair<int, int>> m;
+// The tune cache is a flat JSON object {"key": [tile, wg_per_cu, split], ...}
+// (split: int8 and fp16 subbands in separate correlator launches; entries
+// with two values are read as split = 0).
+struct TuneChoice {
+    int tile = 128, wpc = 2, split = 0;
+};
+std::map<std::string, TuneChoice> read_cache(const char* path) {
+    std::map<std::string, TuneChoice> m;
     std::ifstream f(path);
     if (!f) return m;
     std::stringstream ss;
@@ -632,30 +644,40 @@ std::map<std::string, std::pair<int, int>> read_cache(const char* path) {
         const std::string key = s.substr(i + 1, j - i - 1);
         const size_t lb = s.find('[', j), rb = s.find(']', j);
         if (lb == std::string::npos || rb == std::string::npos) break;
-        int a = 0, b = 0;
-        if (sscanf(s.c_str() + lb, "[%d,%d]", &a, &b) == 2 || sscanf(s.c_str() + lb, "[ %d , %d ]", &a, &b) == 2)
-            m[key] = {a, b};
+        int a = 0, b = 0, c = 0;
+        const int n = sscanf(s.c_str() + lb, "[ %d , %d , %d ]", &a, &b, &c);
+        if (n >= 2) m[key] = TuneChoice{a, b, n == 3 ? c : 0};
         i = rb + 1;
     }
     return m;
 }
 
-void write_cache(const char* path, const std::map<std::string, std::pair<int, int>>& m) {
+void write_cache(const char* path, const std::map<std::string, TuneChoice>& m) {
     std::ofstream f(path);
     f << "{\n";
     size_t k = 0;
     for (const auto& kv : m) {
-        f << "  \"" << kv.first << "\": [" << kv.second.first << ", " << kv.second.second << "]"
+        f << "  \"" << kv.first << "\": [" << kv.second.tile << ", " << kv.second.wpc << ", " << kv.second.split << "]"
           << (++k < m.size() ? ",\n" : "\n");
     }
     f << "}\n";
 }
 
 // Time the int8/fp16 correlator of the plan's own work for each candidate
-// tile (128 wide at 2 workgroups per CU, 64 wide at 4) on scratch buffers
-// holding random samples; returns the best.
-int tune_mode0(afc_plan* p, int& tile_out, int& wg_per_cu_out) {
-    const int cands[][2] = {{128, 2}, {64, 4}};
+// -- tile 128 wide at 2 workgroups per CU or 64 wide at 4, int8 and fp16
+// subbands in one launch or in one launch each (when both types are
+// present) -- on scratch buffers holding random samples; returns the best.
+int tune_mode0(afc_plan* p, TuneChoice& out) {
+    bool has8 = false, has16 = false;
+    for (int b = 0; b < p->d.n_subbands; ++b) {
+        has8 |= p->dt[b] == AFC_I8;
+        has16 |= p->dt[b] == AFC_F16;
+    }
+    std::vector<TuneChoice> cands = {{128, 2, 0}, {64, 4, 0}};
+    if (has8 && has16) {
+        cands.push_back({128, 2, 1});
+        cands.push_back({64, 4, 1});
+    }
     size_t vis_bytes = (size_t)p->d.n_subbands * kP * nbl_of(p->Na) * 32;
     void* z = nullptr;
     void* vis = nullptr;
@@ -677,17 +699,22 @@ int tune_mode0(afc_plan* p, int& tile_out, int& wg_per_cu_out) {
     hipEventCreate(&e0);
     hipEventCreate(&e1);
     float best = 1e30f;
-    tile_out = 128;
-    wg_per_cu_out = 2;
+    out = cands[0];
+    int rc = AFC_OK;
     for (const auto& c : cands) {
-        int rc = upload_mode(p, 0, c[0]);
+        p->split = c.split != 0;
+        rc = upload_mode(p, 0, c.tile);
+        if (rc == AFC_OK) rc = upload_mode(p, 2, c.tile);
         if (rc != AFC_OK) break;
-        const afc_plan::Mode& md = p->mode[0];
         float tmin = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
             hipEventRecord(e0, nullptr);
-            launch_xengine_list(z, vis, nullptr, nullptr, p->d_sbs, md.d_work, md.ranges, p->N, p->Na, 0, md.tile,
-                                nullptr, nullptr, nullptr);
+            for (int m : {0, 2}) {
+                const afc_plan::Mode& md = p->mode[m];
+                if (md.used)
+                    launch_xengine_list(z, vis, nullptr, nullptr, p->d_sbs, md.d_work, md.ranges, p->N, p->Na, 0,
+                                        md.tile, nullptr, nullptr, nullptr);
+            }
             hipEventRecord(e1, nullptr);
             hipEventSynchronize(e1);
             float ms = 0;
@@ -696,15 +723,14 @@ int tune_mode0(afc_plan* p, int& tile_out, int& wg_per_cu_out) {
         }
         if (tmin < best) {
             best = tmin;
-            tile_out = c[0];
-            wg_per_cu_out = c[1];
+            out = c;
         }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     hipFree(z);
     hipFree(vis);
-    return AFC_OK;
+    return rc;
 }
 
 void free_capture(afc_plan::Capture* c) {
@@ -764,11 +790,11 @@ int capture_plan(afc_plan* p, const int16_t* x, const float* taps, const std::ve
     if (flags) le = launch_plan_compact(flags, B, p->Na, inv, amap, flagged, counts, p->cap_stream);
     if (le == hipSuccess)
         le = launch_ppf_batched(x, taps, z_workspace, c->d_items, B, p->N, p->d.n_spectra, inv, p->cap_stream);
-    for (int m = 0; m < 2 && le == hipSuccess; ++m) {
+    for (int m = 0; m < 3 && le == hipSuccess; ++m) {
         const afc_plan::Mode& md = p->mode[m];
         if (!md.used) continue;
-        le = launch_xengine_list(z_workspace, vis, weights, flags, p->d_sbs, md.d_work, md.ranges, p->N, p->Na, m,
-                                 md.tile, counts, amap, p->cap_stream);
+        le = launch_xengine_list(z_workspace, vis, weights, flags, p->d_sbs, md.d_work, md.ranges, p->N, p->Na,
+                                 m == 1 ? 1 : 0, md.tile, counts, amap, p->cap_stream);
     }
     if (flags && le == hipSuccess) le = launch_plan_zero_flagged(flagged, counts, B, p->Na, vis, weights, p->cap_stream);
     e = hipStreamEndCapture(p->cap_stream, &c->graph);
@@ -854,26 +880,27 @@ AFC_API int afc_plan_create(const afc_dims* d, const afc_dtype* dtype_per_sb, co
         any1 |= p->dt[b] == AFC_F32;
     }
     if (any0) {
-        int tile = 128, wpc = 2;
+        TuneChoice ch;
         if (tune_cache_path && *tune_cache_path) {
             auto cache = read_cache(tune_cache_path);
             const std::string key = tune_key(*p);
             auto it = cache.find(key);
-            if (it != cache.end() && (it->second.first == 64 || it->second.first == 128) && it->second.second >= 1 &&
-                it->second.second <= 8) {
-                tile = it->second.first;
-                wpc = it->second.second;
+            if (it != cache.end() && (it->second.tile == 64 || it->second.tile == 128) && it->second.wpc >= 1 &&
+                it->second.wpc <= 8 && (it->second.split == 0 || it->second.split == 1)) {
+                ch = it->second;
             } else {
-                rc = tune_mode0(p, tile, wpc);
+                rc = tune_mode0(p, ch);
                 if (rc != AFC_OK) {
                     afc_plan_destroy(p);
                     return rc;
                 }
-                cache[key] = {tile, wpc};
+                cache[key] = ch;
                 write_cache(tune_cache_path, cache);
             }
         }
-        rc = upload_mode(p, 0, tile);
+        p->split = ch.split != 0;
+        rc = upload_mode(p, 0, ch.tile);
+        if (rc == AFC_OK) rc = upload_mode(p, 2, ch.tile);
         if (rc != AFC_OK) {
             afc_plan_destroy(p);
             return rc;
@@ -895,11 +922,11 @@ AFC_API size_t afc_plan_workspace_bytes(const afc_plan* p) { return p ? p->ws_by
 AFC_API int afc_plan_info(const afc_plan* p, int32_t* tile_rows, int32_t* tile_cols, int32_t* n_workgroups,
                           int32_t* n_work_items) {
     if (!p) return fail(AFC_ERR_INVALID, "plan is NULL");
-    const afc_plan::Mode& md = p->mode[0].used ? p->mode[0] : p->mode[1];
+    const afc_plan::Mode& md = p->mode[0].used ? p->mode[0] : p->mode[2].used ? p->mode[2] : p->mode[1];
     if (tile_rows) *tile_rows = md.tile;
     if (tile_cols) *tile_cols = md.tile;
     if (n_workgroups) *n_workgroups = md.n_wg;
-    if (n_work_items) *n_work_items = p->mode[0].n_items + p->mode[1].n_items;
+    if (n_work_items) *n_work_items = p->mode[0].n_items + p->mode[1].n_items + p->mode[2].n_items;
     return AFC_OK;
 }
 

@@ -128,6 +128,21 @@ def test_plan_forced_small_tiles(afc, dev, tmp_path):
     assert info.tile == 64
 
 
+def test_plan_split_launches(afc, dev, tmp_path):
+    """A tune cache entry puts int8 and fp16 subbands in correlator launches
+    of their own; results are unchanged."""
+    log("plan split int8 / fp16 launches")
+    Na = 56
+    S_list = [700, 64, 333, 5]
+    dts = ["i8", "f16", "i8", "f16"]
+    key = f"N{2 * Na}_i8x2_f16x2_f32x0_S5-700"
+    path = tmp_path / "tune.json"
+    path.write_text('{"%s": [128, 2, 1]}\n' % key)
+    flags = np.zeros((4, Na), np.uint8)
+    flags[2, [3, 30, 55]] = 1
+    _run_plan(afc, dev, Na, S_list, dts, flags, tune_cache=str(path))
+
+
 def test_plan_full_size_a12_batched(afc, dev, tmp_path):
     """AARTFAAC-12 batching workload: 32 subbands, S_b in 500..3051, 0-10% flagged, mixed fp16/int8."""
     log("plan full size a12_batched")
