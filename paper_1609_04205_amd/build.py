@@ -15,7 +15,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libafc.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["ppf.hip", "ppf_fine.hip", "xengine.hip", "validity.hip", "flag.hip", "imaging.hip", "calib.hip", "checked.hip",
-           "plan_flags.hip", "afc_api.cpp"]
+           "afc_api.cpp"]
 # calib.hip relies on error-free product/sum transformations: no contraction
 EXTRA = {"calib.hip": ["-ffp-contract=off"]}
 ARCH = os.environ.get("AFC_OFFLOAD_ARCH", "gfx950")

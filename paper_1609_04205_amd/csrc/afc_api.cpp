@@ -503,9 +503,6 @@ struct afc_plan {
     int64_t L = 0;
     // device tables (d_sbs and the work lists never change after creation)
     XSubband* d_sbs = nullptr;
-    // antenna compaction tables, rewritten from the flags by every launch
-    // that has flags: inv, amap, flagged [B][Na] and counts [B][2]
-    int32_t* d_compact = nullptr;
     struct Mode {
         bool used = false;
         int tile = 128;
@@ -713,7 +710,7 @@ int tune_mode0(afc_plan* p, TuneChoice& out) {
                 const afc_plan::Mode& md = p->mode[m];
                 if (md.used)
                     launch_xengine_list(z, vis, nullptr, nullptr, p->d_sbs, md.d_work, md.ranges, p->N, p->Na, 0,
-                                        md.tile, nullptr, nullptr, nullptr);
+                                        md.tile, nullptr);
             }
             hipEventRecord(e1, nullptr);
             hipEventSynchronize(e1);
@@ -779,24 +776,13 @@ int capture_plan(afc_plan* p, const int16_t* x, const float* taps, const std::ve
         free_capture(c);
         return hip_fail(e, "graph capture begin");
     }
-    // with flags: compact the flagged antennas out of the channeliser's
-    // output and the correlator's tiles, then zero their baselines
-    const int64_t NaB = (int64_t)p->Na * B;
-    int32_t* inv = flags ? p->d_compact : nullptr;
-    int32_t* amap = flags ? p->d_compact + NaB : nullptr;
-    int32_t* flagged = flags ? p->d_compact + 2 * NaB : nullptr;
-    int32_t* counts = flags ? p->d_compact + 3 * NaB : nullptr;
-    hipError_t le = hipSuccess;
-    if (flags) le = launch_plan_compact(flags, B, p->Na, inv, amap, flagged, counts, p->cap_stream);
-    if (le == hipSuccess)
-        le = launch_ppf_batched(x, taps, z_workspace, c->d_items, B, p->N, p->d.n_spectra, inv, p->cap_stream);
+    hipError_t le = launch_ppf_batched(x, taps, z_workspace, c->d_items, B, p->N, p->d.n_spectra, p->cap_stream);
     for (int m = 0; m < 3 && le == hipSuccess; ++m) {
         const afc_plan::Mode& md = p->mode[m];
         if (!md.used) continue;
         le = launch_xengine_list(z_workspace, vis, weights, flags, p->d_sbs, md.d_work, md.ranges, p->N, p->Na,
-                                 m == 1 ? 1 : 0, md.tile, counts, amap, p->cap_stream);
+                                 m == 1 ? 1 : 0, md.tile, p->cap_stream);
     }
-    if (flags && le == hipSuccess) le = launch_plan_zero_flagged(flagged, counts, B, p->Na, vis, weights, p->cap_stream);
     e = hipStreamEndCapture(p->cap_stream, &c->graph);
     if (le != hipSuccess || e != hipSuccess) {
         free_capture(c);
@@ -866,7 +852,6 @@ AFC_API int afc_plan_create(const afc_dims* d, const afc_dtype* dtype_per_sb, co
                               p->dt[b], 1.0f};
     }
     hipError_t e = hipMalloc(&p->d_sbs, B * sizeof(XSubband));
-    if (e == hipSuccess) e = hipMalloc(&p->d_compact, ((size_t)3 * B * p->Na + 2 * B) * sizeof(int32_t));
     if (e == hipSuccess) e = hipMemcpy(p->d_sbs, sbs.data(), B * sizeof(XSubband), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -969,7 +954,6 @@ AFC_API void afc_plan_destroy(afc_plan* p) {
     for (auto& md : p->mode)
         if (md.d_work) hipFree(md.d_work);
     if (p->d_sbs) hipFree(p->d_sbs);
-    if (p->d_compact) hipFree(p->d_compact);
     if (p->cap_stream) hipStreamDestroy(p->cap_stream);
     delete p;
 }

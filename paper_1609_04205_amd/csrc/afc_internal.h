@@ -41,10 +41,8 @@ struct PpfItem {
     int32_t dt;             // afc_dtype
     float gain;
 };
-// inv (or nullptr): [n_items][N/2] compact index of each antenna, -1 for a
-// flagged one, whose receivers are then not stored
 hipError_t launch_ppf_batched(const int16_t* x, const float* taps, void* z_ws, const PpfItem* items_dev,
-                              int n_items, int N, int max_S, const int32_t* inv, hipStream_t stream);
+                              int n_items, int N, int max_S, hipStream_t stream);
 
 // Fine channeliser: 256-channel bank, delay and bandpass compensation,
 // coherent 4:1 integration to 64 channels, stored in the layout of the
@@ -105,22 +103,9 @@ struct XcdRanges {
 // One workgroup per work item (workgroup ids go round-robin over the 8
 // XCDs); mode 0: int8 / fp16 subbands with tile-wide tiles (128 or 64),
 // mode 1: fp32 subbands (64).  Returns the grid size through n_wg_out.
-// counts, amap (or nullptr): per subband [active, flagged] antenna counts and
-// [B][Na] the antenna of each compact index, when the channeliser has
-// compacted flagged antennas out (launch_plan_compact)
 hipError_t launch_xengine_list(const void* z_ws, void* vis, int32_t* weights, const uint8_t* flags,
                                const XSubband* sbs_dev, const XWork* work_dev, const XcdRanges& ranges,
-                               int N, int Na, int mode, int tile, const int32_t* counts, const int32_t* amap,
-                               hipStream_t stream);
-// Batching form with antenna flags: per subband, the compact index of every
-// unflagged antenna in antenna order (inv [B][Na], -1 when flagged), the
-// antenna of each compact index (amap [B][Na]), the flagged antennas
-// (flagged [B][Na]) and the counts [B][2] (active, flagged).
-hipError_t launch_plan_compact(const uint8_t* flags, int B, int Na, int32_t* inv, int32_t* amap, int32_t* flagged,
-                               int32_t* counts, hipStream_t stream);
-// V = 0 in every channel and W = 0 for every baseline of a flagged antenna
-hipError_t launch_plan_zero_flagged(const int32_t* flagged, const int32_t* counts, int B, int Na, void* vis,
-                                    int32_t* weights, hipStream_t stream);
+                               int N, int Na, int mode, int tile, hipStream_t stream);
 int xengine_list_grid(const XcdRanges& ranges);
 // Fill `bytes` (a multiple of 4) of device memory with hashed bytes that are
 // valid int8 samples and finite fp16 values (bit 6 of every byte clear).

@@ -72,14 +72,11 @@ constexpr int kChunk = 768;                  // spectra per workgroup, a multipl
 constexpr int kTT = 18;                      // tap pairs per branch and part (t = 0..17, cyclic)
 
 // One workgroup: receivers [i0, i0+16) of one subband, spectra [s_begin, s_end).
-// inv (or nullptr): compact index of each antenna, -1 for a flagged one;
-// receiver 2a + p is then stored at 2 inv[a] + p, and not at all when a is
-// flagged (the batching form compacts flagged antennas out of the X-engine).
 template <int DT, int kWaves>
 __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const float* __restrict__ taps,
                                          void* __restrict__ zs, const Tw64& tw, int N, int S, int Sb,
                                          int i0, int s_begin, int s_end, float gain, float2* lds,
-                                         unsigned* ltp, const int32_t* __restrict__ inv = nullptr) {
+                                         unsigned* ltp) {
     constexpr int kThreads = 64 * kWaves;
     constexpr int kGrp = 16 / kWaves;            // branch groups p1 per wave
     constexpr int kFftJobs = 16 / kWaves;        // 16-point FFT jobs per lane and phase
@@ -189,11 +186,6 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
     const int sl = lane & 7, ii = lane >> 3;
     const int ilf = rh * 8 + ii;
     const int rf = i0 + ilf;
-    int rs = rf;                                     // row of receiver rf in z (-1: not stored)
-    if (inv && rf < N) {
-        const int c = inv[rf >> 1];
-        rs = c < 0 ? -1 : 2 * c + (rf & 1);
-    }
 
     // Exact fp16 parts of the int16 (re, im) words wa, wb of two times
     // (x = 256 hb + lo): o = {re lo / 256, im lo / 256, re hb, im hb}, each
@@ -310,9 +302,9 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
             dft16(a);
             const int s = sg + 8 * bh + sl;
             const int blk = (sg >> 3) + bh;
-            if (rf < N && rs >= 0 && blk < Sb) {
+            if (rf < N && blk < Sb) {
                 const bool live = s < S;
-                const unsigned lane_zoff = (blk * N + rs) * kSBlk + sl;     // samples within a channel
+                const unsigned lane_zoff = (blk * N + rf) * kSBlk + sl;     // samples within a channel
                 const int64_t ch_stride = (int64_t)Sb * N * kSBlk;          // samples per channel
                 // spectra >= S are stored as zeros (int8: through a zero gain)
                 const float gq = live ? gain_u : 0.0f;
@@ -375,7 +367,7 @@ __global__ __launch_bounds__(64 * kWavesBatched) void ppf_batched_kernel(const i
                                                               const float* __restrict__ taps, void* __restrict__ z,
                                                               Tw64 tw, const PpfItem* __restrict__ items,
                                                               int N, int n_groups, int n_chunks, int total,
-                                                              int per_xcd, const int32_t* __restrict__ inv_all) {
+                                                              int per_xcd) {
     __shared__ float2 lds[kSpectraPerPhase * kSStride];
     __shared__ __attribute__((aligned(16))) unsigned ltp[2 * kP * kTT];
     // XCD-aware order as in ppf_kernel: neighbouring receiver groups (which
@@ -391,13 +383,12 @@ __global__ __launch_bounds__(64 * kWavesBatched) void ppf_batched_kernel(const i
     const int s_end = min(item.S, s_begin + kChunk);
     const int16_t* xs = x + item.x_off;
     void* zs = reinterpret_cast<char*>(z) + item.z_off;
-    const int32_t* inv = inv_all ? inv_all + (int64_t)it * (N / 2) : nullptr;
     if (item.dt == AFC_F32)
-        ppf_body<AFC_F32, kWavesBatched>(xs, taps, zs, tw, N, item.S, item.Sb, grp * kNi, s_begin, s_end, item.gain, lds, ltp, inv);
+        ppf_body<AFC_F32, kWavesBatched>(xs, taps, zs, tw, N, item.S, item.Sb, grp * kNi, s_begin, s_end, item.gain, lds, ltp);
     else if (item.dt == AFC_F16)
-        ppf_body<AFC_F16, kWavesBatched>(xs, taps, zs, tw, N, item.S, item.Sb, grp * kNi, s_begin, s_end, item.gain, lds, ltp, inv);
+        ppf_body<AFC_F16, kWavesBatched>(xs, taps, zs, tw, N, item.S, item.Sb, grp * kNi, s_begin, s_end, item.gain, lds, ltp);
     else
-        ppf_body<AFC_I8, kWavesBatched>(xs, taps, zs, tw, N, item.S, item.Sb, grp * kNi, s_begin, s_end, item.gain, lds, ltp, inv);
+        ppf_body<AFC_I8, kWavesBatched>(xs, taps, zs, tw, N, item.S, item.Sb, grp * kNi, s_begin, s_end, item.gain, lds, ltp);
 }
 
 }  // namespace
@@ -428,7 +419,7 @@ hipError_t launch_ppf(const PpfLaunch& a, hipStream_t stream) {
 }
 
 hipError_t launch_ppf_batched(const int16_t* x, const float* taps, void* z_ws, const PpfItem* items_dev,
-                              int n_items, int N, int max_S, const int32_t* inv, hipStream_t stream) {
+                              int n_items, int N, int max_S, hipStream_t stream) {
     static const Tw64 tw = make_twiddles();
     const int n_groups = (int)ceil_div(N, kNi);
     const int n_chunks = (int)ceil_div(max_S, kChunk);
@@ -438,7 +429,7 @@ hipError_t launch_ppf_batched(const int16_t* x, const float* taps, void* z_ws, c
     const int per_xcd = (int)ceil_div(total, 8);
     const dim3 grid((unsigned)(per_xcd * 8));
     hipLaunchKernelGGL(ppf_batched_kernel, grid, dim3(64 * kWavesBatched), 0, stream, x, taps, z_ws, tw, items_dev, N,
-                       n_groups, n_chunks, total, per_xcd, inv);
+                       n_groups, n_chunks, total, per_xcd);
     return hipGetLastError();
 }
 

@@ -244,18 +244,11 @@ struct JobIdle {       // 64-tile, the wave above the diagonal
 // the 128 x 256 tiles of the one-workgroup-per-CU kernel).  A stage buffer
 // holds A then B; a diagonal tile (ti == tj, TB == TILE) stages A only and
 // reads both operands from it.
-//
-// N receivers hold data (rows N and above read row N - 1 and are never
-// stored); Nz is the receiver stride of z (N, or more when the rows of
-// flagged antennas have been compacted away: then amap maps a compact
-// antenna index to the antenna's index in the visibility layout, and fl_sb
-// is not needed).
 template <int DT, int TILE, class J, int TB = TILE>
 __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __restrict__ vis_ch,
                                          int32_t* __restrict__ w_sb, const uint8_t* __restrict__ fl_sb,
                                          int N, int Na, int S, int ti, int tj, bool write_weights,
-                                         char* lds_raw, const int (&am)[4], const int (&bn)[2], int Nz = -1,
-                                         const int32_t* __restrict__ amap = nullptr) {
+                                         char* lds_raw, const int (&am)[4], const int (&bn)[2]) {
     using Tr = XT<DT>;
     using acc_t = typename Tr::acc_t;
     using V = std::conditional_t<DT == AFC_I8, v4i, v8h>;
@@ -387,8 +380,7 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
     // Offsets within the channel: voffset = this thread's chunk in stage 0,
     // soffset = the stage (a channel of samples is far below 2 GiB: the entry
     // points bound one subband of input to 2^31 values).
-    if (Nz < 0) Nz = N;
-    const int z_bytes = nb * Nz * RB;
+    const int z_bytes = nb * N * RB;
     // source offset of chunk c of a panel of `rows` receivers starting at r0
     auto chunk_src = [&](int c, int rows, int r0) {
         const int chunk = tid + c * kThreads;
@@ -396,20 +388,20 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
         const int rem = chunk % (rows * PLANES);
         const int row = rem / PLANES, sl = rem % PLANES;
         const int q = sl ^ swz<RB, PLANES>(row);
-        return (bl * Nz + min(r0 + row, N - 1)) * RB + q * 16;
+        return (bl * N + min(r0 + row, N - 1)) * RB + q * 16;
     };
     int src_a[CPT], src_b[CPT_B];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) src_a[c] = chunk_src(c, TILE, i0);
 #pragma unroll
     for (int c = 0; c < CPT_B; ++c) src_b[c] = chunk_src(c, TB, j0);
-    const int stage_bytes = kStg * Nz * RB;
+    const int stage_bytes = kStg * N * RB;
     auto issue_panel = [&](int st, char* panel, int c, int src, int rows) {
         char* dst = panel + (c * kThreads + wid * 64) * 16;
         int voff = src, soff = st * stage_bytes;
         if ((st + 1) * kStg > nb) {   // past the end (uniform): whole offset in voffset, block clamped to nb - 1
             const int bl = (tid + c * kThreads) / (rows * PLANES);
-            voff += (min(st * kStg + bl, nb - 1) - bl) * Nz * RB;
+            voff += (min(st * kStg + bl, nb - 1) - bl) * N * RB;
             soff = 0;
         }
         buffer_load_lds16(z, z_bytes, dst, voff, soff);
@@ -538,8 +530,7 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             const int Jc = j0 + bn[J::IB[p]] * 32 + lr;
-            const int bc = Jc >> 1;                          // column antenna (compact index)
-            const int b = amap && Jc < N ? amap[bc] : bc;     // ... in the visibility layout
+            const int b = Jc >> 1;
             const bool fb = fcol[J::IB[p]];
 #pragma unroll
             for (int r = 0; r < 16; r += 2) {
@@ -548,9 +539,8 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
                 const E yr = pair_swap(odd ? r0 : r1), yi = pair_swap(odd ? i0v : i1v);
                 E o0 = odd ? yr : r0, o1 = odd ? yi : i0v, o2 = odd ? r1 : yr, o3 = odd ? i1v : yi;
                 const int I = i0 + am[J::IA[p]] * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
-                const int ac = I >> 1;
-                if (Jc >= N || I >= N || ac < bc) continue;
-                const int a = amap ? amap[ac] : ac;          // monotone: a >= b as ac >= bc
+                const int a = I >> 1;
+                if (Jc >= N || I >= N || a < b) continue;
                 if (a == b) {             // inputs equal for (0, 0) and (1, 1)
                     if (odd) o3 = E(0);
                     else o1 = E(0);
@@ -575,7 +565,7 @@ template <int DT, int TILE>
 __device__ __forceinline__ void xtile_f32(const char* __restrict__ z, char* __restrict__ vis_ch,
                                       int32_t* __restrict__ w_sb, const uint8_t* __restrict__ fl_sb,
                                       int N, int Na, int S, int ti, int tj, bool write_weights,
-                                      char* lds_raw, int Nz = -1, const int32_t* __restrict__ amap = nullptr) {
+                                      char* lds_raw) {
     using Tr = XT<DT>;
     constexpr int RB = Tr::RB, PLANES = Tr::PLANES, kStg = stage_blocks<DT, TILE>();
     constexpr int WT = TILE / 2, MB = WT / 32;
@@ -586,7 +576,6 @@ __device__ __forceinline__ void xtile_f32(const char* __restrict__ z, char* __re
     static_assert(DT == AFC_F32, "fp32 only");
     using acc_t = typename Tr::acc_t;
 
-    if (Nz < 0) Nz = N;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr = wid >> 1, wc = wid & 1;
@@ -630,7 +619,7 @@ __device__ __forceinline__ void xtile_f32(const char* __restrict__ z, char* __re
                 const int row = rem / PLANES, q = rem % PLANES;
                 const int blk = min(st * kStg + bl, nb - 1);
                 const int rg = min(r0 + row, N - 1);
-                pre[slot][pn][c] = *reinterpret_cast<const uint4*>(z + ((int64_t)blk * Nz + rg) * RB + q * 16);
+                pre[slot][pn][c] = *reinterpret_cast<const uint4*>(z + ((int64_t)blk * N + rg) * RB + q * 16);
             }
         }
     };
@@ -791,16 +780,14 @@ __device__ __forceinline__ void xtile_f32(const char* __restrict__ z, char* __re
             if (diag && wr == wc && m < n) continue;
             const int J = j0 + wc * WT + n * 32 + lr;
             if (J >= N) continue;
-            const int bc = J >> 1, qq = J & 1;
-            const int b = amap ? amap[bc] : bc;
+            const int b = J >> 1, qq = J & 1;
             const bool fb = fcol[n];
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int I = i0 + wr * WT + m * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
                 if (I >= N) continue;
-                const int ac = I >> 1, p = I & 1;
-                if (ac < bc) continue;
-                const int a = amap ? amap[ac] : ac;
+                const int a = I >> 1, p = I & 1;
+                if (a < b) continue;
                 const bool flagged = fb || frow[m][((r >> 2) << 1) | ((r >> 1) & 1)];
                 const int64_t bl = (int64_t)a * (a + 1) / 2 + b;
                 const int64_t e = bl * 4 + p * 2 + qq;
@@ -819,15 +806,14 @@ __device__ __forceinline__ void xtile_f32(const char* __restrict__ z, char* __re
 template <int DT, int TILE>
 __device__ __forceinline__ void xtile(const char* __restrict__ z, char* __restrict__ vis_ch,
                                       int32_t* __restrict__ w_sb, const uint8_t* __restrict__ fl_sb,
-                                      int N, int Na, int S, int ti, int tj, bool write_weights, char* lds_raw,
-                                      int Nz = -1, const int32_t* __restrict__ amap = nullptr) {
+                                      int N, int Na, int S, int ti, int tj, bool write_weights, char* lds_raw) {
     if constexpr (DT == AFC_F32) {
-        xtile_f32<DT, TILE>(z, vis_ch, w_sb, fl_sb, N, Na, S, ti, tj, write_weights, lds_raw, Nz, amap);
+        xtile_f32<DT, TILE>(z, vis_ch, w_sb, fl_sb, N, Na, S, ti, tj, write_weights, lds_raw);
     } else {
         const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         auto run = [&](auto job, const int (&am)[4], const int (&bn)[2]) {
             xtile_mm<DT, TILE, decltype(job)>(z, vis_ch, w_sb, fl_sb, N, Na, S, ti, tj, write_weights, lds_raw,
-                                              am, bn, Nz, amap);
+                                              am, bn);
         };
         if constexpr (TILE == 128) {
             if (ti != tj) {
@@ -947,18 +933,11 @@ __global__ __launch_bounds__(kThreads, 1) void xengine_wide_kernel(XWideArgs a) 
 // round-robin over the 8 XCDs and the list holds each XCD's items (whole
 // channels, cost-balanced across XCDs) contiguously, so that the hardware
 // dispatcher keeps the tiles in flight on an XCD a window of few channels.
-//
-// With compaction (counts != nullptr) the channeliser has stored only the
-// receivers of unflagged antennas, in antenna order, at the front of each
-// subband's rows: subband b has 2 * counts[2 b] receivers with data, amap
-// [b][c] is the antenna of compact antenna c, and tiles wholly beyond the
-// data exit at once, so flagged baselines cost no MFMA work (their zeros
-// come from plan_zero_flagged_kernel).
 template <int MODE, int TILE, int WPC>
 __global__ __launch_bounds__(kThreads, WPC) void xengine_list_kernel(
     const char* __restrict__ z_ws, char* __restrict__ vis, int32_t* __restrict__ weights,
     const uint8_t* __restrict__ flags, const XSubband* __restrict__ sbs, const XWork* __restrict__ work,
-    XcdRanges r, int N, int Na, const int32_t* __restrict__ counts, const int32_t* __restrict__ amap) {
+    XcdRanges r, int N, int Na) {
     constexpr int kLds = MODE == 0 ? (lds_bytes<AFC_I8, TILE>() > lds_bytes<AFC_F16, TILE>() ? lds_bytes<AFC_I8, TILE>()
                                                                                             : lds_bytes<AFC_F16, TILE>())
                                    : lds_bytes<AFC_F32, TILE>();
@@ -970,22 +949,19 @@ __global__ __launch_bounds__(kThreads, WPC) void xengine_list_kernel(
     const XSubband sd = sbs[wk.sb];
     char* vis_ch = vis + sd.vis_off + (int64_t)wk.ch * nbl * 4 * 8;
     int32_t* wsb = weights ? weights + (int64_t)wk.sb * nbl : nullptr;
-    const uint8_t* fl = flags && !counts ? flags + (int64_t)wk.sb * Na : nullptr;
+    const uint8_t* fl = flags ? flags + (int64_t)wk.sb * Na : nullptr;
     const bool ww = wsb != nullptr && wk.ch == 0;
-    const int Nv = counts ? 2 * counts[2 * wk.sb] : N;        // receivers with data
-    if (wk.ti * TILE >= Nv) return;                            // uniform
-    const int32_t* am = counts ? amap + (int64_t)wk.sb * Na : nullptr;
     if constexpr (MODE == 0) {
         if (sd.dt == AFC_I8) {
             const char* z = z_ws + sd.z_off + (int64_t)wk.ch * sd.Sb * N * kSBlk * 2;
-            xtile<AFC_I8, TILE>(z, vis_ch, wsb, fl, Nv, Na, sd.S, wk.ti, wk.tj, ww, lds, N, am);
+            xtile<AFC_I8, TILE>(z, vis_ch, wsb, fl, N, Na, sd.S, wk.ti, wk.tj, ww, lds);
         } else {
             const char* z = z_ws + sd.z_off + (int64_t)wk.ch * sd.Sb * N * kSBlk * 4;
-            xtile<AFC_F16, TILE>(z, vis_ch, wsb, fl, Nv, Na, sd.S, wk.ti, wk.tj, ww, lds, N, am);
+            xtile<AFC_F16, TILE>(z, vis_ch, wsb, fl, N, Na, sd.S, wk.ti, wk.tj, ww, lds);
         }
     } else {
         const char* z = z_ws + sd.z_off + (int64_t)wk.ch * sd.Sb * N * kSBlk * 8;
-        xtile<AFC_F32, TILE>(z, vis_ch, wsb, fl, Nv, Na, sd.S, wk.ti, wk.tj, ww, lds, N, am);
+        xtile<AFC_F32, TILE>(z, vis_ch, wsb, fl, N, Na, sd.S, wk.ti, wk.tj, ww, lds);
     }
 }
 
@@ -1082,8 +1058,7 @@ int xengine_list_grid(const XcdRanges& r) {
 
 hipError_t launch_xengine_list(const void* z_ws, void* vis, int32_t* weights, const uint8_t* flags,
                                const XSubband* sbs_dev, const XWork* work_dev, const XcdRanges& ranges, int N,
-                               int Na, int mode, int tile, const int32_t* counts, const int32_t* amap,
-                               hipStream_t stream) {
+                               int Na, int mode, int tile, hipStream_t stream) {
     const char* z = reinterpret_cast<const char*>(z_ws);
     char* v = reinterpret_cast<char*>(vis);
     const int g = xengine_list_grid(ranges);
@@ -1091,13 +1066,13 @@ hipError_t launch_xengine_list(const void* z_ws, void* vis, int32_t* weights, co
     const dim3 grid((unsigned)g), block(kThreads);
     if (mode == 1)  // fp32 subbands
         hipLaunchKernelGGL((xengine_list_kernel<1, 64, 2>), grid, block, 0, stream, z, v, weights, flags, sbs_dev,
-                           work_dev, ranges, N, Na, counts, amap);
+                           work_dev, ranges, N, Na);
     else if (tile == 128)
         hipLaunchKernelGGL((xengine_list_kernel<0, 128, 2>), grid, block, 0, stream, z, v, weights, flags, sbs_dev,
-                           work_dev, ranges, N, Na, counts, amap);
+                           work_dev, ranges, N, Na);
     else
         hipLaunchKernelGGL((xengine_list_kernel<0, 64, 4>), grid, block, 0, stream, z, v, weights, flags, sbs_dev,
-                           work_dev, ranges, N, Na, counts, amap);
+                           work_dev, ranges, N, Na);
     return hipGetLastError();
 }
 
