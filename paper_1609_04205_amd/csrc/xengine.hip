@@ -16,9 +16,12 @@
 // one subband; 4 waves in 2 x 2, each owning (TILE/2)^2 outputs as 32 x 32
 // MFMA blocks.  Tiles wholly above the diagonal are never launched; inside a
 // diagonal tile the wave and the MFMA blocks above the diagonal are skipped.
-// Samples stream through LDS in stages of 2-4 spectrum blocks, double-buffered, copied with 16-byte coalesced loads of the block layout
-// [block][receiver][8 spectra] and stored with an XOR swizzle of the 16-byte
-// chunks so that the MFMA operand reads are bank-conflict free.
+// int8 / fp16: the row panel of a tile streams through LDS in stages of 2-4
+// spectrum blocks (direct global-to-LDS loads of the block layout
+// [block][receiver][8 spectra], XOR-swizzled 16-byte chunks so that the MFMA
+// operand reads are bank-conflict free); off the diagonal each wave loads
+// its own column block straight into registers.  fp32 stages both panels
+// through registers into LDS.
 //
 // Sample types (gfx950 MFMA):
 //   int8  v_mfma_i32_32x32x32_i8  (16 spectra per K-step), exact int32 sums
@@ -28,6 +31,7 @@
 //         keep the rounding error of 3051-term sums near 1e-7 relative
 #include <algorithm>
 #include <type_traits>
+#include <utility>
 
 #include "afc_internal.h"
 
@@ -75,16 +79,26 @@ constexpr int prefetch_depth() { return 2; }
 template <int DT>
 constexpr bool uses_dma() { return DT != AFC_F32; }
 #ifndef AFC_DMA_DEPTH
-#define AFC_DMA_DEPTH 2
+#define AFC_DMA_DEPTH 3
 #endif
 constexpr int kDmaDepth = AFC_DMA_DEPTH;      // stages of global-to-LDS loads in flight
+#ifndef AFC_XENGINE_BDIRECT
+#define AFC_XENGINE_BDIRECT 1
+#endif
+// off-diagonal square tiles load their B operands into registers (1) or
+// stage them through LDS with the A panel (0)
+constexpr bool kBDirect = AFC_XENGINE_BDIRECT != 0;
 // DMA ring: the stage being multiplied, the next one (already landed when
 // its first operands are read) and kDmaDepth - 1 further stages in flight,
 // plus the buffer being refilled
 constexpr int kDmaBuffers = kDmaDepth + 2;
 template <int DT, int TILE>
 constexpr int lds_bytes() {
-    return (uses_dma<DT>() ? kDmaBuffers : 2) * 2 * stage_blocks<DT, TILE>() * TILE * XT<DT>::RB;
+    // 128-wide int8 / fp16 tiles stage only the row panel (their column
+    // operands are loaded into registers, or, on the diagonal, are the row
+    // panel); the others stage both
+    constexpr int panels = uses_dma<DT>() && TILE == 128 && kBDirect ? 1 : 2;
+    return (uses_dma<DT>() ? kDmaBuffers : 2) * panels * stage_blocks<DT, TILE>() * TILE * XT<DT>::RB;
 }
 // the one-workgroup-per-CU kernel: 128-row A panel and 256-row B panel per stage
 template <int DT>
@@ -106,6 +120,29 @@ __device__ __forceinline__ void buffer_load_lds16(const char* base, int bytes, c
     const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, bytes, 0x00020000);
     __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)dst, 16, voff, soff, 0, 0);
 #endif
+}
+
+// 16 bytes from base + voff + soff (a raw buffer of `bytes` bytes) into
+// registers.  A buffer load, unlike a flat one, cannot touch LDS, so the
+// compiler's LDS wait counts stay exact around it.
+__device__ __forceinline__ uint4 buffer_load16(const char* base, int bytes, int voff, int soff) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, bytes, 0x00020000);
+    const v4i v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    return make_uint4((unsigned)v.x, (unsigned)v.y, (unsigned)v.z, (unsigned)v.w);
+#else
+    return make_uint4(0u, 0u, 0u, 0u);
+#endif
+}
+
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+// f(integral_constant<int, 0>) ... f(integral_constant<int, N - 1>)
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
 // s_waitcnt vmcnt(N) with the other counters left at their maximum
@@ -264,7 +301,20 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
     static_assert(NKK % 2 == 0, "k-steps per stage must be even");
     constexpr int NA = J::NA, NBO = J::NB, NP = J::NP;
     constexpr int NB = kDmaBuffers;
-    constexpr int BUF = PANEL + PANEL_B;                     // bytes of one stage buffer
+    // a stage buffer holds panel A and, where it is staged, panel B (not for
+    // the diagonal jobs, whose operands all come from panel A, nor for the
+    // direct-B form)
+    constexpr bool kDiagJob = std::is_same_v<J, JobDiag0> || std::is_same_v<J, JobDiag1> ||
+                              std::is_same_v<J, JobDiag2> || std::is_same_v<J, JobDiag3>;
+    // Off-diagonal square tiles take their B operands straight from global
+    // memory into registers: wave w alone uses column block w, so staging it
+    // through LDS bought no sharing and cost an LDS write and read per byte.
+    // The loads of a stage go out with that stage's A panel and land in a
+    // ring of RS register slots (the stage in use and kDmaDepth in flight).
+    constexpr bool BD = kBDirect && std::is_same_v<J, JobRows4> && TB == TILE;
+    constexpr int RS = BD ? kDmaDepth + 1 : 1;
+    static_assert(RS <= 4, "register ring of at most four stages");
+    constexpr int BUF = PANEL + (BD || kDiagJob ? 0 : PANEL_B);   // bytes of one stage buffer
 
     const int tid = threadIdx.x, lane = tid & 63, lr = lane & 31, lh = lane >> 5;
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -272,7 +322,10 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
     const bool diag = ti == tj;
     const int nb = (S + kSBlk - 1) / kSBlk;
     const int tail_valid = S - (nb - 1) * kSBlk;             // spectra in the last block
-    const int n_st = (nb + kStg - 1) / kStg;
+    // stages, rounded up to a multiple of the register ring (the extra
+    // stages read the last block again and are masked to zero)
+    const int n_st = (nb + kStg * RS - 1) / (kStg * RS) * RS;
+    const int n_final = n_st - RS;                           // first stage of the final group
 
     acc_t accR[NP > 0 ? NP : 1], accI[NP > 0 ? NP : 1];
 #pragma unroll
@@ -289,13 +342,20 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
     // wait counts stay exact across branches); a diagonal tile's B operands
     // come from panel A
     const int rows_b = diag ? TILE : TB;
-    auto load_ops = [&](const char* PA, const char* PB, int kk, uint4 (&oa)[NA], uint4 (&ob)[NBO]) {
+    // B operands loaded directly: [ring slot][k-step of the stage]
+    uint4 bdir[RS][BD ? NKK : 1];
+    auto load_ops = [&](auto slot_tag, const char* PA, const char* PB, int kk, uint4 (&oa)[NA], uint4 (&ob)[NBO]) {
+        constexpr int slot = decltype(slot_tag)::value;
         const int bl = DT == AFC_I8 ? 2 * kk + lh : kk;
         const int q = DT == AFC_I8 ? 0 : lh;
 #pragma unroll
         for (int i = 0; i < NA; ++i) oa[i] = rd(PA, TILE, bl, am[i] * 32 + lr, q);
+        if constexpr (BD) {
+            ob[0] = bdir[slot][kk];
+        } else {
 #pragma unroll
-        for (int i = 0; i < NBO; ++i) ob[i] = rd(PB, rows_b, bl, bn[i] * 32 + lr, q);
+            for (int i = 0; i < NBO; ++i) ob[i] = rd(PB, rows_b, bl, bn[i] * 32 + lr, q);
+        }
     };
     auto cvt = [](uint4 u) -> V {
         if constexpr (DT == AFC_I8) return v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
@@ -398,19 +458,37 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
     const int stage_bytes = kStg * N * RB;
     auto issue_panel = [&](int st, char* panel, int c, int src, int rows) {
         char* dst = panel + (c * kThreads + wid * 64) * 16;
+        const int bl = (tid + c * kThreads) / (rows * PLANES);
+        if constexpr (BD) {           // branch-free: block clamped to nb - 1 in voffset
+            buffer_load_lds16(z, z_bytes, dst, src + (min(st * kStg + bl, nb - 1) - bl) * N * RB, 0);
+            return;
+        }
         int voff = src, soff = st * stage_bytes;
         if ((st + 1) * kStg > nb) {   // past the end (uniform): whole offset in voffset, block clamped to nb - 1
-            const int bl = (tid + c * kThreads) / (rows * PLANES);
             voff += (min(st * kStg + bl, nb - 1) - bl) * N * RB;
             soff = 0;
         }
         buffer_load_lds16(z, z_bytes, dst, voff, soff);
     };
-    auto issue = [&](int st) {
+    // this lane's B row and, per k-step of a stage, its block and chunk
+    const int b_row = min(j0 + bn[0] * 32 + lr, N - 1);
+    auto issue = [&](auto slot_tag, int st) {
+        constexpr int slot = decltype(slot_tag)::value;
         char* buf = lds_raw + (st % NB) * BUF;
 #pragma unroll
         for (int c = 0; c < CPT; ++c) issue_panel(st, buf, c, src_a[c], TILE);
-        if (!diag) {
+        if constexpr (BD) {
+            // no branch around these loads (the compiler's wait counts for
+            // their registers stay exact): the block index is clamped to
+            // nb - 1 arithmetically
+#pragma unroll
+            for (int kk = 0; kk < NKK; ++kk) {
+                const int lbl = DT == AFC_I8 ? 2 * kk + lh : kk;
+                const int q = DT == AFC_I8 ? 0 : lh;
+                const int blk = min(st * kStg + lbl, nb - 1);
+                bdir[slot][kk] = buffer_load16(z, z_bytes, (blk * N + b_row) * RB + q * 16, 0);
+            }
+        } else if (!diag) {
 #pragma unroll
             for (int c = 0; c < CPT_B; ++c) issue_panel(st, buf + PANEL, c, src_b[c], TB);
         }
@@ -421,6 +499,10 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
         const int later = min(n_st - 1 - s, kDmaDepth - 1);
         if (diag) wait_vmcnt_runtime<CPT>(later);
         else wait_vmcnt_runtime<CPT + CPT_B>(later);
+    };
+    // the same for the direct-B form, where `later` is known at compile time
+    auto wait_landed_bd = [&](auto later_tag) {
+        wait_vmcnt<(CPT + NKK) * decltype(later_tag)::value>();
     };
     auto panels = [&](int st, const char*& PA, const char*& PB) {
         const char* buf = lds_raw + (st % NB) * BUF;
@@ -440,33 +522,49 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
             j[i] = jsw(b[i]);
         }
     };
-    auto run_stage = [&](int st, auto has_next_tag) {
+    // stage st (using register slot R of the direct B ring); the stages of
+    // the final group mask the operands of blocks at or past the partial one
+    auto run_stage = [&](auto r_tag, int st, auto has_next_tag, auto mask_tag) {
+        constexpr int R = decltype(r_tag)::value;
+        constexpr int RN = (R + 1) % RS;                     // slot of stage st + 1
         constexpr bool kNext = decltype(has_next_tag)::value;
+        constexpr bool kMask = decltype(mask_tag)::value;
         const char *PA, *PB;
         panels(st, PA, PB);
 #pragma unroll
         for (int kk = 0; kk + 1 < NKK; ++kk) {
             mma(oa[kk & 1], bv[kk & 1], bj[kk & 1],
-                [&] { load_ops(PA, PB, kk + 1, oa[(kk + 1) & 1], ob[(kk + 1) & 1]); },
+                [&] { load_ops(r_tag, PA, PB, kk + 1, oa[(kk + 1) & 1], ob[(kk + 1) & 1]); },
                 [&] {
-                    if constexpr (!kNext) mask_tail_ops(st, kk + 1, oa[(kk + 1) & 1], ob[(kk + 1) & 1]);
+                    if constexpr (kMask) mask_tail_ops(st, kk + 1, oa[(kk + 1) & 1], ob[(kk + 1) & 1]);
                     prep(ob[(kk + 1) & 1], bv[(kk + 1) & 1], bj[(kk + 1) & 1]);
                 });
         }
         mma(oa[(NKK - 1) & 1], bv[(NKK - 1) & 1], bj[(NKK - 1) & 1],
             [&] {
                 if constexpr (kNext) {
-                    wait_landed(st + 1);
-                    dma_barrier();
-                    if (st + 1 + kDmaDepth < n_st) issue(st + 1 + kDmaDepth);
+                    if constexpr (BD) {
+                        // stages issued after st + 1: kDmaDepth - 1 before
+                        // the final group, RS - 2 - R inside it
+                        wait_landed_bd(std::integral_constant<int, kMask ? RS - 2 - R : kDmaDepth - 1>{});
+                        dma_barrier();
+                        // stage st + 1 + kDmaDepth reuses this stage's slot
+                        // R; it exists exactly for the stages before the
+                        // final group
+                        if constexpr (!kMask) issue(r_tag, st + 1 + kDmaDepth);
+                    } else {
+                        wait_landed(st + 1);
+                        dma_barrier();
+                        if (st + 1 + kDmaDepth < n_st) issue(r_tag, st + 1 + kDmaDepth);
+                    }
                     const char *NA_, *NB_;
                     panels(st + 1, NA_, NB_);
-                    load_ops(NA_, NB_, 0, oa[0], ob[0]);
+                    load_ops(std::integral_constant<int, RN>{}, NA_, NB_, 0, oa[0], ob[0]);
                 }
             },
             [&] {
                 if constexpr (kNext) {
-                    if (st + 2 == n_st) mask_tail_ops(st + 1, 0, oa[0], ob[0]);
+                    if (st + 1 >= n_final) mask_tail_ops(st + 1, 0, oa[0], ob[0]);
                     prep(ob[0], bv[0], bj[0]);
                 }
             });
@@ -474,21 +572,28 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
     // scalar loads still in flight would turn every LDS wait in the loop
     // into lgkmcnt(0): settle them here
     __builtin_amdgcn_s_waitcnt(0xC07F);
-#pragma unroll
-    for (int d = 0; d < kDmaDepth; ++d)
-        if (d < n_st) issue(d);
-    wait_landed(0);
+    static_for<kDmaDepth>([&](auto d) {
+        // (the direct-B form always has at least RS stages)
+        if (BD || d < n_st) issue(std::integral_constant<int, decltype(d)::value % RS>{}, d);
+    });
+    if constexpr (BD) wait_landed_bd(std::integral_constant<int, kDmaDepth - 1>{});
+    else wait_landed(0);
     dma_barrier();
-    if (kDmaDepth < n_st) issue(kDmaDepth);
+    if (BD || kDmaDepth < n_st) issue(std::integral_constant<int, kDmaDepth % RS>{}, kDmaDepth);
     {
         const char *PA, *PB;
         panels(0, PA, PB);
-        load_ops(PA, PB, 0, oa[0], ob[0]);
-        if (n_st == 1) mask_tail_ops(0, 0, oa[0], ob[0]);
+        load_ops(std::integral_constant<int, 0>{}, PA, PB, 0, oa[0], ob[0]);
+        if (n_final == 0) mask_tail_ops(0, 0, oa[0], ob[0]);
         prep(ob[0], bv[0], bj[0]);
     }
-    for (int st = 0; st + 1 < n_st; ++st) run_stage(st, std::true_type{});
-    run_stage(n_st - 1, std::false_type{});
+    // the stage loop is unrolled by the ring size so that every slot index
+    // is a constant; the final RS stages are peeled off
+    for (int st = 0; st < n_final; st += RS)
+        static_for<RS>([&](auto r) { run_stage(r, st + r, std::true_type{}, std::false_type{}); });
+    static_for<RS>([&](auto r) {
+        run_stage(r, n_final + r, std::integral_constant<bool, (decltype(r)::value + 1 < RS)>{}, std::true_type{});
+    });
     lds_barrier();
 
     // ---- epilogue: 2x2 polarisation blocks of antennas a >= b
