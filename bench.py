@@ -255,6 +255,21 @@ def main():
             f"normalise {ms_v['normalise']:.3f} ms")
         del pkt, bits, visn
 
+        # ---- the same int8 X-engine launch on all-zero samples: the cycles
+        # are the same, the shader clock is not (the MFMAs draw less power
+        # on constant operand data), so this is the kernel at a clock the
+        # chip sustains only for such data
+        z8.zero_()
+        tzr = Timer(torch)
+        for it in range(3):
+            e = tzr.rec("xengine") if it > 0 else None
+            afc.correlate(z8, n_spectra=S, out=vis, weights=wts)
+            if e is not None:
+                e.record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        out["xengine_int8_zero_samples_ms"] = round(tzr.ms("xengine"), 3)
+        log(f"int8 xengine on zero samples {tzr.ms('xengine'):.3f} ms")
+
         # ---- fp32 path on the same input: int8 vs fp32
         del z8
         z32 = torch.empty(afc.channelised_shape(B, S, N), dtype=torch.float32, device=dev)

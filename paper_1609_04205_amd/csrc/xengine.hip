@@ -100,11 +100,6 @@ constexpr int lds_bytes() {
     constexpr int panels = uses_dma<DT>() && TILE == 128 && kBDirect ? 1 : 2;
     return (uses_dma<DT>() ? kDmaBuffers : 2) * panels * stage_blocks<DT, TILE>() * TILE * XT<DT>::RB;
 }
-// the one-workgroup-per-CU kernel: 128-row A panel and 256-row B panel per stage
-template <int DT>
-constexpr int wide_lds_bytes() {
-    return kDmaBuffers * 3 * stage_blocks<DT, 128>() * 128 * XT<DT>::RB;
-}
 
 // Workgroup barrier for the DMA pipeline: no memory fence (which would wait
 // for every outstanding global-to-LDS load); a compiler-level memory clobber
@@ -234,10 +229,6 @@ __device__ __forceinline__ void tile_rc(int t, int& ti, int& tj) {
 // Work of one wave in an int8 / fp16 tile: NP blocks of 32 x 32 outputs,
 // block p pairing row block am[IA[p]] of panel A with column block
 // bn[IB[p]] of panel B (am, bn hold NA and NB block indices).
-struct JobRows4x2 {    // off-diagonal 128 x 256 tile: every row block x this wave's two column blocks
-    static constexpr int NA = 4, NB = 2, NP = 8;
-    static constexpr int IA[8] = {0, 1, 2, 3, 0, 1, 2, 3}, IB[8] = {0, 0, 0, 0, 1, 1, 1, 1};
-};
 struct JobRows4 {      // off-diagonal 128-tile: every row block x this wave's column block
     static constexpr int NA = 4, NB = 1, NP = 4;
     static constexpr int IA[8] = {0, 1, 2, 3}, IB[8] = {0, 0, 0, 0};
@@ -277,11 +268,9 @@ struct JobIdle {       // 64-tile, the wave above the diagonal
 // of subband sb.
 //
 // The row panel A is TILE receivers tall (rows ti*TILE ..), the column panel B
-// TB receivers (columns tj*TILE ..; TB = TILE for square tiles, 2*TILE for
-// the 128 x 256 tiles of the one-workgroup-per-CU kernel).  A stage buffer
-// holds A then B; a diagonal tile (ti == tj, TB == TILE) stages A only and
-// reads both operands from it.
-template <int DT, int TILE, class J, int TB = TILE>
+// as wide (columns tj*TILE ..).  A stage buffer holds A then B; a diagonal
+// tile (ti == tj) stages A only and reads both operands from it.
+template <int DT, int TILE, class J>
 __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __restrict__ vis_ch,
                                          int32_t* __restrict__ w_sb, const uint8_t* __restrict__ fl_sb,
                                          int N, int Na, int S, int ti, int tj, bool write_weights,
@@ -291,11 +280,10 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
     using V = std::conditional_t<DT == AFC_I8, v4i, v8h>;
     constexpr int RB = Tr::RB, PLANES = Tr::PLANES, kStg = stage_blocks<DT, TILE>();
     constexpr int PANEL = kStg * TILE * RB;                  // bytes of panel A in one stage
-    constexpr int PANEL_B = kStg * TB * RB;                  // bytes of panel B in one stage
+    constexpr int PANEL_B = PANEL;                           // bytes of panel B in one stage
     constexpr int CPT = kStg * TILE * PLANES / kThreads;     // 16-byte chunks of A per thread per stage
-    constexpr int CPT_B = kStg * TB * PLANES / kThreads;     // of B
+    constexpr int CPT_B = CPT;                               // of B
     static_assert((kStg * TILE * PLANES) % kThreads == 0, "a stage must split evenly over the threads");
-    static_assert(TB == TILE || TB == 2 * TILE, "column panel of one or two tile widths");
     // k-steps per stage (int8: 16 spectra, fp16: 8 spectra each)
     constexpr int NKK = DT == AFC_I8 ? kStg / 2 : kStg;
     static_assert(NKK % 2 == 0, "k-steps per stage must be even");
@@ -311,7 +299,7 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
     // through LDS bought no sharing and cost an LDS write and read per byte.
     // The loads of a stage go out with that stage's A panel and land in a
     // ring of RS register slots (the stage in use and kDmaDepth in flight).
-    constexpr bool BD = kBDirect && std::is_same_v<J, JobRows4> && TB == TILE;
+    constexpr bool BD = kBDirect && std::is_same_v<J, JobRows4>;
     constexpr int RS = BD ? kDmaDepth + 1 : 1;
     static_assert(RS <= 4, "register ring of at most four stages");
     constexpr int BUF = PANEL + (BD || kDiagJob ? 0 : PANEL_B);   // bytes of one stage buffer
@@ -341,7 +329,6 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
     // this wave's operands of k-step kk (unconditional, so that the LDS
     // wait counts stay exact across branches); a diagonal tile's B operands
     // come from panel A
-    const int rows_b = diag ? TILE : TB;
     // B operands loaded directly: [ring slot][k-step of the stage]
     uint4 bdir[RS][BD ? NKK : 1];
     auto load_ops = [&](auto slot_tag, const char* PA, const char* PB, int kk, uint4 (&oa)[NA], uint4 (&ob)[NBO]) {
@@ -354,7 +341,7 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
             ob[0] = bdir[slot][kk];
         } else {
 #pragma unroll
-            for (int i = 0; i < NBO; ++i) ob[i] = rd(PB, rows_b, bl, bn[i] * 32 + lr, q);
+            for (int i = 0; i < NBO; ++i) ob[i] = rd(PB, TILE, bl, bn[i] * 32 + lr, q);
         }
     };
     auto cvt = [](uint4 u) -> V {
@@ -454,7 +441,7 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
 #pragma unroll
     for (int c = 0; c < CPT; ++c) src_a[c] = chunk_src(c, TILE, i0);
 #pragma unroll
-    for (int c = 0; c < CPT_B; ++c) src_b[c] = chunk_src(c, TB, j0);
+    for (int c = 0; c < CPT_B; ++c) src_b[c] = chunk_src(c, TILE, j0);
     const int stage_bytes = kStg * N * RB;
     auto issue_panel = [&](int st, char* panel, int c, int src, int rows) {
         char* dst = panel + (c * kThreads + wid * 64) * 16;
@@ -490,7 +477,7 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
             }
         } else if (!diag) {
 #pragma unroll
-            for (int c = 0; c < CPT_B; ++c) issue_panel(st, buf + PANEL, c, src_b[c], TB);
+            for (int c = 0; c < CPT_B; ++c) issue_panel(st, buf + PANEL, c, src_b[c], TILE);
         }
     };
     // wait until this wave's loads of stage s have landed, given that the
@@ -968,69 +955,6 @@ __global__ __launch_bounds__(kThreads, 2) void xengine_kernel(XArgs a) {
     xtile<DT, TILE>(z, vis, wsb, fl, a.N, a.Na, a.S[sb], ti, tj, wsb != nullptr && ch == 0, lds);
 }
 
-// One-workgroup-per-CU X-engine (int8 / fp16).  With one wave per SIMD a
-// wave may hold 256 accumulator registers, so an off-diagonal wave owns a
-// 4 x 2 job of 32 x 32 blocks (128 rows x 64 columns): per k-step it reads
-// 4 A and 2 B operands from LDS for 16 MFMAs, against 5 for 8 in the
-// two-workgroups-per-CU form, and each staged byte of the 128 x 256 tile
-// feeds a third more MACs.  Per channel the row tiles ti (128 receivers) are
-// covered by: ti / 2 tiles of 128 x 256 (column tiles 2k, 2k + 1), one
-// 128 x 128 tile (column tile ti - 1) when ti is odd, and the diagonal
-// 128 x 128 tile (ten lower-triangle blocks spread 3/3/2/2 over the waves).
-// Items are ordered long first: all 128 x 256 tiles of a channel, then the
-// 128 x 128 ones, then the diagonal ones.
-struct XWideArgs {
-    const char* z;              // subband 0, channel 0
-    char* vis;
-    int32_t* weights;
-    const uint8_t* flags;
-    int64_t z_ch_bytes;         // bytes between channels
-    int64_t z_sb_bytes;         // bytes between subbands
-    int N, Na, P;
-    int n_pairs, n_singles, n_items;    // items per channel
-    int total, per_xcd;
-    int S[AFC_MAX_SUBBANDS];
-};
-
-template <int DT>
-__global__ __launch_bounds__(kThreads, 1) void xengine_wide_kernel(XWideArgs a) {
-    __shared__ __attribute__((aligned(16))) char lds[wide_lds_bytes<DT>()];
-    const int bid = blockIdx.x;
-    const int w = (bid & 7) * a.per_xcd + (bid >> 3);       // XCD-contiguous ranges of items
-    if (w >= a.total) return;
-    int t = w % a.n_items;
-    const int rest = w / a.n_items;
-    const int ch = rest % a.P;
-    const int sb = rest / a.P;
-    const char* z = a.z + sb * a.z_sb_bytes + ch * a.z_ch_bytes;
-    const int64_t nbl = (int64_t)a.Na * (a.Na + 1) / 2;
-    char* vis = a.vis + ((int64_t)sb * a.P + ch) * nbl * 4 * 8;
-    int32_t* wsb = a.weights ? a.weights + (int64_t)sb * nbl : nullptr;
-    const uint8_t* fl = a.flags ? a.flags + (int64_t)sb * a.Na : nullptr;
-    const bool ww = wsb != nullptr && ch == 0;
-    const int S = a.S[sb];
-    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (t < a.n_pairs) {                   // 128 x 256: row tile ti holds ti / 2 of them
-        int ti = 2;
-        for (; t >= (ti >> 1); ++ti) t -= ti >> 1;
-        const int am[4] = {0, 1, 2, 3}, bn[2] = {2 * wid, 2 * wid + 1};
-        xtile_mm<DT, 128, JobRows4x2, 256>(z, vis, wsb, fl, a.N, a.Na, S, ti, 2 * t, ww, lds, am, bn);
-        return;
-    }
-    t -= a.n_pairs;
-    if (t < a.n_singles) {                 // 128 x 128 left over in an odd row tile
-        const int ti = 2 * t + 1;
-        const int am[4] = {0, 1, 2, 3}, bn[2] = {wid, 0};
-        xtile_mm<DT, 128, JobRows4>(z, vis, wsb, fl, a.N, a.Na, S, ti, ti - 1, ww, lds, am, bn);
-        return;
-    }
-    const int ti = t - a.n_singles;        // diagonal
-    if (wid == 0) xtile_mm<DT, 128, JobDiag0>(z, vis, wsb, fl, a.N, a.Na, S, ti, ti, ww, lds, JobDiag0::AM, JobDiag0::BN);
-    else if (wid == 1) xtile_mm<DT, 128, JobDiag1>(z, vis, wsb, fl, a.N, a.Na, S, ti, ti, ww, lds, JobDiag1::AM, JobDiag1::BN);
-    else if (wid == 2) xtile_mm<DT, 128, JobDiag2>(z, vis, wsb, fl, a.N, a.Na, S, ti, ti, ww, lds, JobDiag2::AM, JobDiag2::BN);
-    else xtile_mm<DT, 128, JobDiag3>(z, vis, wsb, fl, a.N, a.Na, S, ti, ti, ww, lds, JobDiag3::AM, JobDiag3::BN);
-}
-
 // Batched form: one workgroup per work item of a host-built list; each item
 // is one tile of one channel of one subband with its own sample type and
 // integration length.  MODE 0 serves int8 and fp16 subbands (mixed in one
@@ -1119,34 +1043,6 @@ hipError_t launch_xengine(const XLaunch& l, hipStream_t stream) {
     a.per_xcd = (int)ceil_div(total, 8);
     for (int b = 0; b < l.B; ++b) a.S[b] = l.S_host[b];
     const dim3 grid((unsigned)(a.per_xcd * 8));
-#ifdef AFC_XENGINE_WIDE
-    if (l.dt != AFC_F32) {
-        XWideArgs w{};
-        w.z = a.z;
-        w.vis = a.vis;
-        w.weights = a.weights;
-        w.flags = a.flags;
-        w.z_ch_bytes = a.z_ch_bytes;
-        w.z_sb_bytes = a.z_sb_bytes;
-        w.N = a.N;
-        w.Na = a.Na;
-        w.P = kP;
-        const int T = (int)ceil_div(l.N, 128);
-        w.n_pairs = 0;
-        for (int ti = 0; ti < T; ++ti) w.n_pairs += ti / 2;
-        w.n_singles = T / 2;
-        w.n_items = w.n_pairs + w.n_singles + T;
-        const int64_t wt = (int64_t)w.n_items * kP * l.B;
-        if (wt > (1LL << 30)) return hipErrorInvalidValue;
-        w.total = (int)wt;
-        w.per_xcd = (int)ceil_div(wt, 8);
-        for (int b = 0; b < l.B; ++b) w.S[b] = l.S_host[b];
-        const dim3 wg((unsigned)(w.per_xcd * 8));
-        if (l.dt == AFC_I8) hipLaunchKernelGGL((xengine_wide_kernel<AFC_I8>), wg, dim3(kThreads), 0, stream, w);
-        else hipLaunchKernelGGL((xengine_wide_kernel<AFC_F16>), wg, dim3(kThreads), 0, stream, w);
-        return hipGetLastError();
-    }
-#endif
     switch (l.dt) {
         case AFC_I8: hipLaunchKernelGGL((xengine_kernel<AFC_I8, 128>), grid, dim3(kThreads), 0, stream, a); break;
         case AFC_F16: hipLaunchKernelGGL((xengine_kernel<AFC_F16, 128>), grid, dim3(kThreads), 0, stream, a); break;
