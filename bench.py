@@ -448,17 +448,27 @@ def main():
         # ---- calibration adjoint, 576 antennas x 64 channels
         Vc, Mc, gc = W.make_calibration(Na=576, P=64, seed=5)
         Vt, Mt, gt = (torch.from_numpy(a).to(dev) for a in (Vc, Mc, gc))
-        afc.calibrate_grad(Vt, Mt, gt)
+        wcal = torch.empty(afc._lib.afc_calibrate_workspace_bytes(576, 64), dtype=torch.uint8, device=dev)
+        afc.calibrate_grad(Vt, Mt, gt, workspace=wcal)
         torch.cuda.synchronize()
+        # 20 calls back to back between one pair of events (a call is ~0.16
+        # ms of GPU work, so host launch gaps would otherwise be timed too)
+        n_cal = 20
         tc = Timer(torch)
-        for _ in range(5):
-            e = tc.rec("cal")
-            afc.calibrate_grad(Vt, Mt, gt)
-            e.record(torch.cuda.current_stream())
+        e = tc.rec("cal")
+        for _ in range(n_cal):
+            afc.calibrate_grad(Vt, Mt, gt, workspace=wcal)
+        e.record(torch.cuda.current_stream())
         torch.cuda.synchronize()
-        cal_ms = tc.ms("cal")
-        cal_bytes = 2.0 * 64 * nbl * 2 * 8          # XX and YY of V and M
-        out["calibration"] = {"ms": round(cal_ms, 4), "algorithmic_gbs": round(cal_bytes / (cal_ms * 1e-3) / 1e9, 1)}
+        cal_ms = tc.ms("cal") / n_cal
+        # V and M arrive in the correlator's [P][Nbl][2][2] layout: the
+        # algorithmic bytes are both arrays (32 B per baseline each; the
+        # hardware reads whole records), of which XX and YY are half
+        cal_bytes = 2.0 * 64 * nbl * 4 * 8
+        out["calibration"] = {"ms": round(cal_ms, 4), "algorithmic_gbs": round(cal_bytes / (cal_ms * 1e-3) / 1e9, 1),
+                              "hbm_frac": round(cal_bytes / (cal_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                              "xx_yy_gbs": round(cal_bytes / 2 / (cal_ms * 1e-3) / 1e9, 1)}
+        del wcal
         log(f"calibration {cal_ms:.3f} ms")
         # ---- gain solver (30 iterations from unit gains) and sigma-clip flagging
         n_it = 30

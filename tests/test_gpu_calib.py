@@ -103,3 +103,25 @@ def test_autograd_matches_torch(afc, dev):
     got = gc.grad.cpu().numpy()
     rel = np.linalg.norm(got - ref_grad) / np.linalg.norm(ref_grad)
     assert rel <= 1e-6
+
+
+def test_grad_unaligned_records_match_aligned(afc, dev):
+    """V and M at an 8-byte (not 16-byte) offset take the 8-byte-load path;
+    it gives bit-identical loss and gradient to the 16-byte record path, and
+    both pass the oracle check."""
+    V, M, g = W.make_calibration(Na=70, P=3, seed=21)
+    Vt, Mt, gt = (torch.from_numpy(a).to(dev) for a in (V, M, g))
+
+    def shifted(t):
+        buf = torch.empty(t.numel() + 2, dtype=t.dtype, device=dev)
+        u = buf[2:].view(t.shape)
+        u.copy_(t)
+        assert u.data_ptr() % 16 == 8
+        return u
+
+    la, ga = afc.calibrate_grad(Vt, Mt, gt)
+    lu, gu = afc.calibrate_grad(shifted(Vt), shifted(Mt), gt)
+    torch.cuda.synchronize()
+    assert Vt.data_ptr() % 16 == 0 and Mt.data_ptr() % 16 == 0
+    assert torch.equal(la, lu) and torch.equal(ga, gu)
+    _check(afc, dev, V, M, g)
