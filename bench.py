@@ -210,12 +210,14 @@ def main():
     out["roofline"] = xe_roof if xe_ms >= ppf_ms else ppf_roof
     out["roofline_other"] = ppf_roof if xe_ms >= ppf_ms else xe_roof
     # complex MACs the int8 X-engine actually issues on MFMA: whole 128 x 128
-    # off-diagonal tiles, ten 32 x 32 blocks per diagonal tile, spectra padded
-    # to whole stages of 4 blocks of 8
+    # off-diagonal tiles, ten 32 x 32 blocks per diagonal tile; spectra padded
+    # to whole stages of 4 blocks of 8, and off the diagonal the stage count
+    # to a multiple of the 4-stage register ring
     T = -(-N // 128)
-    pairs_computed = T * (T - 1) // 2 * 128 * 128 + T * 10 * 32 * 32
-    spectra_computed = -(-((S + 7) // 8) // 4) * 32
-    computed = float(B) * P * pairs_computed * spectra_computed
+    nb = (S + 7) // 8
+    spectra_off = -(-nb // 16) * 16 * 8
+    spectra_diag = -(-nb // 4) * 4 * 8
+    computed = float(B) * P * (T * (T - 1) // 2 * 128 * 128 * spectra_off + T * 10 * 32 * 32 * spectra_diag)
     out["xengine_computed_cmac"] = computed
     out["xengine_useful_fraction"] = round(cmac / computed, 4)
     log(f"int8 step {ms_step:.3f} ms (ppf {ppf_ms:.3f}, xengine {xe_ms:.3f})")
@@ -557,6 +559,7 @@ def run_fine(torch, afc, W, dev, cfg, reps=3):
                    "channelise_ms": round(f_ms, 3),
                    "channelise_gbs": round(fine_bytes / (f_ms * 1e-3) / 1e9, 1),
                    "channelise_hbm_frac": round(fine_bytes / (f_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                   "algorithmic_bytes": fine_bytes,
                    "channelise_ms_per_subband_second": round(f_ms / B / data_f, 3),
                    "xengine_ms": round(fx_ms, 3),
                    "step_ms": round(f_ms + fx_ms, 3),
