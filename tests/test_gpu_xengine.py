@@ -44,6 +44,10 @@ CASES = [
     ("f32", 2, 33, 100, [3, 100], None, range(0, 64, 13)),
     ("i8", 1, 1, 5, None, None, range(64)),                   # one antenna
     ("f16", 1, 64, 16, None, None, range(0, 64, 21)),         # exactly one 128 tile
+    # three 128-row tiles (off-diagonal tiles load their column operands
+    # directly) with stage counts that are not a multiple of the register ring
+    ("i8", 2, 150, 300, [300, 171], [7], range(0, 64, 13)),
+    ("f16", 1, 150, 77, None, None, range(0, 64, 13)),
 ]
 
 
