@@ -11,8 +11,8 @@ Shapes follow the paper's arrays: 48 dual-polarised antennas per station
 (Sec. "LOFAR Telescope Architecture"), 6 or 12 stations (AARTFAAC-6 / -12,
 Table 1), 195312.5 Hz subbands of complex 16-bit samples (Sec. "LOFAR Digital
 Processing"), 3 kHz channels and 1 s integrations (Table 1).  The real
-observations are not available, so everything here is synthetic; the recipe
-is restated in DESIGN.md.
+observations are not available, so everything here is synthetic: seeded
+Gaussian noise per input plus point sources with known geometric phases.
 
 Array layouts (all C order):
   x   int16  [B][L][Na][2][2]   time-major subband samples, inputs i = 2a+p
