@@ -48,6 +48,8 @@ def _load():
     lib.orc_xcorr_i64.restype = C.c_int
     lib.orc_cal_loss_grad.argtypes = [_p, _p, _p, _i64, _i64, _p, _p]
     lib.orc_cal_loss_grad.restype = C.c_int
+    lib.orc_cal_loss_grad_w.argtypes = [_p, _p, _p, _p, _i64, _i64, _p, _p]
+    lib.orc_cal_loss_grad_w.restype = C.c_int
     lib.orc_fine_channelise.argtypes = [_p, _i64, _i64, _i64, _p, _i64, _i64, _i64, _i64,
                                         C.c_double, C.c_double, C.c_double, _p, _i64, _p]
     lib.orc_fine_channelise.restype = C.c_int
@@ -244,9 +246,24 @@ def zero_invalid(z: np.ndarray, v: np.ndarray) -> np.ndarray:
 # --------------------------------------------------------------------------
 # gain calibration (Sec. "Calibration Pipeline")
 # --------------------------------------------------------------------------
+def cal_weights(P: int, nbl: int, flags: Optional[np.ndarray] = None,
+                weights: Optional[np.ndarray] = None) -> np.ndarray:
+    """Per-baseline calibration weights float64 [P][Nbl][2] (XX, YY) (Sec.
+    "Real-time Flagging, Calibration and Imaging": the calibration works on
+    the flagged visibilities, re-weighted for lost data): 0 where flags
+    (uint8 [P][Nbl][2], nonzero = flagged) is set, else the given weight
+    (float [P][Nbl][2]) or 1."""
+    w = np.ones((P, nbl, 2), np.float64) if weights is None else np.asarray(weights, np.float64).copy()
+    if flags is not None:
+        w[np.asarray(flags) != 0] = 0.0
+    return w
+
+
 def cal_loss_grad(V: np.ndarray, M: np.ndarray, g: np.ndarray,
-                  want_grad: bool = True) -> Tuple[np.ndarray, Optional[np.ndarray]]:
-    """V, M float32 [P][Nbl][2][2][2]; g float32 [P][Na][2][2].
+                  want_grad: bool = True, weights: Optional[np.ndarray] = None
+                  ) -> Tuple[np.ndarray, Optional[np.ndarray]]:
+    """V, M float32 [P][Nbl][2][2][2]; g float32 [P][Na][2][2]; optional
+    weights float64 [P][Nbl][2] (the weighted loss sum w_ab |R_ab|^2).
 
     Returns loss float64 [P][2] and grad complex128 [P][Na][2] (or None).
     """
@@ -257,7 +274,12 @@ def cal_loss_grad(V: np.ndarray, M: np.ndarray, g: np.ndarray,
     assert V.shape[:2] == (P, Na * (Na + 1) // 2) and M.shape == V.shape
     loss = np.empty((P, 2), np.float64)
     grad = np.empty((P, Na, 2, 2), np.float64) if want_grad else None
-    rc = _load().orc_cal_loss_grad(_ptr(V), _ptr(M), _ptr(g), Na, P, _ptr(loss), _ptr(grad))
+    if weights is None:
+        rc = _load().orc_cal_loss_grad(_ptr(V), _ptr(M), _ptr(g), Na, P, _ptr(loss), _ptr(grad))
+    else:
+        w = _c(weights, np.float64)
+        assert w.shape == (P, Na * (Na + 1) // 2, 2)
+        rc = _load().orc_cal_loss_grad_w(_ptr(V), _ptr(M), _ptr(w), _ptr(g), Na, P, _ptr(loss), _ptr(grad))
     if rc != 0:
         raise MemoryError("orc_cal_loss_grad")
     return loss, (None if grad is None else _to_complex(grad))
@@ -278,7 +300,8 @@ def _full(T_lower: np.ndarray, Na: int, pol: int) -> np.ndarray:
     return F
 
 
-def cal_solve(V: np.ndarray, M: np.ndarray, g0: np.ndarray, n_iter: int) -> np.ndarray:
+def cal_solve(V: np.ndarray, M: np.ndarray, g0: np.ndarray, n_iter: int,
+              weights: Optional[np.ndarray] = None) -> np.ndarray:
     """Per-channel complex gains minimising L = ||V - G M G^H||_F^2 for XX and
     YY (Sec. "Calibration Pipeline": amplitude and phase calibration per
     channel against a point-source model; least-squares reading).
@@ -291,6 +314,10 @@ def cal_solve(V: np.ndarray, M: np.ndarray, g0: np.ndarray, n_iter: int) -> np.n
     n_iter iterations the common phase is removed so that g_0 is real and
     positive.
 
+    With weights (float [P][Nbl][2], the weighted loss of cal_loss_grad)
+    the same update minimises sum_b w_ab |V_ab - g_a z_ab|^2 over g_a:
+    sum_b w_ab V_ab conj(z_ab) / sum_b w_ab |z_ab|^2.
+
     V, M float32 [P][Nbl][2][2][2]; g0 complex [P][Na][2] -> complex128 [P][Na][2].
     """
     P, nbl = V.shape[0], V.shape[1]
@@ -300,11 +327,16 @@ def cal_solve(V: np.ndarray, M: np.ndarray, g0: np.ndarray, n_iter: int) -> np.n
         for pol in range(2):
             Vf = _full(V[ch], Na, pol)
             Mf = _full(M[ch], Na, pol)
+            Wf = np.ones((Na, Na))
+            if weights is not None:
+                a_, b_ = np.tril_indices(Na)
+                Wf[a_, b_] = weights[ch, :, pol]
+                Wf[b_, a_] = weights[ch, :, pol]
             g = np.asarray(g0[ch, :, pol], np.complex128).copy()
             for it in range(1, n_iter + 1):
                 z = Mf * np.conj(g)[None, :]
-                num = (Vf * np.conj(z)).sum(axis=1)
-                den = (np.abs(z) ** 2).sum(axis=1)
+                num = (Wf * Vf * np.conj(z)).sum(axis=1)
+                den = (Wf * np.abs(z) ** 2).sum(axis=1)
                 g_new = np.where(den > 0, num / np.where(den > 0, den, 1.0), g)
                 if it % 2 == 0:
                     g_new = 0.5 * (g_new + g)

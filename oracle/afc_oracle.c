@@ -282,9 +282,17 @@ int orc_xcorr_i64(const int8_t *z, int64_t S, int64_t Na, const uint8_t *flags,
  *       XX = [0][0], YY = [1][1]); the upper triangle is the conjugate.
  * g:    float32 [P][Na][2][2] complex gain per channel, antenna, pol.
  * loss: [P][2];  grad: [P][Na][2][2] = dL/dRe g + i dL/dIm g, or NULL.
+ *
+ * Weighted form (Sec. "Real-time Flagging, Calibration and Imaging": the
+ * calibration works on the flagged visibilities, re-weighted for lost
+ * data): with real weights w_ab = w_ba >= 0 per stored baseline and
+ * polarisation, double [P][Nbl][2] (NULL = all 1),
+ *   L = sum_{a,b} w_ab |R_ab|^2,
+ *   grad_a = -2 sum_b [w_ab R_ab conj(M_ab) + w_ba conj(R_ba) M_ba] g_b.
+ * A flagged baseline has weight 0.
  * ---------------------------------------------------------------------- */
-int orc_cal_loss_grad(const float *V, const float *M, const float *g, int64_t Na, int64_t P,
-                      double *loss, double *grad)
+int orc_cal_loss_grad_w(const float *V, const float *M, const double *w, const float *g, int64_t Na,
+                        int64_t P, double *loss, double *grad)
 {
     int64_t nbl = Na * (Na + 1) / 2;
     int64_t job;
@@ -295,8 +303,10 @@ int orc_cal_loss_grad(const float *V, const float *M, const float *g, int64_t Na
         double *Vr = (double *)malloc(sizeof(double) * 2 * Na * Na);
         double *Mr = (double *)malloc(sizeof(double) * 2 * Na * Na);
         double *Rr = (double *)malloc(sizeof(double) * 2 * Na * Na);
-        if (!Vr || !Mr || !Rr) { err = 1; free(Vr); free(Mr); free(Rr); continue; }
-        /* Hermitian completion of the stored lower triangle */
+        double *Wr = (double *)malloc(sizeof(double) * Na * Na);
+        if (!Vr || !Mr || !Rr || !Wr) { err = 1; free(Vr); free(Mr); free(Rr); free(Wr); continue; }
+        /* Hermitian completion of the stored lower triangle (the weights
+         * are symmetric) */
         for (int64_t a = 0; a < Na; ++a)
             for (int64_t b = 0; b <= a; ++b) {
                 int64_t off = 2 * (((ch * nbl + a * (a + 1) / 2 + b) * 2 + pol) * 2 + pol);
@@ -306,6 +316,7 @@ int orc_cal_loss_grad(const float *V, const float *M, const float *g, int64_t Na
                 Mr[2 * (a * Na + b)] = mr;  Mr[2 * (a * Na + b) + 1] = mi;
                 Mr[2 * (b * Na + a)] = mr;  Mr[2 * (b * Na + a) + 1] = -mi;
                 if (a == b) { Vr[2 * (a * Na + a) + 1] = vi; Mr[2 * (a * Na + a) + 1] = mi; }
+                Wr[a * Na + b] = Wr[b * Na + a] = w ? w[(ch * nbl + a * (a + 1) / 2 + b) * 2 + pol] : 1.0;
             }
         /* R_ab = V_ab - g_a M_ab conj(g_b);  L = sum |R_ab|^2 */
         double L = 0.0;
@@ -321,7 +332,7 @@ int orc_cal_loss_grad(const float *V, const float *M, const float *g, int64_t Na
                 double rr = Vr[2 * (a * Na + b)] - wr, ri = Vr[2 * (a * Na + b) + 1] - wi;
                 Rr[2 * (a * Na + b)] = rr;
                 Rr[2 * (a * Na + b) + 1] = ri;
-                L += rr * rr + ri * ri;
+                L += Wr[a * Na + b] * (rr * rr + ri * ri);
             }
         }
         loss[ch * 2 + pol] = L;
@@ -332,11 +343,12 @@ int orc_cal_loss_grad(const float *V, const float *M, const float *g, int64_t Na
                     /* c = R_ab conj(M_ab) + conj(R_ba) M_ba */
                     double rr = Rr[2 * (a * Na + b)], ri = Rr[2 * (a * Na + b) + 1];
                     double mr = Mr[2 * (a * Na + b)], mi = Mr[2 * (a * Na + b) + 1];
-                    double cr = rr * mr + ri * mi, ci = ri * mr - rr * mi;
+                    double wab = Wr[a * Na + b], wba = Wr[b * Na + a];
+                    double cr = wab * (rr * mr + ri * mi), ci = wab * (ri * mr - rr * mi);
                     double r2r = Rr[2 * (b * Na + a)], r2i = -Rr[2 * (b * Na + a) + 1];
                     double m2r = Mr[2 * (b * Na + a)], m2i = Mr[2 * (b * Na + a) + 1];
-                    cr += r2r * m2r - r2i * m2i;
-                    ci += r2r * m2i + r2i * m2r;
+                    cr += wba * (r2r * m2r - r2i * m2i);
+                    ci += wba * (r2r * m2i + r2i * m2r);
                     double gbr = g[2 * ((ch * Na + b) * 2 + pol)], gbi = g[2 * ((ch * Na + b) * 2 + pol) + 1];
                     sr += cr * gbr - ci * gbi;
                     si += cr * gbi + ci * gbr;
@@ -345,9 +357,15 @@ int orc_cal_loss_grad(const float *V, const float *M, const float *g, int64_t Na
                 grad[2 * ((ch * Na + a) * 2 + pol) + 1] = -2.0 * si;
             }
         }
-        free(Vr); free(Mr); free(Rr);
+        free(Vr); free(Mr); free(Rr); free(Wr);
     }
     return err ? -1 : 0;
+}
+
+int orc_cal_loss_grad(const float *V, const float *M, const float *g, int64_t Na, int64_t P,
+                      double *loss, double *grad)
+{
+    return orc_cal_loss_grad_w(V, M, NULL, g, Na, P, loss, grad);
 }
 
 /* ------------------------------------------------------------------------

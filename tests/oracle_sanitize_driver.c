@@ -25,6 +25,8 @@ void orc_xcorr_pairs_i64(const int8_t *, int64_t, int64_t, int64_t, const int32_
 void orc_xcorr_f64(const double *, int64_t, int64_t, const uint8_t *, double *, int32_t *);
 int orc_xcorr_i64(const int8_t *, int64_t, int64_t, const uint8_t *, int64_t *, int32_t *);
 int orc_cal_loss_grad(const float *, const float *, const float *, int64_t, int64_t, double *, double *);
+int orc_cal_loss_grad_w(const float *, const float *, const double *, const float *, int64_t, int64_t, double *,
+                        double *);
 int orc_fine_channelise(const int16_t *, int64_t, int64_t, int64_t, const float *, int64_t, int64_t, int64_t,
                         int64_t, double, double, double, const float *, int64_t, double *);
 void orc_spectrum_validity(const uint8_t *, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t,
@@ -149,6 +151,15 @@ static int calibration(void)
     for (int k = 0; k < 4; ++k) CHECK(loss[k] == 0.0, "noise-free loss is zero");
     for (int64_t n = 0; n < P * Na * 4; ++n) CHECK(grad[n] == 0.0, "noise-free gradient is zero");
     CHECK(orc_cal_loss_grad(V, M, g, Na, P, loss, NULL) == 0, "loss only");
+    {   /* weighted form: noise-free data stay at zero loss and gradient */
+        const int64_t nbl = Na * (Na + 1) / 2;
+        double *w = malloc(sizeof(double) * P * nbl * 2);
+        for (int64_t n = 0; n < P * nbl * 2; ++n) w[n] = (double)(n % 3);
+        CHECK(orc_cal_loss_grad_w(V, M, w, g, Na, P, loss, grad) == 0, "weighted cal");
+        for (int k = 0; k < 4; ++k) CHECK(loss[k] == 0.0, "weighted noise-free loss is zero");
+        for (int64_t n = 0; n < P * Na * 4; ++n) CHECK(grad[n] == 0.0, "weighted noise-free gradient is zero");
+        free(w);
+    }
     free(V); free(M); free(g); free(grad);
     return 0;
 }

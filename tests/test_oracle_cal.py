@@ -139,3 +139,91 @@ def test_zero_residual_zero_grad_and_invariants():
             rhs = -4.0 * np.real(np.trace(R.conj().T @ S_))
             assert np.isclose(lhs, rhs, rtol=1e-9)
     del gg
+
+
+# ---- weighted loss (flags and lost-data weights)
+
+def _weights(rng, P, Na, zero_frac=0.2):
+    nbl = Na * (Na + 1) // 2
+    w = rng.uniform(0.25, 2.0, (P, nbl, 2))
+    w[rng.random((P, nbl, 2)) < zero_frac] = 0.0
+    return w
+
+
+def test_weighted_loss_is_weighted_frobenius_sum():
+    """L = sum_{a,b} w_ab |R_ab|^2 over the full matrices (numpy), with the
+    weights completed symmetrically."""
+    rng = np.random.default_rng(31)
+    Na, P = 9, 2
+    V, M, g = _rand_case(rng, Na, P)
+    w = _weights(rng, P, Na)
+    loss, _ = oracle.cal_loss_grad(V, M, g, weights=w)
+    a_, b_ = np.tril_indices(Na)
+    for k in range(P):
+        for pol in range(2):
+            Vf = _full(_cplx(V[k, :, pol, pol].astype(np.float64)), Na)
+            Mf = _full(_cplx(M[k, :, pol, pol].astype(np.float64)), Na)
+            Wf = np.zeros((Na, Na))
+            Wf[a_, b_] = w[k, :, pol]
+            Wf[b_, a_] = w[k, :, pol]
+            G = np.diag(_cplx(g[k, :, pol].astype(np.float64)))
+            R = Vf - G @ Mf @ G.conj().T
+            assert np.isclose(loss[k, pol], np.sum(Wf * np.abs(R) ** 2), rtol=1e-12)
+
+
+def test_weighted_unit_weights_equal_unweighted_and_scaling():
+    rng = np.random.default_rng(32)
+    V, M, g = _rand_case(rng, 8, 2)
+    l0, g0 = oracle.cal_loss_grad(V, M, g)
+    l1, g1 = oracle.cal_loss_grad(V, M, g, weights=np.ones((2, 36, 2)))
+    np.testing.assert_array_equal(l0, l1)
+    np.testing.assert_array_equal(g0, g1)
+    w = _weights(rng, 2, 8)
+    lw, gw = oracle.cal_loss_grad(V, M, g, weights=w)
+    l2, g2 = oracle.cal_loss_grad(V, M, g, weights=2 * w)      # exact: a power of two
+    np.testing.assert_array_equal(l2, 2 * lw)
+    np.testing.assert_array_equal(g2, 2 * gw)
+
+
+def test_flagged_baselines_equal_zeroed_data():
+    """A zero weight removes the baseline: the same loss and gradient as
+    zeroing V and M there (R = 0).  Flags map to zero weights."""
+    rng = np.random.default_rng(33)
+    Na, P = 10, 2
+    V, M, g = _rand_case(rng, Na, P)
+    nbl = Na * (Na + 1) // 2
+    flags = (rng.random((P, nbl, 2)) < 0.3).astype(np.uint8)
+    w = oracle.cal_weights(P, nbl, flags=flags)
+    assert np.all(w[flags != 0] == 0) and np.all(w[flags == 0] == 1)
+    lw, gw = oracle.cal_loss_grad(V, M, g, weights=w)
+    Vz, Mz = V.copy(), M.copy()
+    for pol in range(2):
+        sel = flags[:, :, pol] != 0
+        Vz[:, :, pol, pol][sel] = 0
+        Mz[:, :, pol, pol][sel] = 0
+    lz, gz = oracle.cal_loss_grad(Vz, Mz, g)
+    np.testing.assert_allclose(lw, lz, rtol=1e-13)
+    np.testing.assert_allclose(gw, gz, rtol=1e-12, atol=1e-12 * np.abs(gz).max())
+    # flags and weights together: flagged entries 0, others the weight
+    w2 = oracle.cal_weights(P, nbl, flags=flags, weights=np.full((P, nbl, 2), 3.0))
+    assert np.all(w2[flags != 0] == 0) and np.all(w2[flags == 0] == 3.0)
+
+
+def test_weighted_gradient_finite_differences():
+    rng = np.random.default_rng(34)
+    Na, P = 7, 1
+    V, M, g = _rand_case(rng, Na, P)
+    g = np.round(g * 64) / 64
+    w = _weights(rng, P, Na)
+    _, grad = oracle.cal_loss_grad(V, M, g, weights=w)
+    h = 1.0 / 1024
+    for a in [0, 2, 6]:
+        for pol in range(2):
+            for comp in range(2):
+                gp = g.copy(); gp[0, a, pol, comp] += h
+                gm = g.copy(); gm[0, a, pol, comp] -= h
+                lp, _ = oracle.cal_loss_grad(V, M, gp, want_grad=False, weights=w)
+                lm, _ = oracle.cal_loss_grad(V, M, gm, want_grad=False, weights=w)
+                fd = (lp[0, pol] - lm[0, pol]) / (2 * h)
+                an = grad[0, a, pol].real if comp == 0 else grad[0, a, pol].imag
+                assert abs(fd - an) <= 1e-4 * max(1.0, abs(an))

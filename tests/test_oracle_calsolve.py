@@ -166,3 +166,30 @@ def test_sigma_clip_stage2_rms_excludes_stage1_flags():
     f = oracle.sigma_clip(V, k)
     assert f[5, bl, 0] == 1 and f[9, bl, 0] == 1
     assert f[:, bl, 0].sum() == 2
+
+
+def test_weighted_solve_zero_weights_equal_zeroed_data_and_noise_free_recovery():
+    """The weighted update with 0/1 weights equals the unweighted one on
+    data zeroed at the zero-weight baselines (the sums see the same terms),
+    and with any positive weights noise-free data give back the true gains."""
+    V, M, g = W.make_calibration(Na=10, P=2, snr=6.0, seed=41)
+    P, nbl = V.shape[0], V.shape[1]
+    rng = np.random.default_rng(42)
+    flags = (rng.random((P, nbl, 2)) < 0.25).astype(np.uint8)
+    w = oracle.cal_weights(P, nbl, flags=flags)
+    g0 = np.ones((P, 10, 2), np.complex128)
+    sw = oracle.cal_solve(V, M, g0, 30, weights=w)
+    Vz, Mz = V.copy(), M.copy()
+    for pol in range(2):
+        sel = flags[:, :, pol] != 0
+        Vz[:, :, pol, pol][sel] = 0
+        Mz[:, :, pol, pol][sel] = 0
+    sz = oracle.cal_solve(Vz, Mz, g0, 30)
+    np.testing.assert_allclose(sw, sz, rtol=1e-12, atol=1e-12)
+    # noise-free, positive random weights: the true gains (phase-referenced)
+    Vc, Mc, gc = W.make_calibration(Na=10, P=2, snr=1e12, seed=43)
+    wp = rng.uniform(0.5, 2.0, (P, nbl, 2))
+    sol = oracle.cal_solve(Vc, Mc, g0, 300, weights=wp)
+    gt = gc[..., 0].astype(np.float64) + 1j * gc[..., 1]
+    gt = gt * (np.conj(gt[:, :1, :]) / np.abs(gt[:, :1, :]))
+    assert np.abs(sol - gt).max() <= 1e-5 * np.abs(gt).max()

@@ -55,7 +55,12 @@ MUTATIONS = [
      "double v = (double)(y[i] * gain);", None),
     ("cal-missing-conjugate", C_SRC, "Vr[2 * (b * Na + a) + 1] = -vi;", "Vr[2 * (b * Na + a) + 1] = vi;", None),
     ("grad-dropped-term", C_SRC,
-     "cr += r2r * m2r - r2i * m2i;\n                    ci += r2r * m2i + r2i * m2r;", "", None),
+     "cr += wba * (r2r * m2r - r2i * m2i);\n                    ci += wba * (r2r * m2i + r2i * m2r);", "", None),
+    ("cal-weight-loss-dropped", C_SRC, "L += Wr[a * Na + b] * (rr * rr + ri * ri);", "L += rr * rr + ri * ri;", None),
+    ("cal-weight-grad-dropped", C_SRC, "double cr = wab * (rr * mr + ri * mi), ci = wab * (ri * mr - rr * mi);",
+     "double cr = (rr * mr + ri * mi), ci = (ri * mr - rr * mi);", None),
+    ("cal-weight-pol-index", C_SRC, "w[(ch * nbl + a * (a + 1) / 2 + b) * 2 + pol]",
+     "w[(ch * nbl + a * (a + 1) / 2 + b) * 2]", None),
     ("grad-sign", C_SRC, "grad[2 * ((ch * Na + a) * 2 + pol)] = -2.0 * sr;",
      "grad[2 * ((ch * Na + a) * 2 + pol)] = 2.0 * sr;", None),
     ("fine-delay-sign", C_SRC, "const double ang = 2.0 * ORC_PI * (nu_c + fk) * tau;",
@@ -72,6 +77,8 @@ MUTATIONS = [
      "fine_channelise(x, taps, i, Pf, T, 0, S, tau[n], nu_c, df, w, R).T", None),
     ("zero-invalid-noop", PY_SRC, "return np.where(keep, z, 0)", "return z", None),
     ("solve-averaging-parity", PY_SRC, "if it % 2 == 0:", "if it % 2 == 1:", None),
+    ("solve-weight-numerator", PY_SRC, "num = (Wf * Vf * np.conj(z)).sum(axis=1)", "num = (Vf * np.conj(z)).sum(axis=1)",
+     None),
     ("solve-phase-reference", PY_SRC, "g = g * (np.conj(g[0]) / abs(g[0]))", "g = g * (g[0] / abs(g[0]))", None),
     ("clip-rms-includes-flagged", PY_SRC,
      "m = np.where(keep, a2, 0.0).sum(axis=0) / np.maximum(n, 1)", "m = a2.mean(axis=0)", None),
