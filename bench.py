@@ -470,7 +470,20 @@ def main():
         out["calibration"] = {"ms": round(cal_ms, 4), "algorithmic_gbs": round(cal_bytes / (cal_ms * 1e-3) / 1e9, 1),
                               "hbm_frac": round(cal_bytes / (cal_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                               "xx_yy_gbs": round(cal_bytes / 2 / (cal_ms * 1e-3) / 1e9, 1)}
-        del wcal
+        # the weighted gradient (sigma-clip flags and lost-data weights)
+        nbl_c = 576 * 577 // 2
+        flc = (torch.rand((64, nbl_c, 2), device=dev) < 0.05).to(torch.uint8)
+        wtc = torch.rand((64, nbl_c, 2), device=dev) + 0.5
+        afc.calibrate_grad(Vt, Mt, gt, workspace=wcal, flags=flc, weights=wtc)
+        torch.cuda.synchronize()
+        tcw = Timer(torch)
+        e = tcw.rec("calw")
+        for _ in range(n_cal):
+            afc.calibrate_grad(Vt, Mt, gt, workspace=wcal, flags=flc, weights=wtc)
+        e.record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        out["calibration"]["weighted_ms"] = round(tcw.ms("calw") / n_cal, 4)
+        del wcal, flc, wtc
         log(f"calibration {cal_ms:.3f} ms")
         # ---- gain solver (30 iterations from unit gains) and sigma-clip flagging
         n_it = 30

@@ -325,6 +325,36 @@ AFC_API int afc_calibrate_solve(int32_t n_antennas, int32_t n_channels, const vo
                                 const void* M, void* g, int32_t n_iter, double* loss,
                                 void* workspace, hipStream_t stream);
 
+/* -------------------------------------------------------------------------
+ * afc_calibrate_grad_weighted, afc_calibrate_solve_weighted -- the loss,
+ * gradient and solver above on flagged and re-weighted visibilities
+ * (Sec. "Real-time Flagging, Calibration and Imaging": lost packets re-weight
+ * the visibilities, sigma clipping flags them, and calibration works on the
+ * flagged visibilities).  With a real weight w_ab per stored baseline and
+ * polarisation (w_ba = w_ab):
+ *
+ *   L = sum_{a,b} w_ab |R_ab|^2
+ *   grad_a = -2 sum_b [ w_ab R_ab conj(M_ab) + w_ba conj(R_ba) M_ba ] g_b
+ *   solver: D_a = sum_b w_ab |M_ab|^2 |g_b|^2 (the weighted least-squares
+ *           optimum of each g_a with the others fixed)
+ *
+ * w_ab = 0 where vis_flags is nonzero, else weights[...] (or 1 when weights
+ * is NULL).  Both arrays are [P][Nbl][2] (channel, baseline, XX / YY), the
+ * layout afc_sigma_clip writes; either may be NULL (both NULL = the
+ * unweighted entry points, bit for bit).  Weights must be finite and >= 0
+ * (finiteness is checked in checked mode; the sign is not checked).
+ * All other arguments, the workspace sizes and the limits are those of
+ * afc_calibrate_grad and afc_calibrate_solve.
+ * ------------------------------------------------------------------------- */
+AFC_API int afc_calibrate_grad_weighted(int32_t n_antennas, int32_t n_channels, const void* V,
+                                        const void* M, const uint8_t* vis_flags,
+                                        const float* weights, const void* g, double* loss,
+                                        void* grad, void* workspace, hipStream_t stream);
+AFC_API int afc_calibrate_solve_weighted(int32_t n_antennas, int32_t n_channels, const void* V,
+                                         const void* M, const uint8_t* vis_flags,
+                                         const float* weights, void* g, int32_t n_iter,
+                                         double* loss, void* workspace, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * afc_sigma_clip -- real-time flagging (Sec. "Calibration Pipeline",
  * flagging: sigma clipping of visibility amplitudes against a threshold

@@ -60,6 +60,8 @@ _lib.afc_calibrate_grad_noalloc.argtypes = [_i32, _i32, _vp, _vp, _vp, _vp, _vp,
 _lib.afc_calibrate_solve_workspace_bytes.argtypes = [_i32, _i32]
 _lib.afc_calibrate_solve_workspace_bytes.restype = _sz
 _lib.afc_calibrate_solve.argtypes = [_i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp]
+_lib.afc_calibrate_grad_weighted.argtypes = [_i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.afc_calibrate_solve_weighted.argtypes = [_i32, _i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp]
 _lib.afc_sigma_clip_workspace_bytes.argtypes = [_i32, _i32]
 _lib.afc_sigma_clip_workspace_bytes.restype = _sz
 _lib.afc_sigma_clip.argtypes = [_i32, _i32, _vp, _f32, _vp, _vp, _vp]
@@ -86,7 +88,8 @@ EXPORTS = ["afc_channelised_bytes", "afc_visibility_bytes", "afc_channelise",
            "afc_normalise_visibilities", "afc_calibrate_solve_workspace_bytes", "afc_calibrate_solve",
            "afc_sigma_clip_workspace_bytes", "afc_sigma_clip", "afc_apply_vis_flags",
            "afc_imaging_workspace_bytes", "afc_grid_visibilities", "afc_image_from_grid",
-           "afc_calibrate_workspace_bytes", "afc_calibrate_grad", "afc_calibrate_grad_noalloc", "afc_plan_create",
+           "afc_calibrate_workspace_bytes", "afc_calibrate_grad", "afc_calibrate_grad_noalloc",
+           "afc_calibrate_grad_weighted", "afc_calibrate_solve_weighted", "afc_plan_create",
            "afc_plan_workspace_bytes", "afc_plan_launch", "afc_plan_info", "afc_plan_destroy",
            "afc_set_checked_mode", "afc_checked_mode", "afc_count_nonfinite", "afc_last_error"]
 
@@ -394,16 +397,34 @@ def _workspace(ws, nbytes: int, device):
     return ws
 
 
-def calibrate_grad(V, M, g, want_grad: bool = True, workspace=None):
-    """V, M float32 [P][Nbl][2][2][2]; g float32 [P][Na][2][2] -> (loss float64 [P][2], grad [P][Na][2][2])."""
+def _cal_weights(P: int, Na: int, flags, weights):
+    torch = _torch()
+    nbl = Na * (Na + 1) // 2
+    if flags is not None:
+        _require(flags, torch.uint8, "flags", (P, nbl, 2))
+    if weights is not None:
+        _require(weights, torch.float32, "weights", (P, nbl, 2))
+
+
+def calibrate_grad(V, M, g, want_grad: bool = True, workspace=None, flags=None, weights=None):
+    """V, M float32 [P][Nbl][2][2][2]; g float32 [P][Na][2][2] -> (loss float64 [P][2], grad [P][Na][2][2]).
+    With flags (uint8 [P][Nbl][2], nonzero = flagged) and/or weights (float32
+    [P][Nbl][2]): the weighted loss (afc_calibrate_grad_weighted)."""
     torch = _torch()
     P, Na = _cal_shapes(V, M, g)
     loss = torch.empty((P, 2), dtype=torch.float64, device=V.device)
     grad = torch.empty_like(g) if want_grad else None
     wsb = _lib.afc_calibrate_workspace_bytes(Na, P)
     workspace = _workspace(workspace, wsb, V.device)
-    _check(_lib.afc_calibrate_grad(Na, P, _ptr(V), _ptr(M), _ptr(g), _ptr(loss), _ptr(grad), _ptr(workspace),
-                                   _stream(V, M, g, loss, grad, workspace)), "afc_calibrate_grad")
+    if flags is None and weights is None:
+        _check(_lib.afc_calibrate_grad(Na, P, _ptr(V), _ptr(M), _ptr(g), _ptr(loss), _ptr(grad), _ptr(workspace),
+                                       _stream(V, M, g, loss, grad, workspace)), "afc_calibrate_grad")
+    else:
+        _cal_weights(P, Na, flags, weights)
+        _check(_lib.afc_calibrate_grad_weighted(Na, P, _ptr(V), _ptr(M), _ptr(flags), _ptr(weights), _ptr(g),
+                                                _ptr(loss), _ptr(grad), _ptr(workspace),
+                                                _stream(V, M, flags, weights, g, loss, grad, workspace)),
+               "afc_calibrate_grad_weighted")
     return loss, grad
 
 
@@ -425,17 +446,26 @@ def calibrate_grad_noalloc(V, M, g, loss, grad=None):
     return loss, grad
 
 
-def calibrate_solve(V, M, g, n_iter: int = 40, want_loss: bool = True, workspace=None):
+def calibrate_solve(V, M, g, n_iter: int = 40, want_loss: bool = True, workspace=None, flags=None,
+                    weights=None):
     """Gains minimising ||V - G M G^H||_F^2 per (channel, XX/YY): g float32
     [P][Na][2][2] is updated in place (initial gains in, phase-referenced
-    solution out).  Returns the loss float64 [P][2] of the solution (or None)."""
+    solution out).  Returns the loss float64 [P][2] of the solution (or None).
+    flags / weights as in calibrate_grad select the weighted loss."""
     torch = _torch()
     P, Na = _cal_shapes(V, M, g)
     loss = torch.empty((P, 2), dtype=torch.float64, device=V.device) if want_loss else None
     wsb = _lib.afc_calibrate_solve_workspace_bytes(Na, P)
     workspace = _workspace(workspace, wsb, V.device)
-    _check(_lib.afc_calibrate_solve(Na, P, _ptr(V), _ptr(M), _ptr(g), int(n_iter), _ptr(loss), _ptr(workspace),
-                                    _stream(V, M, g, loss, workspace)), "afc_calibrate_solve")
+    if flags is None and weights is None:
+        _check(_lib.afc_calibrate_solve(Na, P, _ptr(V), _ptr(M), _ptr(g), int(n_iter), _ptr(loss), _ptr(workspace),
+                                        _stream(V, M, g, loss, workspace)), "afc_calibrate_solve")
+    else:
+        _cal_weights(P, Na, flags, weights)
+        _check(_lib.afc_calibrate_solve_weighted(Na, P, _ptr(V), _ptr(M), _ptr(flags), _ptr(weights), _ptr(g),
+                                                 int(n_iter), _ptr(loss), _ptr(workspace),
+                                                 _stream(V, M, flags, weights, g, loss, workspace)),
+               "afc_calibrate_solve_weighted")
     return loss
 
 

@@ -378,6 +378,28 @@ AFC_API int afc_calibrate_grad_noalloc(int32_t n_antennas, int32_t n_channels, c
     return AFC_OK;
 }
 
+AFC_API int afc_calibrate_grad_weighted(int32_t n_antennas, int32_t n_channels, const void* V, const void* M,
+                                        const uint8_t* vis_flags, const float* weights, const void* g, double* loss,
+                                        void* grad, void* workspace, hipStream_t stream) {
+    g_err.clear();
+    if (n_antennas < 1 || n_antennas > 4096) return fail(AFC_ERR_INVALID, "n_antennas = %d outside 1..4096", n_antennas);
+    if (n_channels < 1 || n_channels > 65535) return fail(AFC_ERR_INVALID, "n_channels = %d outside 1..65535", n_channels);
+    if (!V || !M || !g || !loss) return fail(AFC_ERR_INVALID, "NULL pointer (V, M, g or loss)");
+    if (!workspace) return fail(AFC_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)",
+                                cal_workspace_bytes(n_antennas, n_channels));
+    int rc = check_cal_inputs(n_antennas, n_channels, V, M, g, stream);
+    if (rc != AFC_OK) return rc;
+    if (weights) {
+        rc = check_inputs({{weights, (size_t)n_channels * nbl_of(n_antennas) * 2, AFC_VALUES_F32, "weights"}}, stream);
+        if (rc != AFC_OK) return rc;
+    }
+    hipError_t e = launch_calibrate(n_antennas, n_channels, reinterpret_cast<const float2*>(V),
+                                    reinterpret_cast<const float2*>(M), reinterpret_cast<const float2*>(g), loss,
+                                    reinterpret_cast<float2*>(grad), workspace, stream, vis_flags, weights);
+    if (e != hipSuccess) return hip_fail(e, "calibration launch");
+    return AFC_OK;
+}
+
 AFC_API size_t afc_calibrate_solve_workspace_bytes(int32_t n_antennas, int32_t n_channels) {
     if (n_antennas < 1 || n_antennas > 4096 || n_channels < 1 || n_channels > 65535) return 0;
     return cal_solve_workspace_bytes(n_antennas, n_channels);
@@ -397,6 +419,29 @@ AFC_API int afc_calibrate_solve(int32_t n_antennas, int32_t n_channels, const vo
     hipError_t e = launch_calibrate_solve(n_antennas, n_channels, reinterpret_cast<const float2*>(V),
                                           reinterpret_cast<const float2*>(M), reinterpret_cast<float2*>(g), n_iter,
                                           loss, workspace, stream);
+    if (e != hipSuccess) return hip_fail(e, "calibration solver launch");
+    return AFC_OK;
+}
+
+AFC_API int afc_calibrate_solve_weighted(int32_t n_antennas, int32_t n_channels, const void* V, const void* M,
+                                         const uint8_t* vis_flags, const float* weights, void* g, int32_t n_iter,
+                                         double* loss, void* workspace, hipStream_t stream) {
+    g_err.clear();
+    if (n_antennas < 1 || n_antennas > 4096) return fail(AFC_ERR_INVALID, "n_antennas = %d outside 1..4096", n_antennas);
+    if (n_channels < 1 || n_channels > 65535) return fail(AFC_ERR_INVALID, "n_channels = %d outside 1..65535", n_channels);
+    if (n_iter < 0 || n_iter > 100000) return fail(AFC_ERR_INVALID, "n_iter = %d outside 0..100000", n_iter);
+    if (!V || !M || !g) return fail(AFC_ERR_INVALID, "NULL pointer (V, M or g)");
+    if (!workspace) return fail(AFC_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)",
+                                cal_solve_workspace_bytes(n_antennas, n_channels));
+    int rc = check_cal_inputs(n_antennas, n_channels, V, M, g, stream);
+    if (rc != AFC_OK) return rc;
+    if (weights) {
+        rc = check_inputs({{weights, (size_t)n_channels * nbl_of(n_antennas) * 2, AFC_VALUES_F32, "weights"}}, stream);
+        if (rc != AFC_OK) return rc;
+    }
+    hipError_t e = launch_calibrate_solve(n_antennas, n_channels, reinterpret_cast<const float2*>(V),
+                                          reinterpret_cast<const float2*>(M), reinterpret_cast<float2*>(g), n_iter,
+                                          loss, workspace, stream, vis_flags, weights);
     if (e != hipSuccess) return hip_fail(e, "calibration solver launch");
     return AFC_OK;
 }

@@ -139,13 +139,17 @@ hipError_t count_nonfinite(const void* p, size_t n, int kind, unsigned long long
 // address on the current device.
 constexpr size_t kCalScratchBytes = (size_t)AFC_CAL_NOALLOC_MAX_BYTES;
 hipError_t cal_scratch_address(void** out);
+// fl (uint8 [P][Nbl][2], nonzero = flagged) and wt (float [P][Nbl][2]) weight
+// the loss per baseline and polarisation; both NULL = the unweighted loss
 hipError_t launch_calibrate(int Na, int P, const float2* V, const float2* M, const float2* g,
-                            double* loss, float2* grad, void* ws, hipStream_t stream);
+                            double* loss, float2* grad, void* ws, hipStream_t stream,
+                            const uint8_t* fl = nullptr, const float* wt = nullptr);
 // gain solver: n_iter preconditioned-gradient (alternating least-squares)
 // iterations from g, result phase-referenced to antenna 0, written to g
 size_t cal_solve_workspace_bytes(int Na, int P);
 hipError_t launch_calibrate_solve(int Na, int P, const float2* V, const float2* M, float2* g, int n_iter,
-                                  double* loss, void* ws, hipStream_t stream);
+                                  double* loss, void* ws, hipStream_t stream, const uint8_t* fl = nullptr,
+                                  const float* wt = nullptr);
 // two-stage sigma clipping of XX / YY visibility amplitudes -> flags [P][Nbl][2]
 size_t sigma_clip_workspace_bytes(int Na, int P);
 hipError_t launch_sigma_clip(int Na, int P, const float2* V, float k, uint8_t* flags, void* ws, hipStream_t stream);

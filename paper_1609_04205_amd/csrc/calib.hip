@@ -115,14 +115,19 @@ __device__ __forceinline__ void tile_rc(int t, int& ti, int& tj) {
 // at 16-byte aligned addresses: each element is read as two 16-byte halves,
 // (XX, XY) and (YX, YY), which the hardware fetches whole anyway (6% faster
 // than two 8-byte loads).
-template <bool kDiag, bool kRec>
+// kW: weighted loss sum_{a,b} w_ab |R_ab|^2 with w from the visibility
+// flags fl (uint8 [P][Nbl][2], nonzero = weight 0) and the weights wt (float
+// [P][Nbl][2]; either may be NULL): every per-element term (loss, the
+// gradient's t = w R conj(M), the solver's w |M|^2) is scaled by w.
+template <bool kDiag, bool kRec, bool kW>
 __global__ __launch_bounds__(kThreads) void cal_tiles_kernel(int Na, int P, int n_tiles, int64_t ch_stride,
                                                              int64_t pol_off, int el_stride,
                                                              const float2* __restrict__ V,
                                                              const float2* __restrict__ M, const float2* __restrict__ g,
                                                              double2* __restrict__ rowpart, double2* __restrict__ colpart,
                                                              float* __restrict__ losspart, double* __restrict__ rowd,
-                                                             double* __restrict__ cold) {
+                                                             double* __restrict__ cold, const uint8_t* __restrict__ fl,
+                                                             const float* __restrict__ wt) {
     constexpr int NV = kDiag ? 3 : 2;                         // re, im (and D) per sum
     __shared__ double col_lds[4][kTileA][2][NV];
     __shared__ float loss_lds[4][2];
@@ -133,6 +138,7 @@ __global__ __launch_bounds__(kThreads) void cal_tiles_kernel(int Na, int P, int 
     const int c4 = tid & 15, r4 = tid >> 4;
     const float2* Vc = V + (int64_t)ch * ch_stride;
     const float2* Mc = M + (int64_t)ch * ch_stride;
+    const int64_t nbl_w = (int64_t)Na * (Na + 1) / 2;        // baselines of the weight arrays
     const float2* gc = g + (int64_t)ch * Na * 2;              // [a][2]
 
     float2 gb[4][2];
@@ -168,12 +174,22 @@ __global__ __launch_bounds__(kThreads) void cal_tiles_kernel(int Na, int P, int 
         // all loads of the row first (clamped to element 0 where the
         // element is outside the triangle; such elements contribute nothing)
         float2 vv[4][2], mv[4][2];
+        float ww[4][2];
         bool ok[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int b = tj * kTileA + c4 + 16 * q;
             ok[q] = a < Na && b < Na && b <= a;
             const int64_t e = ok[q] ? ((int64_t)a * (a + 1) / 2 + b) * el_stride : 0;
+            if constexpr (kW) {
+                // the element's two weights (XX, YY); outside the triangle
+                // the element contributes nothing anyway
+                const int64_t wi = ok[q] ? ((int64_t)ch * nbl_w + (int64_t)a * (a + 1) / 2 + b) * 2 : 0;
+                const unsigned short fp = fl ? *reinterpret_cast<const unsigned short*>(fl + wi) : (unsigned short)0;
+                const float2 wp = wt ? *reinterpret_cast<const float2*>(wt + wi) : make_float2(1.0f, 1.0f);
+                ww[q][0] = (fp & 0xFF) ? 0.0f : wp.x;
+                ww[q][1] = (fp >> 8) ? 0.0f : wp.y;
+            }
             if constexpr (kRec) {
                 const float4 v0 = *reinterpret_cast<const float4*>(Vc + e);
                 const float4 v1 = *reinterpret_cast<const float4*>(Vc + e + 2);
@@ -199,11 +215,12 @@ __global__ __launch_bounds__(kThreads) void cal_tiles_kernel(int Na, int P, int 
                 for (int p = 0; p < 2; ++p) {
                     const float2 v = vv[q][p], mm = mv[q][p];
                     const float2 R = residual(v, mm, ga[p], gb[q][p]);
-                    const float r2 = R.x * R.x + R.y * R.y;
+                    const float wq = kW ? ww[q][p] : 1.0f;
+                    const float r2 = wq * (R.x * R.x + R.y * R.y);
                     lsum[p] += a == b ? r2 : 2.0f * r2;
-                    // t = R conj(M)
-                    const float tr = R.x * mm.x + R.y * mm.y;
-                    const float tm = a == b ? 0.0f : R.y * mm.x - R.x * mm.y;   // diagonal: Re(t) only
+                    // t = w R conj(M)
+                    const float tr = wq * (R.x * mm.x + R.y * mm.y);
+                    const float tm = a == b ? 0.0f : wq * (R.y * mm.x - R.x * mm.y);   // diagonal: Re(t) only
                     // row a: t g_b
                     row[p][0] += (double)(tr * gb[q][p].x - tm * gb[q][p].y);
                     row[p][1] += (double)(tr * gb[q][p].y + tm * gb[q][p].x);
@@ -213,7 +230,7 @@ __global__ __launch_bounds__(kThreads) void cal_tiles_kernel(int Na, int P, int 
                     }
                     if constexpr (kDiag) {
                         // |M|^2 |g_b|^2 to row a; |M|^2 |g_a|^2 to column b off the diagonal
-                        const double m2 = (double)mm.x * mm.x + (double)mm.y * mm.y;
+                        const double m2 = (double)wq * ((double)mm.x * mm.x + (double)mm.y * mm.y);
                         row[p][2] += m2 * ((double)gb[q][p].x * gb[q][p].x + (double)gb[q][p].y * gb[q][p].y);
                         if (a != b) col[q][p][2] += m2 * ((double)ga[p].x * ga[p].x + (double)ga[p].y * ga[p].y);
                     }
@@ -391,7 +408,7 @@ size_t cal_solve_workspace_bytes(int Na, int P) {
 }
 
 hipError_t launch_calibrate_solve(int Na, int P, const float2* V, const float2* M, float2* g, int n_iter,
-                                  double* loss, void* ws, hipStream_t stream) {
+                                  double* loss, void* ws, hipStream_t stream, const uint8_t* fl, const float* wt) {
     const int nT = n_tiles_side(Na);
     const int n_tiles = nT * (nT + 1) / 2;
     const size_t n_g = (size_t)P * Na * 2;
@@ -425,8 +442,13 @@ hipError_t launch_calibrate_solve(int Na, int P, const float2* V, const float2* 
     }
     const unsigned ug = (unsigned)ceil_div((int64_t)n_g, 256);
     for (int it = 1; it <= n_iter; ++it) {
-        hipLaunchKernelGGL((cal_tiles_kernel<true, false>), dim3(n_tiles, P), dim3(kThreads), 0, stream, Na, P, n_tiles,
-                           2 * nbl, nbl, 1, Vc, Mc, ga, rowpart, colpart, losspart, rowd, cold);
+        if (fl || wt)
+            hipLaunchKernelGGL((cal_tiles_kernel<true, false, true>), dim3(n_tiles, P), dim3(kThreads), 0, stream, Na,
+                               P, n_tiles, 2 * nbl, nbl, 1, Vc, Mc, ga, rowpart, colpart, losspart, rowd, cold, fl, wt);
+        else
+            hipLaunchKernelGGL((cal_tiles_kernel<true, false, false>), dim3(n_tiles, P), dim3(kThreads), 0, stream, Na,
+                               P, n_tiles, 2 * nbl, nbl, 1, Vc, Mc, ga, rowpart, colpart, losspart, rowd, cold, nullptr,
+                               nullptr);
         hipLaunchKernelGGL(cal_reduce_kernel<true>, dim3((unsigned)ceil_div(Na, 256), P, 2), dim3(256), 0, stream,
                            Na, P, nT, n_tiles, rowpart, colpart, losspart, it_loss, grad, rowd, cold, D);
         hipLaunchKernelGGL(cal_update_kernel, dim3(ug), dim3(256), 0, stream, (int)n_g, ga, grad, D, gb,
@@ -438,7 +460,7 @@ hipError_t launch_calibrate_solve(int Na, int P, const float2* V, const float2* 
     hipLaunchKernelGGL(cal_reference_kernel, dim3(ug), dim3(256), 0, stream, Na, P, ga, g);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (loss) return launch_calibrate(Na, P, V, M, g, loss, nullptr, ws, stream);
+    if (loss) return launch_calibrate(Na, P, V, M, g, loss, nullptr, ws, stream, fl, wt);
     return hipSuccess;
 }
 
@@ -469,7 +491,7 @@ hipError_t cal_scratch_address(void** out) {
 }
 
 hipError_t launch_calibrate(int Na, int P, const float2* V, const float2* M, const float2* g, double* loss,
-                            float2* grad, void* ws, hipStream_t stream) {
+                            float2* grad, void* ws, hipStream_t stream, const uint8_t* fl, const float* wt) {
     const int nT = n_tiles_side(Na);
     const int n_tiles = nT * (nT + 1) / 2;
     char* w = reinterpret_cast<char*>(ws);
@@ -478,12 +500,18 @@ hipError_t launch_calibrate(int Na, int P, const float2* V, const float2* M, con
     float* losspart = reinterpret_cast<float*>(colpart + (size_t)P * 2 * n_tiles * kTileA);
     const int64_t nbl = (int64_t)Na * (Na + 1) / 2;
     const bool aligned16 = (reinterpret_cast<uintptr_t>(V) | reinterpret_cast<uintptr_t>(M)) % 16 == 0;
-    if (aligned16)
-        hipLaunchKernelGGL((cal_tiles_kernel<false, true>), dim3(n_tiles, P), dim3(kThreads), 0, stream, Na, P, n_tiles,
-                           nbl * 4, (int64_t)3, 4, V, M, g, rowpart, colpart, losspart, nullptr, nullptr);
-    else
-        hipLaunchKernelGGL((cal_tiles_kernel<false, false>), dim3(n_tiles, P), dim3(kThreads), 0, stream, Na, P,
-                           n_tiles, nbl * 4, (int64_t)3, 4, V, M, g, rowpart, colpart, losspart, nullptr, nullptr);
+    const bool weighted = fl || wt;
+#define AFC_CAL_TILES(REC, W)                                                                                       \
+    hipLaunchKernelGGL((cal_tiles_kernel<false, REC, W>), dim3(n_tiles, P), dim3(kThreads), 0, stream, Na, P,         \
+                       n_tiles, nbl * 4, (int64_t)3, 4, V, M, g, rowpart, colpart, losspart, nullptr, nullptr, fl, wt)
+    if (aligned16) {
+        if (weighted) AFC_CAL_TILES(true, true);
+        else AFC_CAL_TILES(true, false);
+    } else {
+        if (weighted) AFC_CAL_TILES(false, true);
+        else AFC_CAL_TILES(false, false);
+    }
+#undef AFC_CAL_TILES
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(cal_reduce_kernel<false>, dim3((unsigned)ceil_div(Na, 256), P, 2), dim3(256), 0, stream, Na, P,

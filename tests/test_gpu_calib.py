@@ -125,3 +125,48 @@ def test_grad_unaligned_records_match_aligned(afc, dev):
     assert Vt.data_ptr() % 16 == 0 and Mt.data_ptr() % 16 == 0
     assert torch.equal(la, lu) and torch.equal(ga, gu)
     _check(afc, dev, V, M, g)
+
+
+def _weights_case(rng, P, nbl, frac=0.2):
+    flags = (rng.random((P, nbl, 2)) < frac).astype(np.uint8)
+    wts = rng.uniform(0.25, 2.0, (P, nbl, 2)).astype(np.float32)
+    return flags, wts
+
+
+@pytest.mark.parametrize("Na,P,chans", [(70, 3, None), (576, 64, [0, 21, 63])])
+def test_weighted_grad_matches_oracle(afc, dev, Na, P, chans):
+    """Flags (weight 0) and lost-data weights: the weighted loss and gradient
+    against the oracle's weighted sums (same tolerances as unweighted)."""
+    log(f"weighted calibration Na={Na} P={P}")
+    V, M, g = W.make_calibration(Na=Na, P=P, seed=Na + 3)
+    nbl = Na * (Na + 1) // 2
+    flags, wts = _weights_case(np.random.default_rng(Na), P, nbl)
+    Vt, Mt, gt = (torch.from_numpy(a).to(dev) for a in (V, M, g))
+    loss, grad = afc.calibrate_grad(Vt, Mt, gt, flags=torch.from_numpy(flags).to(dev),
+                                    weights=torch.from_numpy(wts).to(dev))
+    torch.cuda.synchronize()
+    loss, grad = loss.cpu().numpy(), _cplx(grad.cpu().numpy())
+    chans = list(range(P)) if chans is None else chans
+    w = oracle.cal_weights(P, nbl, flags=flags, weights=wts)
+    lref, gref = oracle.cal_loss_grad(V[chans], M[chans], g[chans], weights=w[chans])
+    worst_l = worst_g = 0.0
+    for k, ch in enumerate(chans):
+        for pol in range(2):
+            worst_l = max(worst_l, abs(loss[ch, pol] - lref[k, pol]) / abs(lref[k, pol]))
+            gn = np.linalg.norm(gref[k, :, pol])
+            worst_g = max(worst_g, np.linalg.norm(grad[ch, :, pol] - gref[k, :, pol]) / gn)
+    log(f"  loss rel err {worst_l:.2e}, grad rel err {worst_g:.2e}")
+    assert worst_l <= 1e-5 and worst_g <= 1e-6
+
+
+def test_weighted_unit_weights_bit_identical(afc, dev):
+    """Weights of 1 and no flags give the unweighted call's bits."""
+    V, M, g = W.make_calibration(Na=40, P=4, seed=8)
+    Vt, Mt, gt = (torch.from_numpy(a).to(dev) for a in (V, M, g))
+    nbl = 40 * 41 // 2
+    l0, g0 = afc.calibrate_grad(Vt, Mt, gt)
+    l1, g1 = afc.calibrate_grad(Vt, Mt, gt, weights=torch.ones((4, nbl, 2), dtype=torch.float32, device=dev))
+    l2, g2 = afc.calibrate_grad(Vt, Mt, gt, flags=torch.zeros((4, nbl, 2), dtype=torch.uint8, device=dev))
+    torch.cuda.synchronize()
+    assert torch.equal(l0, l1) and torch.equal(g0, g1)
+    assert torch.equal(l0, l2) and torch.equal(g0, g2)

@@ -159,3 +159,63 @@ def test_apply_flags_then_solve_rejects_rfi(afc, dev):
     e_d = np.abs(dirty - clean).max()
     log(f"  |g_flagged - g_clean| = {e_f:.2e}, unflagged {e_d:.2e}")
     assert e_f < 0.02 and e_d > 10 * e_f
+
+
+def _solve_gpu_w(afc, dev, V, M, g0, n_iter, flags, wts):
+    g = torch.from_numpy(np.ascontiguousarray(np.stack([g0.real, g0.imag], -1).astype(np.float32))).to(dev)
+    loss = afc.calibrate_solve(torch.from_numpy(V).to(dev), torch.from_numpy(M).to(dev), g, n_iter,
+                               flags=None if flags is None else torch.from_numpy(flags).to(dev),
+                               weights=None if wts is None else torch.from_numpy(wts).to(dev))
+    torch.cuda.synchronize()
+    return _cplx(g.cpu().numpy()), loss.cpu().numpy()
+
+
+@pytest.mark.parametrize("Na,P,n_iter", [(24, 4, 40), (576, 64, 30)])
+def test_weighted_solver_matches_oracle(afc, dev, Na, P, n_iter):
+    """The weighted solver (flags and lost-data weights) against the
+    oracle's weighted alternating least squares; its loss against the
+    oracle's weighted loss at the returned gains."""
+    V, M, g = W.make_calibration(Na=Na, P=P, n_src=4, snr=20.0, seed=Na + 7)
+    nbl = Na * (Na + 1) // 2
+    rng = np.random.default_rng(Na)
+    flags = (rng.random((P, nbl, 2)) < 0.15).astype(np.uint8)
+    wts = rng.uniform(0.5, 1.5, (P, nbl, 2)).astype(np.float32)
+    g0 = np.ones((P, Na, 2), np.complex128)
+    log(f"weighted solve Na={Na} P={P} n_iter={n_iter}")
+    got, loss = _solve_gpu_w(afc, dev, V, M, g0, n_iter, flags, wts)
+    chs = list(range(P)) if P <= 4 else [0, 33, 63]
+    w = oracle.cal_weights(P, nbl, flags=flags, weights=wts)
+    ref = oracle.cal_solve(V[chs], M[chs], g0[chs], n_iter, weights=w[chs])
+    err = np.abs(got[chs] - ref).max() / np.abs(ref).max()
+    log(f"  max |g - g_oracle| / max |g| = {err:.2e}")
+    assert err <= 1e-5
+    gs = np.stack([got[chs].real, got[chs].imag], -1).astype(np.float32)
+    lref, _ = oracle.cal_loss_grad(V[chs], M[chs], gs, want_grad=False, weights=w[chs])
+    np.testing.assert_allclose(loss[chs], lref, rtol=1e-4, atol=1e-6 * max(1.0, lref.max()))
+
+
+def test_sigma_clip_flags_feed_weighted_solver(afc, dev):
+    """Flags straight from afc_sigma_clip into the weighted solver equal
+    zeroing the flagged V and M entries (afc_apply_vis_flags) before the
+    unweighted solver."""
+    Na, P = 32, 16
+    V, M, g = W.make_calibration(Na=Na, P=P, n_src=4, snr=50.0, seed=23)
+    rng = np.random.default_rng(24)
+    a, b = np.tril_indices(Na)
+    cross = np.flatnonzero(a != b)
+    for _ in range(30):
+        ch, bl, pol = rng.integers(P), rng.choice(cross), rng.integers(2)
+        V[ch, bl, pol, pol] = rng.standard_normal(2) * 5e3
+    Vt, Mt = torch.from_numpy(V).to(dev), torch.from_numpy(M).to(dev)
+    fl = afc.sigma_clip(Vt, 5.0)
+    g0 = np.ones((P, Na, 2), np.complex128)
+    gw, _ = _solve_gpu_w(afc, dev, V, M, g0, 40, fl.cpu().numpy(), None)
+    flags = fl.cpu().numpy()
+    assert flags.sum() > 0
+    Vz, Mz = V.copy(), M.copy()
+    for pol in range(2):
+        sel = flags[:, :, pol] != 0
+        Vz[:, :, pol, pol][sel] = 0
+        Mz[:, :, pol, pol][sel] = 0
+    gz, _ = _solve_gpu_w(afc, dev, Vz, Mz, g0, 40, None, None)
+    assert np.abs(gw - gz).max() <= 1e-6 * np.abs(gz).max()
