@@ -48,6 +48,9 @@ CASES = [
     # directly) with stage counts that are not a multiple of the register ring
     ("i8", 2, 150, 300, [300, 171], [7], range(0, 64, 13)),
     ("f16", 1, 150, 77, None, None, range(0, 64, 13)),
+    # one spectrum block (one real stage, the rest of the register ring padding)
+    ("i8", 2, 100, 8, [8, 1], [99], range(0, 64, 17)),
+    ("f16", 1, 100, 3, None, None, range(0, 64, 17)),
 ]
 
 
