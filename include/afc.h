@@ -341,8 +341,10 @@ AFC_API int afc_calibrate_solve(int32_t n_antennas, int32_t n_channels, const vo
  * w_ab = 0 where vis_flags is nonzero, else weights[...] (or 1 when weights
  * is NULL).  Both arrays are [P][Nbl][2] (channel, baseline, XX / YY), the
  * layout afc_sigma_clip writes; either may be NULL (both NULL = the
- * unweighted entry points, bit for bit).  Weights must be finite and >= 0
- * (finiteness is checked in checked mode; the sign is not checked).
+ * unweighted entry points, bit for bit).  vis_flags must be 2-byte and
+ * weights 8-byte aligned (AFC_ERR_INVALID otherwise).  Weights must be
+ * finite and >= 0 (finiteness is checked in checked mode; the sign is not
+ * checked).
  * All other arguments, the workspace sizes and the limits are those of
  * afc_calibrate_grad and afc_calibrate_solve.
  * ------------------------------------------------------------------------- */

@@ -387,6 +387,8 @@ AFC_API int afc_calibrate_grad_weighted(int32_t n_antennas, int32_t n_channels, 
     if (!V || !M || !g || !loss) return fail(AFC_ERR_INVALID, "NULL pointer (V, M, g or loss)");
     if (!workspace) return fail(AFC_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)",
                                 cal_workspace_bytes(n_antennas, n_channels));
+    if (reinterpret_cast<uintptr_t>(vis_flags) % 2 || reinterpret_cast<uintptr_t>(weights) % 8)
+        return fail(AFC_ERR_INVALID, "vis_flags must be 2-byte and weights 8-byte aligned");
     int rc = check_cal_inputs(n_antennas, n_channels, V, M, g, stream);
     if (rc != AFC_OK) return rc;
     if (weights) {
@@ -433,6 +435,8 @@ AFC_API int afc_calibrate_solve_weighted(int32_t n_antennas, int32_t n_channels,
     if (!V || !M || !g) return fail(AFC_ERR_INVALID, "NULL pointer (V, M or g)");
     if (!workspace) return fail(AFC_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)",
                                 cal_solve_workspace_bytes(n_antennas, n_channels));
+    if (reinterpret_cast<uintptr_t>(vis_flags) % 2 || reinterpret_cast<uintptr_t>(weights) % 8)
+        return fail(AFC_ERR_INVALID, "vis_flags must be 2-byte and weights 8-byte aligned");
     int rc = check_cal_inputs(n_antennas, n_channels, V, M, g, stream);
     if (rc != AFC_OK) return rc;
     if (weights) {

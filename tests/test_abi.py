@@ -72,6 +72,13 @@ def test_invalid_arguments_are_rejected_on_host(afc):
     assert lib.afc_correlate(C.byref(big), afc.AFC_I8, dummy, None, None, dummy, None, None) == -2
     assert lib.afc_calibrate_grad(48, 4, dummy, dummy, dummy, dummy, None, None, None) == -4
     assert lib.afc_calibrate_grad(0, 4, dummy, dummy, dummy, dummy, None, dummy, None) == -1
+    # weighted calibration: flags 2-byte and weights 8-byte aligned
+    f_odd, w_odd = C.c_void_p(0x1001), C.c_void_p(0x1004)
+    assert lib.afc_calibrate_grad_weighted(48, 4, dummy, dummy, f_odd, None, dummy, dummy, None, dummy, None) == -1
+    assert b"aligned" in lib.afc_last_error()
+    assert lib.afc_calibrate_solve_weighted(48, 4, dummy, dummy, None, w_odd, dummy, 5, None, dummy, None) == -1
+    assert b"aligned" in lib.afc_last_error()
+    assert lib.afc_calibrate_solve_weighted(48, 4, dummy, dummy, None, None, dummy, -1, None, dummy, None) == -1
     out = C.c_void_p()
     assert lib.afc_plan_create(C.byref(d), None, None, None, C.byref(out)) == -1
     assert not out.value
@@ -168,6 +175,10 @@ def test_binding_rejects_wrong_buffer_sizes_on_host(afc):
     _raises(afc, lambda: afc.calibrate_grad(_meta((P, nbl + 1, 2, 2, 2), torch.float32), V, g), "V shape")
     _raises(afc, lambda: afc.calibrate_grad(V, _meta((P - 1, nbl, 2, 2, 2), torch.float32), g), "M shape")
     _raises(afc, lambda: afc.calibrate_solve(V, V, _meta((P, Na, 2), torch.float32)), "g shape")
+    _raises(afc, lambda: afc.calibrate_grad(V, V, g, flags=_meta((P, nbl, 3), torch.uint8)), "flags shape")
+    _raises(afc, lambda: afc.calibrate_solve(V, V, g, weights=_meta((P, nbl + 1, 2), torch.float32)),
+            "weights shape")
+    _raises(afc, lambda: afc.calibrate_grad(V, V, g, weights=_meta((P, nbl, 2), torch.float64)), "float32")
     _raises(afc, lambda: afc.sigma_clip(V, out=_meta((P, nbl, 3), torch.uint8)), "out shape")
     _raises(afc, lambda: afc.apply_vis_flags(_meta((P, nbl, 2), torch.uint8), V=_meta((P, nbl, 2, 2), torch.float32)),
             "V shape")
