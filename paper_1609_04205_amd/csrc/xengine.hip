@@ -13,9 +13,12 @@
 // not fit int8).
 //
 // Work: one workgroup = one TILE x TILE tile (ti >= tj) of one channel of
-// one subband; 4 waves in 2 x 2, each owning (TILE/2)^2 outputs as 32 x 32
-// MFMA blocks.  Tiles wholly above the diagonal are never launched; inside a
-// diagonal tile the wave and the MFMA blocks above the diagonal are skipped.
+// one subband, 4 waves, outputs in 32 x 32 MFMA blocks.  128-wide int8 /
+// fp16 tiles: off the diagonal wave w owns column block w against the four
+// row blocks; a diagonal tile spreads its ten lower-triangle blocks 3/3/2/2
+// over the waves.  64-wide tiles and fp32: 2 x 2 waves of one quarter each,
+// the wave above the diagonal idle on a diagonal tile.  Tiles wholly above
+// the diagonal are never launched.
 // int8 / fp16: the row panel of a tile streams through LDS in stages of 2-4
 // spectrum blocks (direct global-to-LDS loads of the block layout
 // [block][receiver][8 spectra], XOR-swizzled 16-byte chunks so that the MFMA
