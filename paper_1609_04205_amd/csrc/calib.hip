@@ -12,6 +12,11 @@
 // Every stored element therefore feeds one row sum (antenna a) and one
 // column sum (antenna b).
 //
+// Weighted form (Sec. "Real-time Flagging, Calibration and Imaging": the
+// calibration works on the flagged visibilities, re-weighted for lost data):
+// L = sum_{a,b} w_ab |R_ab|^2 with a real weight w_ab = w_ba per stored
+// baseline and polarisation (0 where flagged), and t_ab = w_ab R_ab conj(M_ab).
+//
 // Pass 1: one workgroup per 64 x 64 antenna tile of the lower triangle and
 // channel, both polarisations.  Each thread owns 4 rows x 4 columns;
 // the residual is formed in float32 with error-free product and sum
