@@ -563,15 +563,16 @@ def _make_cal_loss():
     class CalLoss(torch.autograd.Function):
         """L[k][pol] = ||V - G M G^H||_F^2 with the hand-written adjoint kernel.
 
-        g is complex64 [P][Na][2]; V, M float32 [P][Nbl][2][2][2].  The
-        forward kernel computes the gradient together with the loss; the
-        backward scales it by the incoming gradient of each (channel, pol).
+        g is complex64 [P][Na][2]; V, M float32 [P][Nbl][2][2][2]; optional
+        flags / weights [P][Nbl][2] select the weighted loss.  The forward
+        kernel computes the gradient together with the loss; the backward
+        scales it by the incoming gradient of each (channel, pol).
         """
 
         @staticmethod
-        def forward(ctx, V, M, g):
+        def forward(ctx, V, M, g, flags=None, weights=None):
             gr = torch.view_as_real(g.contiguous())
-            loss, grad = calibrate_grad(V, M, gr, want_grad=True)
+            loss, grad = calibrate_grad(V, M, gr, want_grad=True, flags=flags, weights=weights)
             ctx.save_for_backward(torch.view_as_complex(grad))
             return loss
 
@@ -579,7 +580,7 @@ def _make_cal_loss():
         def backward(ctx, grad_out):
             (grad,) = ctx.saved_tensors
             gg = grad * grad_out.to(torch.float32)[:, None, :]
-            return None, None, gg
+            return None, None, gg, None, None
 
     return CalLoss
 
@@ -587,12 +588,13 @@ def _make_cal_loss():
 _cal_loss_cls = None
 
 
-def cal_loss(V, M, g):
-    """Differentiable calibration loss [P][2] (float64) with respect to complex g."""
+def cal_loss(V, M, g, flags=None, weights=None):
+    """Differentiable calibration loss [P][2] (float64) with respect to complex
+    g; with flags / weights the weighted loss."""
     global _cal_loss_cls
     if _cal_loss_cls is None:
         _cal_loss_cls = _make_cal_loss()
-    return _cal_loss_cls.apply(V, M, g)
+    return _cal_loss_cls.apply(V, M, g, flags, weights)
 
 
 @dataclass

@@ -170,3 +170,37 @@ def test_weighted_unit_weights_bit_identical(afc, dev):
     torch.cuda.synchronize()
     assert torch.equal(l0, l1) and torch.equal(g0, g1)
     assert torch.equal(l0, l2) and torch.equal(g0, g2)
+
+
+def test_weighted_autograd_matches_torch(afc, dev):
+    """cal_loss with flags and weights: backward equals torch autograd of
+    sum w_ab |R_ab|^2 in float64 on the CPU."""
+    Na, P = 20, 2
+    V, M, g = W.make_calibration(Na=Na, P=P, seed=27)
+    nbl = Na * (Na + 1) // 2
+    flags, wts = _weights_case(np.random.default_rng(28), P, nbl)
+    Vt, Mt = torch.from_numpy(V).to(dev), torch.from_numpy(M).to(dev)
+    gc = torch.view_as_complex(torch.from_numpy(g).to(dev)).clone().requires_grad_(True)
+    L = afc.cal_loss(Vt, Mt, gc, flags=torch.from_numpy(flags).to(dev), weights=torch.from_numpy(wts).to(dev))
+    L.sum().backward()
+    a, b = np.tril_indices(Na)
+    wfull = oracle.cal_weights(P, nbl, flags=flags, weights=wts)
+    ref_grad = np.zeros((P, Na, 2), np.complex128)
+    ref_loss = np.zeros((P, 2))
+    for k in range(P):
+        for pol in range(2):
+            Vf = np.zeros((Na, Na), np.complex128)
+            Mf = np.zeros((Na, Na), np.complex128)
+            Wf = np.zeros((Na, Na))
+            Vf[a, b] = _cplx(V[k, :, pol, pol]); Vf[b, a] = np.conj(Vf[a, b])
+            Mf[a, b] = _cplx(M[k, :, pol, pol]); Mf[b, a] = np.conj(Mf[a, b])
+            Wf[a, b] = wfull[k, :, pol]; Wf[b, a] = wfull[k, :, pol]
+            gt = torch.tensor(_cplx(g[k, :, pol]), requires_grad=True)
+            R = torch.tensor(Vf) - gt[:, None] * torch.tensor(Mf) * gt.conj()[None, :]
+            lk = (torch.tensor(Wf) * R.abs() ** 2).sum()
+            lk.backward()
+            ref_grad[k, :, pol] = gt.grad.numpy()
+            ref_loss[k, pol] = float(lk.detach())
+    np.testing.assert_allclose(L.detach().cpu().numpy(), ref_loss, rtol=1e-5)
+    got = gc.grad.cpu().numpy()
+    assert np.linalg.norm(got - ref_grad) / np.linalg.norm(ref_grad) <= 1e-6
