@@ -72,7 +72,7 @@ constexpr int kChunk = 768;                  // spectra per workgroup, a multipl
 constexpr int kTT = 18;                      // tap pairs per branch and part (t = 0..17, cyclic)
 
 // One workgroup: receivers [i0, i0+16) of one subband, spectra [s_begin, s_end).
-template <int DT, int kWaves>
+template <int DT, int kWaves, bool kOne>
 __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const float* __restrict__ taps,
                                          void* __restrict__ zs, const Tw64& tw, int N, int S, int Sb,
                                          int i0, int s_begin, int s_end, float gain, float2* lds,
@@ -316,7 +316,7 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
                         float2 y = a[4 * ga + de];
                         if constexpr (DT != AFC_I8)
                             if (!live) y = make_float2(0.0f, 0.0f);
-                        store_sample<DT>(zs, (int64_t)k * ch_stride, lane_zoff, y, gq);
+                        store_sample<DT, kOne>(zs, (int64_t)k * ch_stride, lane_zoff, y, gq);
                     }
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -341,7 +341,7 @@ __device__ __forceinline__ void ppf_body(const int16_t* __restrict__ xs, const f
     }
 }
 
-template <int DT>
+template <int DT, bool kOne>
 __global__ __launch_bounds__(64 * kWavesMain) void ppf_kernel(const int16_t* __restrict__ x, const float* __restrict__ taps,
                                                        void* __restrict__ z, Tw64 tw, int64_t x_sb_stride,
                                                        int64_t z_sb_bytes, int N, int S, int Sb, int n_groups,
@@ -358,11 +358,12 @@ __global__ __launch_bounds__(64 * kWavesMain) void ppf_kernel(const int16_t* __r
     const int sb = w / (n_groups * n_chunks);
     const int s_begin = chunk * kChunk;
     const int s_end = min(S, s_begin + kChunk);
-    ppf_body<DT, kWavesMain>(x + sb * x_sb_stride, taps, reinterpret_cast<char*>(z) + sb * z_sb_bytes, tw, N, S, Sb,
+    ppf_body<DT, kWavesMain, kOne>(x + sb * x_sb_stride, taps, reinterpret_cast<char*>(z) + sb * z_sb_bytes, tw, N, S, Sb,
                  grp * kNi, s_begin, s_end, gain, lds, ltp);
 }
 
 // Batched form: one launch over per-subband jobs with their own S, type and gain.
+template <bool kOne>
 __global__ __launch_bounds__(64 * kWavesBatched) void ppf_batched_kernel(const int16_t* __restrict__ x,
                                                               const float* __restrict__ taps, void* __restrict__ z,
                                                               Tw64 tw, const PpfItem* __restrict__ items,
@@ -384,11 +385,11 @@ __global__ __launch_bounds__(64 * kWavesBatched) void ppf_batched_kernel(const i
     const int16_t* xs = x + item.x_off;
     void* zs = reinterpret_cast<char*>(z) + item.z_off;
     if (item.dt == AFC_F32)
-        ppf_body<AFC_F32, kWavesBatched>(xs, taps, zs, tw, N, item.S, item.Sb, grp * kNi, s_begin, s_end, item.gain, lds, ltp);
+        ppf_body<AFC_F32, kWavesBatched, kOne>(xs, taps, zs, tw, N, item.S, item.Sb, grp * kNi, s_begin, s_end, item.gain, lds, ltp);
     else if (item.dt == AFC_F16)
-        ppf_body<AFC_F16, kWavesBatched>(xs, taps, zs, tw, N, item.S, item.Sb, grp * kNi, s_begin, s_end, item.gain, lds, ltp);
+        ppf_body<AFC_F16, kWavesBatched, kOne>(xs, taps, zs, tw, N, item.S, item.Sb, grp * kNi, s_begin, s_end, item.gain, lds, ltp);
     else
-        ppf_body<AFC_I8, kWavesBatched>(xs, taps, zs, tw, N, item.S, item.Sb, grp * kNi, s_begin, s_end, item.gain, lds, ltp);
+        ppf_body<AFC_I8, kWavesBatched, kOne>(xs, taps, zs, tw, N, item.S, item.Sb, grp * kNi, s_begin, s_end, item.gain, lds, ltp);
 }
 
 }  // namespace
@@ -401,20 +402,21 @@ hipError_t launch_ppf(const PpfLaunch& a, hipStream_t stream) {
     const int per_xcd = (int)ceil_div(total, 8);
     const dim3 grid((unsigned)(per_xcd * 8));
     const int64_t z_sb_bytes = a.z_sb_stride * sample_bytes(a.dt);
+    // one store descriptor per subband when its output is below 2^31 bytes
+    const bool one = (int64_t)kP * a.Sb * a.N * kSBlk * sample_bytes(a.dt) <= 0x7FFFFFFFLL;
+#define AFC_PPF_LAUNCH(DT)                                                                                       \
+    if (one)                                                                                                     \
+        hipLaunchKernelGGL((ppf_kernel<DT, true>), grid, dim3(64 * kWavesMain), 0, stream, a.x, a.taps, a.z, tw,  \
+                           a.x_sb_stride, z_sb_bytes, a.N, a.S, a.Sb, n_groups, n_chunks, total, per_xcd, a.gain); \
+    else                                                                                                         \
+        hipLaunchKernelGGL((ppf_kernel<DT, false>), grid, dim3(64 * kWavesMain), 0, stream, a.x, a.taps, a.z, tw, \
+                           a.x_sb_stride, z_sb_bytes, a.N, a.S, a.Sb, n_groups, n_chunks, total, per_xcd, a.gain);
     switch (a.dt) {
-        case AFC_F32:
-            hipLaunchKernelGGL(ppf_kernel<AFC_F32>, grid, dim3(64 * kWavesMain), 0, stream, a.x, a.taps, a.z, tw,
-                               a.x_sb_stride, z_sb_bytes, a.N, a.S, a.Sb, n_groups, n_chunks, total, per_xcd, a.gain);
-            break;
-        case AFC_F16:
-            hipLaunchKernelGGL(ppf_kernel<AFC_F16>, grid, dim3(64 * kWavesMain), 0, stream, a.x, a.taps, a.z, tw,
-                               a.x_sb_stride, z_sb_bytes, a.N, a.S, a.Sb, n_groups, n_chunks, total, per_xcd, a.gain);
-            break;
-        default:
-            hipLaunchKernelGGL(ppf_kernel<AFC_I8>, grid, dim3(64 * kWavesMain), 0, stream, a.x, a.taps, a.z, tw,
-                               a.x_sb_stride, z_sb_bytes, a.N, a.S, a.Sb, n_groups, n_chunks, total, per_xcd, a.gain);
-            break;
+        case AFC_F32: AFC_PPF_LAUNCH(AFC_F32) break;
+        case AFC_F16: AFC_PPF_LAUNCH(AFC_F16) break;
+        default: AFC_PPF_LAUNCH(AFC_I8) break;
     }
+#undef AFC_PPF_LAUNCH
     return hipGetLastError();
 }
 
@@ -428,8 +430,15 @@ hipError_t launch_ppf_batched(const int16_t* x, const float* taps, void* z_ws, c
     const int total = (int)total64;
     const int per_xcd = (int)ceil_div(total, 8);
     const dim3 grid((unsigned)(per_xcd * 8));
-    hipLaunchKernelGGL(ppf_batched_kernel, grid, dim3(64 * kWavesBatched), 0, stream, x, taps, z_ws, tw, items_dev, N,
-                       n_groups, n_chunks, total, per_xcd);
+    // one store descriptor per subband when the largest possible subband
+    // output (fp32 samples at the longest integration) is below 2^31 bytes
+    const bool one = (int64_t)kP * ceil_div(max_S, kSBlk) * N * kSBlk * 8 <= 0x7FFFFFFFLL;
+    if (one)
+        hipLaunchKernelGGL((ppf_batched_kernel<true>), grid, dim3(64 * kWavesBatched), 0, stream, x, taps, z_ws, tw,
+                           items_dev, N, n_groups, n_chunks, total, per_xcd);
+    else
+        hipLaunchKernelGGL((ppf_batched_kernel<false>), grid, dim3(64 * kWavesBatched), 0, stream, x, taps, z_ws, tw,
+                           items_dev, N, n_groups, n_chunks, total, per_xcd);
     return hipGetLastError();
 }
 

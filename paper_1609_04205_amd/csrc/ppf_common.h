@@ -73,30 +73,33 @@ __device__ __forceinline__ unsigned requant_bits(float y, float gain) {
 }
 
 // store at sample index base + off (base wave-uniform, off per lane) with a
-// buffer store: the channel base is scalar and the per-lane byte offset a
-// 32-bit value, so the store needs no vector address arithmetic (a channel
-// of samples is far below 2 GiB: one subband of input is bounded to 2^31
-// values).
-template <int DT>
+// buffer store, so the store needs no vector address arithmetic.  kOne: the
+// subband's whole output is below 2^31 bytes (checked by the launch), so one
+// buffer descriptor at the subband's output serves every channel, with the
+// channel's byte offset as the scalar offset (16 descriptors per lane job
+// otherwise cost SGPRs the kernels then spill).  Otherwise one descriptor
+// per channel (a channel of samples is far below 2 GiB: one subband of input
+// is bounded to 2^31 values).
+template <int DT, bool kOne>
 __device__ __forceinline__ void store_sample(void* zs, int64_t base, unsigned off, float2 y, float gain) {
     constexpr unsigned kB = DT == AFC_F32 ? 8 : DT == AFC_F16 ? 4 : 2;
 #if defined(__HIP_DEVICE_COMPILE__)
-    // raw buffer store: scalar base (this channel), per-lane 32-bit offset;
-    // non-temporal (cache policy bit 1: the samples are written once and
-    // not read again by this kernel)
+    // raw buffer store; non-temporal (cache policy bit 1: the samples are
+    // written once and not read again by this kernel)
     const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
-        reinterpret_cast<char*>(zs) + base * kB, (short)0, 0x7FFFFFFF, 0x00020000);
+        reinterpret_cast<char*>(zs) + (kOne ? 0 : base * kB), (short)0, 0x7FFFFFFF, 0x00020000);
+    const unsigned soff = kOne ? (unsigned)(base * kB) : 0u;
     if constexpr (DT == AFC_F32) {
         typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, y), r, off * kB, 0, 2);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, y), r, off * kB, soff, 2);
     } else if constexpr (DT == AFC_F16) {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, __floats2half2_rn(y.x, y.y)), r,
-                                                  off * kB, 0, 2);
+                                                  off * kB, soff, 2);
     } else {
         const unsigned qr = requant_bits(y.x, gain), qi = requant_bits(y.y, gain);
         // bytes: low = real, high = imaginary
         __builtin_amdgcn_raw_buffer_store_b16((unsigned short)__builtin_amdgcn_perm(qi, qr, 0x0c0c0400u), r,
-                                                  off * kB, 0, 2);
+                                                  off * kB, soff, 2);
     }
 #endif
 }

@@ -66,7 +66,7 @@ struct FineArgs {
     float gain;
 };
 
-template <int DT, bool kVec4>
+template <int DT, bool kVec4, bool kOne>
 __global__ __launch_bounds__(kThreadsF) void ppf_fine_kernel(FineArgs a, Tw64 tw64) {
     __shared__ __attribute__((aligned(16))) float2 lds[kQF * kQS];
     // rows padded by one element: the receivers' rows start in different banks
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(kThreadsF) void ppf_fine_kernel(FineArgs a, Tw64 tw
                             float2 y = c4[k3];
                             if constexpr (DT != AFC_I8)
                                 if (!live) y = make_float2(0.0f, 0.0f);
-                            store_sample<DT>(zs, (int64_t)(k2 + 16 * k3) * ch_stride, lane_zoff, y, g);
+                            store_sample<DT, kOne>(zs, (int64_t)(k2 + 16 * k3) * ch_stride, lane_zoff, y, g);
                         }
                     }
                 }
@@ -354,11 +354,17 @@ hipError_t launch_ppf_fine(const FineLaunch& l, hipStream_t stream) {
     const dim3 grid((unsigned)(a.per_xcd * 8));
     // 16-byte row loads need 16-byte aligned rows: N a multiple of 4
     const bool vec4 = l.N % 4 == 0;
+    // one store descriptor per subband when its output is below 2^31 bytes
+    const bool one = (int64_t)64 * l.Sb * l.N * kSBlk * sample_bytes(l.dt) <= 0x7FFFFFFFLL;
 #define AFC_FINE_LAUNCH(DT)                                                                                  \
-    if (vec4)                                                                                                \
-        hipLaunchKernelGGL((ppf_fine_kernel<DT, true>), grid, dim3(kThreadsF), 0, stream, a, tw64);           \
+    if (vec4 && one)                                                                                         \
+        hipLaunchKernelGGL((ppf_fine_kernel<DT, true, true>), grid, dim3(kThreadsF), 0, stream, a, tw64);     \
+    else if (vec4)                                                                                           \
+        hipLaunchKernelGGL((ppf_fine_kernel<DT, true, false>), grid, dim3(kThreadsF), 0, stream, a, tw64);    \
+    else if (one)                                                                                            \
+        hipLaunchKernelGGL((ppf_fine_kernel<DT, false, true>), grid, dim3(kThreadsF), 0, stream, a, tw64);    \
     else                                                                                                     \
-        hipLaunchKernelGGL((ppf_fine_kernel<DT, false>), grid, dim3(kThreadsF), 0, stream, a, tw64);
+        hipLaunchKernelGGL((ppf_fine_kernel<DT, false, false>), grid, dim3(kThreadsF), 0, stream, a, tw64);
     switch (l.dt) {
         case AFC_F32: AFC_FINE_LAUNCH(AFC_F32) break;
         case AFC_F16: AFC_FINE_LAUNCH(AFC_F16) break;

@@ -175,3 +175,31 @@ def test_f32_full_size_sampled(afc, dev):
         assert err <= 1e-5
     del x, z
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_output_above_2gib_per_subband(afc, dev, dtype):
+    """1152 antennas (2304 receivers), 3051 spectra: one subband's fp32 output
+    is 3.6 GB and fp16 1.8 GB.  Above 2^31 bytes the channeliser stores
+    through one buffer descriptor per channel instead of one per subband
+    (fp32 here); sampled receivers, every channel, against the oracle."""
+    cfg = W.Config("a24-1sb", 1152, 1, n_spectra=3051, sigma_n=32.0)
+    log(f"ppf {dtype} 2304 receivers, output {64 * 382 * 2304 * 8 * (8 if dtype == 'f32' else 4) / 1e9:.2f} GB")
+    x, taps, z = _run(afc, dev, cfg, dtype)
+    inputs = [0, 777, 1500, cfg.n_inputs - 1]
+    ref = oracle.ppf_subband(x[0].cpu().numpy(), taps, 64, 16, cfg.n_spectra, inputs=inputs)
+    zz = z[0].index_select(2, torch.tensor(inputs, device=dev))
+    got = zz.permute(0, 1, 3, 2, 4).reshape(64, -1, len(inputs), 2)[:, :cfg.n_spectra].float().cpu().numpy()
+    got = got[..., 0].astype(np.float64) + 1j * got[..., 1]
+    sigma = np.sqrt(np.mean(np.abs(ref) ** 2) / 2)
+    err = np.abs(got - ref).max() / sigma
+    log(f"  max err {err:.3e}")
+    if dtype == "f32":
+        assert err <= 1e-5
+    else:
+        # each component: fp16 rounding (2^-11 relative) + float32 error
+        for comp in (np.real, np.imag):
+            d = np.abs(comp(got) - comp(ref))
+            assert np.all(d <= 2.0 ** -11 * np.abs(comp(ref)) * 1.0001 + 2e-5 * sigma)
+    del x, z
+    torch.cuda.empty_cache()
