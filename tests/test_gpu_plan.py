@@ -113,6 +113,19 @@ def test_plan_f32_subbands(afc, dev):
     _run_plan(afc, dev, Na, [200, 64, 129], ["f32", "i8", "f32"], np.zeros((3, Na), np.uint8))
 
 
+def test_plan_large_subband_output(afc, dev):
+    """2304 receivers and 2000 spectra: a subband's channeliser output could
+    reach 2.4 GB in fp32, above 2^31 bytes, so the batched channeliser
+    stores through one buffer descriptor per channel; the plan equals the
+    plain path (whose int8 subband output, 0.6 GB, takes the per-subband
+    descriptor) bit for bit."""
+    log("plan 2304 receivers, 2000 spectra")
+    Na = 1152
+    flags = np.zeros((1, Na), np.uint8)
+    flags[0, [0, 600, 1151]] = 1
+    _run_plan(afc, dev, Na, [2000], ["i8"], flags, check_oracle=False)
+
+
 def test_plan_forced_small_tiles(afc, dev, tmp_path):
     """A tune cache entry selects 64-wide tiles at 4 workgroups per CU."""
     log("plan forced 64 tiles")
