@@ -48,6 +48,21 @@ def test_sizes(afc):
     assert afc._lib.afc_calibrate_workspace_bytes(0, 64) == 0
 
 
+def test_size_limits(afc):
+    """4096 antennas is the largest array; one subband holds below 2^31 int16
+    input values, so 4096 antennas allow 2032 spectra and not 2033."""
+    lib = afc._lib
+    ok = afc.dims(4096, 1, 2032)
+    assert lib.afc_channelised_bytes(C.byref(ok), afc.AFC_F32) == 64 * 254 * 8192 * 8 * 8
+    assert lib.afc_channelised_bytes(C.byref(afc.dims(4096, 1, 2033)), afc.AFC_F32) == 0
+    assert lib.afc_visibility_bytes(C.byref(afc.dims(4096, 1, 20))) == 64 * (4096 * 4097 // 2) * 32
+    assert lib.afc_visibility_bytes(C.byref(afc.dims(4097, 1, 20))) == 0
+    dummy = C.c_void_p(0x1000)          # never dereferenced: validation fails first
+    too_long = afc.dims(4096, 1, 2033)
+    assert lib.afc_channelise(C.byref(too_long), dummy, dummy, afc.AFC_F32, 1.0, dummy, None) == -2
+    assert b"2^31" in lib.afc_last_error()
+
+
 def test_invalid_arguments_are_rejected_on_host(afc):
     lib = afc._lib
     d = afc.dims(48, 1, 1024)
