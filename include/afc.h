@@ -488,7 +488,9 @@ AFC_API void afc_plan_destroy(afc_plan* p);
  *
  * afc_count_nonfinite  the count behind it, for any device buffer of n
  *                      values of the given type; *count (host) is written
- *                      after the stream has passed the count.
+ *                      after the stream has passed the count.  The count
+ *                      uses one device counter per GPU; counts from several
+ *                      host threads run one after another.
  * ------------------------------------------------------------------------- */
 typedef enum {
     AFC_VALUES_F32 = 0,

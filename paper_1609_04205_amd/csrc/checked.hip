@@ -76,6 +76,10 @@ bool checked_mode() { return g_checked.load() != 0; }
 hipError_t count_nonfinite(const void* p, size_t n, int kind, unsigned long long* count, hipStream_t stream) {
     *count = 0;
     if (n == 0) return hipSuccess;
+    // one counter per device: a count runs from its clear to its read-back
+    // (the stream is synchronised) before another thread may start one
+    static std::mutex busy;
+    std::lock_guard<std::mutex> hold(busy);
     unsigned long long* c = nullptr;
     hipError_t e = counter_address(&c);
     if (e != hipSuccess) return e;

@@ -41,6 +41,35 @@ def test_count_is_exact(afc, dev):
     assert afc.count_nonfinite(big) == 0
 
 
+def test_counts_from_two_threads(afc, dev):
+    """Two host threads count different buffers on streams of their own at
+    the same time (the count uses one device counter per GPU): every count is
+    its own buffer's."""
+    import threading
+    a = torch.zeros(1 << 22, device=dev)
+    a[::1000] = float("nan")
+    b = torch.zeros(1 << 22, dtype=torch.float16, device=dev)
+    b[::777] = float("inf")
+    want = {0: -(-(1 << 22) // 1000), 1: -(-(1 << 22) // 777)}
+    torch.cuda.synchronize()
+    wrong = []
+
+    def run(k, t):
+        s = torch.cuda.Stream(device=dev)
+        with torch.cuda.stream(s):
+            for _ in range(40):
+                got = afc.count_nonfinite(t)
+                if got != want[k]:
+                    wrong.append((k, got))
+
+    ths = [threading.Thread(target=run, args=(0, a)), threading.Thread(target=run, args=(1, b))]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    assert not wrong, wrong[:5]
+
+
 def test_checked_calls_refuse_non_finite_inputs(afc, dev, checked):
     assert afc.checked_mode()
     taps = torch.from_numpy(W.prototype_taps()).to(dev)
