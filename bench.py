@@ -210,14 +210,14 @@ def main():
     out["roofline"] = xe_roof if xe_ms >= ppf_ms else ppf_roof
     out["roofline_other"] = ppf_roof if xe_ms >= ppf_ms else xe_roof
     # complex MACs the int8 X-engine actually issues on MFMA: whole 128 x 128
-    # off-diagonal tiles, ten 32 x 32 blocks per diagonal tile; spectra padded
-    # to whole stages of 4 blocks of 8, and off the diagonal the stage count
-    # to a multiple of the 4-stage register ring
+    # off-diagonal tiles, 36 of the 64 16 x 16 blocks per diagonal tile;
+    # spectra padded to whole stages of 4 blocks of 8, and off the diagonal
+    # the stage count to a multiple of the 3-stage register ring
     T = -(-N // 128)
     nb = (S + 7) // 8
-    spectra_off = -(-nb // 16) * 16 * 8
+    spectra_off = -(-nb // 12) * 12 * 8
     spectra_diag = -(-nb // 4) * 4 * 8
-    computed = float(B) * P * (T * (T - 1) // 2 * 128 * 128 * spectra_off + T * 10 * 32 * 32 * spectra_diag)
+    computed = float(B) * P * (T * (T - 1) // 2 * 128 * 128 * spectra_off + T * 36 * 16 * 16 * spectra_diag)
     out["xengine_computed_cmac"] = computed
     out["xengine_useful_fraction"] = round(cmac / computed, 4)
     log(f"int8 step {ms_step:.3f} ms (ppf {ppf_ms:.3f}, xengine {xe_ms:.3f})")

@@ -13,23 +13,27 @@
 // not fit int8).
 //
 // Work: one workgroup = one TILE x TILE tile (ti >= tj) of one channel of
-// one subband, 4 waves, outputs in 32 x 32 MFMA blocks.  128-wide int8 /
-// fp16 tiles: off the diagonal wave w owns column block w against the four
-// row blocks; a diagonal tile spreads its ten lower-triangle blocks 3/3/2/2
-// over the waves.  64-wide tiles and fp32: 2 x 2 waves of one quarter each,
-// the wave above the diagonal idle on a diagonal tile.  Tiles wholly above
-// the diagonal are never launched.
-// int8 / fp16: the row panel of a tile streams through LDS in stages of 2-4
-// spectrum blocks (direct global-to-LDS loads of the block layout
+// one subband, 4 waves.  int8 / fp16 outputs are 16 x 16 MFMA blocks (on
+// noise-like operands the power limit lets these shapes run ~15% more
+// operations per second than the 32 x 32 ones, for the same operand bytes
+// per operation).  128-wide tiles: off the diagonal wave w owns column blocks
+// 2w, 2w+1 against the eight row blocks (128 x 32 outputs); a diagonal tile
+// gives wave w the column blocks w and 7-w, nine blocks on or below the
+// diagonal each.  64-wide tiles: four row blocks x column block w off the
+// diagonal, ten blocks split 3/3/2/2 on it.  fp32: 32 x 32 blocks, 2 x 2
+// waves of one quarter each, the wave above the diagonal idle on a diagonal
+// tile.  Tiles wholly above the diagonal are never launched.
+// int8 / fp16: the row panel of a tile streams through LDS in stages of one
+// MFMA k-step (direct global-to-LDS loads of the block layout
 // [block][receiver][8 spectra], XOR-swizzled 16-byte chunks so that the MFMA
 // operand reads are bank-conflict free); off the diagonal each wave loads
-// its own column block straight into registers.  fp32 stages both panels
+// its own column blocks straight into registers.  fp32 stages both panels
 // through registers into LDS.
 //
 // Sample types (gfx950 MFMA):
-//   int8  v_mfma_i32_32x32x32_i8  (16 spectra per K-step), exact int32 sums
-//   fp16  v_mfma_f32_32x32x16_f16 ( 8 spectra per K-step), fp32 sums
-//   fp32  v_mfma_f32_32x32x2_f32  ( 2 spectra per K-step), fp32 sums, summed
+//   int8  v_mfma_i32_16x16x64_i8  (32 spectra per k-step), exact int32 sums
+//   fp16  v_mfma_f32_16x16x32_f16 (16 spectra per k-step), fp32 sums
+//   fp32  v_mfma_f32_32x32x2_f32  ( 2 spectra per k-step), fp32 sums, summed
 //         in two levels (blocks of 64 spectra into a second accumulator) to
 //         keep the rounding error of 3051-term sums near 1e-7 relative
 #include <algorithm>
@@ -44,6 +48,7 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 typedef float v16f __attribute__((ext_vector_type(16)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 
 constexpr int kThreads = 256;
@@ -81,27 +86,34 @@ constexpr int prefetch_depth() { return 2; }
 // int8 and fp16 stage through direct global-to-LDS loads, fp32 through registers
 template <int DT>
 constexpr bool uses_dma() { return DT != AFC_F32; }
-#ifndef AFC_DMA_DEPTH
-#define AFC_DMA_DEPTH 3
+// stages of global-to-LDS loads in flight beyond the next one: one stage is
+// 32 spectra for int8 and 16 for fp16
+#ifndef AFC_I8_DMA_DEPTH
+#define AFC_I8_DMA_DEPTH 2
 #endif
-constexpr int kDmaDepth = AFC_DMA_DEPTH;      // stages of global-to-LDS loads in flight
+#ifndef AFC_F16_DMA_DEPTH
+#define AFC_F16_DMA_DEPTH 3
+#endif
+template <int DT>
+constexpr int dma_depth() { return DT == AFC_I8 ? AFC_I8_DMA_DEPTH : AFC_F16_DMA_DEPTH; }
 #ifndef AFC_XENGINE_BDIRECT
 #define AFC_XENGINE_BDIRECT 1
 #endif
 // off-diagonal square tiles load their B operands into registers (1) or
 // stage them through LDS with the A panel (0)
 constexpr bool kBDirect = AFC_XENGINE_BDIRECT != 0;
-// DMA ring: the stage being multiplied, the next one (already landed when
-// its first operands are read) and kDmaDepth - 1 further stages in flight,
-// plus the buffer being refilled
-constexpr int kDmaBuffers = kDmaDepth + 2;
+// DMA ring: the stage being multiplied, the next one (landed before its
+// operands are read) and dma_depth - 1 further stages in flight, plus the
+// buffer being refilled
+template <int DT>
+constexpr int dma_buffers() { return dma_depth<DT>() + 2; }
 template <int DT, int TILE>
 constexpr int lds_bytes() {
     // 128-wide int8 / fp16 tiles stage only the row panel (their column
     // operands are loaded into registers, or, on the diagonal, are the row
     // panel); the others stage both
     constexpr int panels = uses_dma<DT>() && TILE == 128 && kBDirect ? 1 : 2;
-    return (uses_dma<DT>() ? kDmaBuffers : 2) * panels * stage_blocks<DT, TILE>() * TILE * XT<DT>::RB;
+    return (uses_dma<DT>() ? dma_buffers<DT>() : 2) * panels * stage_blocks<DT, TILE>() * TILE * XT<DT>::RB;
 }
 
 // Workgroup barrier for the DMA pipeline: no memory fence (which would wait
@@ -150,12 +162,13 @@ __device__ __forceinline__ void wait_vmcnt() {
     __builtin_amdgcn_s_waitcnt((N & 15) | (((N >> 4) & 3) << 14) | 0x0F70);
 }
 
-// s_waitcnt vmcnt(PER * k) for a runtime k in [0, kDmaDepth - 1] (uniform)
-template <int PER>
+// s_waitcnt vmcnt(PER * k) for a runtime k in [0, DEPTH - 1] (uniform)
+template <int PER, int DEPTH>
 __device__ __forceinline__ void wait_vmcnt_runtime(int k) {
+    static_assert(DEPTH >= 1 && DEPTH <= 4, "DMA depth 1..4");
     if (k <= 0) wait_vmcnt<0>();
-    else if (k == 1 || kDmaDepth <= 2) wait_vmcnt<PER>();
-    else if (k == 2 || kDmaDepth <= 3) wait_vmcnt<(2 * PER < 63 ? 2 * PER : 63)>();
+    else if (k == 1 || DEPTH <= 2) wait_vmcnt<PER>();
+    else if (k == 2 || DEPTH <= 3) wait_vmcnt<(2 * PER < 63 ? 2 * PER : 63)>();
     else wait_vmcnt<(3 * PER < 63 ? 3 * PER : 63)>();
 }
 
@@ -229,123 +242,159 @@ __device__ __forceinline__ void tile_rc(int t, int& ti, int& tj) {
     tj = t - r * (r + 1) / 2;
 }
 
-// Work of one wave in an int8 / fp16 tile: NP blocks of 32 x 32 outputs,
-// block p pairing row block am[IA[p]] of panel A with column block
-// bn[IB[p]] of panel B (am, bn hold NA and NB block indices).
-struct JobRows4 {      // off-diagonal 128-tile: every row block x this wave's column block
-    static constexpr int NA = 4, NB = 1, NP = 4;
-    static constexpr int IA[8] = {0, 1, 2, 3}, IB[8] = {0, 0, 0, 0};
+// ---------------------------------------------------------------------------
+// int8 / fp16 tiles in 16 x 16 MFMA blocks (int8 16x16x64, fp16 16x16x32).
+//
+// One stage of the DMA ring is exactly one k-step (64 bytes of K per lane
+// group: int8 4 spectrum blocks, fp16 2).  A lane supplies row (or column)
+// lane % 16 and the 16-byte K chunk lane / 16; the output block leaves
+// column lane % 16, rows 4 (lane / 16) + 0..3 in the lane.
+//
+// Jobs: NP blocks pairing row operand IA[p] with column operand IB[p]; the
+// blocks of one row operand are consecutive, so that the operand's register
+// can take the next stage's value right after its last MFMA (a rolling
+// reload instead of a second operand set: the 128-tile's 8 x 2 job holds 128
+// accumulator registers).
+struct JobTab {
+    int IA[16], IB[16], AM[8], BN[2];
 };
-// diagonal 128-tile: its ten lower-triangle blocks (m >= n) split 3/3/2/2
-struct JobDiag0 {      // (0,0) (1,0) (2,0)
-    static constexpr int NA = 3, NB = 1, NP = 3;
-    static constexpr int IA[8] = {0, 1, 2, 0}, IB[8] = {0, 0, 0, 0};
-    static constexpr int AM[4] = {0, 1, 2, 0}, BN[2] = {0, 0};
+constexpr JobTab rows_by_cols(int na, int nb) {
+    JobTab t{};
+    int p = 0;
+    for (int i = 0; i < na; ++i)
+        for (int j = 0; j < nb; ++j) {
+            t.IA[p] = i;
+            t.IB[p] = j;
+            ++p;
+        }
+    for (int i = 0; i < na; ++i) t.AM[i] = i;
+    return t;
+}
+// diagonal 128-tile (8 x 8 blocks, 36 on or below the diagonal): wave w takes
+// column blocks w (rows w..7) and 7 - w (rows 7-w..7), 9 blocks each
+constexpr JobTab diag8(int w) {
+    JobTab t{};
+    int p = 0;
+    for (int i = w; i < 8; ++i) {
+        t.IA[p] = i - w;
+        t.IB[p] = 0;
+        ++p;
+        if (i >= 7 - w) {
+            t.IA[p] = i - w;
+            t.IB[p] = 1;
+            ++p;
+        }
+    }
+    for (int k = 0; k < 8 - w; ++k) t.AM[k] = w + k;
+    t.BN[0] = w;
+    t.BN[1] = 7 - w;
+    return t;
+}
+// diagonal 64-tile (4 x 4 blocks, 10 on or below the diagonal) split 3/3/2/2
+constexpr JobTab diag4(int w) {
+    JobTab t{};
+    if (w == 0) {          // (0,0) (1,0) (2,0)
+        t = rows_by_cols(3, 1);
+    } else if (w == 1) {   // (3,0) (1,1) (2,1)
+        t.IA[0] = 0, t.IB[0] = 0, t.IA[1] = 1, t.IB[1] = 1, t.IA[2] = 2, t.IB[2] = 1;
+        t.AM[0] = 3, t.AM[1] = 1, t.AM[2] = 2;
+        t.BN[0] = 0, t.BN[1] = 1;
+    } else if (w == 2) {   // (3,1) (2,2)
+        t.IA[0] = 0, t.IB[0] = 0, t.IA[1] = 1, t.IB[1] = 1;
+        t.AM[0] = 3, t.AM[1] = 2;
+        t.BN[0] = 1, t.BN[1] = 2;
+    } else {               // (3,2) (3,3)
+        t.IA[0] = 0, t.IB[0] = 0, t.IA[1] = 0, t.IB[1] = 1;
+        t.AM[0] = 3;
+        t.BN[0] = 2, t.BN[1] = 3;
+    }
+    return t;
+}
+template <int NA_, int NB_, int NP_, bool kDiag_, bool kDirectB_>
+struct Job16Base {
+    static constexpr int NA = NA_, NB = NB_, NP = NP_;
+    static constexpr bool kDiag = kDiag_, kDirectB = kDirectB_;
 };
-struct JobDiag1 {      // (3,0) (1,1) (2,1)
-    static constexpr int NA = 3, NB = 2, NP = 3;
-    static constexpr int IA[8] = {0, 1, 2, 0}, IB[8] = {0, 1, 1, 0};
-    static constexpr int AM[4] = {3, 1, 2, 0}, BN[2] = {0, 1};
+// off-diagonal 128-tile: all 8 row blocks x this wave's 2 column blocks
+struct Job16R8C2 : Job16Base<8, 2, 16, false, true> {
+    static constexpr JobTab T = rows_by_cols(8, 2);
 };
-struct JobDiag2 {      // (3,1) (2,2)
-    static constexpr int NA = 2, NB = 2, NP = 2;
-    static constexpr int IA[8] = {0, 1, 0, 0}, IB[8] = {0, 1, 0, 0};
-    static constexpr int AM[4] = {3, 2, 0, 0}, BN[2] = {1, 2};
+template <int W>
+struct Job16D8 : Job16Base<8 - W, 2, 9, true, false> {
+    static constexpr JobTab T = diag8(W);
 };
-struct JobDiag3 {      // (3,2) (3,3)
-    static constexpr int NA = 1, NB = 2, NP = 2;
-    static constexpr int IA[8] = {0, 0, 0, 0}, IB[8] = {0, 1, 0, 0};
-    static constexpr int AM[4] = {3, 0, 0, 0}, BN[2] = {2, 3};
+// off-diagonal 64-tile: all 4 row blocks x this wave's column block
+struct Job16R4C1 : Job16Base<4, 1, 4, false, false> {
+    static constexpr JobTab T = rows_by_cols(4, 1);
 };
-struct JobOne {        // 64-tile: one block per wave
-    static constexpr int NA = 1, NB = 1, NP = 1;
-    static constexpr int IA[8] = {0, 0, 0, 0}, IB[8] = {0, 0, 0, 0};
-};
-struct JobIdle {       // 64-tile, the wave above the diagonal
-    static constexpr int NA = 1, NB = 1, NP = 0;
-    static constexpr int IA[8] = {0, 0, 0, 0}, IB[8] = {0, 0, 0, 0};
+template <int W>
+struct Job16D4 : Job16Base<W == 0 ? 3 : W == 1 ? 3 : W == 2 ? 2 : 1, W == 0 ? 1 : 2, W < 2 ? 3 : 2, true, false> {
+    static constexpr JobTab T = diag4(W);
 };
 
-// One int8 / fp16 tile of one (subband, channel) for one wave's job.  All
-// waves of the workgroup stage the panels together; `z` points at channel ch
-// of subband sb.
-//
-// The row panel A is TILE receivers tall (rows ti*TILE ..), the column panel B
-// as wide (columns tj*TILE ..).  A stage buffer holds A then B; a diagonal
-// tile (ti == tj) stages A only and reads both operands from it.
+// the last block of job J that uses row operand i / column operand j
+template <class J>
+constexpr int last_use(int i) {
+    int last = -1;
+    for (int p = 0; p < J::NP; ++p)
+        if (J::T.IA[p] == i) last = p;
+    return last;
+}
+template <class J>
+constexpr int last_use_b(int j) {
+    int last = -1;
+    for (int p = 0; p < J::NP; ++p)
+        if (J::T.IB[p] == j) last = p;
+    return last;
+}
+
 template <int DT, int TILE, class J>
-__device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __restrict__ vis_ch,
-                                         int32_t* __restrict__ w_sb, const uint8_t* __restrict__ fl_sb,
-                                         int N, int Na, int S, int ti, int tj, bool write_weights,
-                                         char* lds_raw, const int (&am)[4], const int (&bn)[2]) {
+__device__ __forceinline__ void xtile_mm16(const char* __restrict__ z, char* __restrict__ vis_ch,
+                                           int32_t* __restrict__ w_sb, const uint8_t* __restrict__ fl_sb,
+                                           int N, int Na, int S, int ti, int tj, bool write_weights,
+                                           char* lds_raw, const int (&am)[8], const int (&bn)[2]) {
     using Tr = XT<DT>;
-    using acc_t = typename Tr::acc_t;
+    using acc_t = std::conditional_t<DT == AFC_I8, v4i, v4f>;
     using V = std::conditional_t<DT == AFC_I8, v4i, v8h>;
     constexpr int RB = Tr::RB, PLANES = Tr::PLANES, kStg = stage_blocks<DT, TILE>();
+    static_assert(kStg * RB == 64, "one stage is one 16 x 16 MFMA k-step");
     constexpr int PANEL = kStg * TILE * RB;                  // bytes of panel A in one stage
     constexpr int PANEL_B = PANEL;                           // bytes of panel B in one stage
     constexpr int CPT = kStg * TILE * PLANES / kThreads;     // 16-byte chunks of A per thread per stage
-    constexpr int CPT_B = CPT;                               // of B
+    constexpr int CPT_B = CPT;
     static_assert((kStg * TILE * PLANES) % kThreads == 0, "a stage must split evenly over the threads");
-    // k-steps per stage (int8: 16 spectra, fp16: 8 spectra each)
-    constexpr int NKK = DT == AFC_I8 ? kStg / 2 : kStg;
-    static_assert(NKK % 2 == 0, "k-steps per stage must be even");
     constexpr int NA = J::NA, NBO = J::NB, NP = J::NP;
-    constexpr int NB = kDmaBuffers;
-    // a stage buffer holds panel A and, where it is staged, panel B (not for
-    // the diagonal jobs, whose operands all come from panel A, nor for the
-    // direct-B form)
-    constexpr bool kDiagJob = std::is_same_v<J, JobDiag0> || std::is_same_v<J, JobDiag1> ||
-                              std::is_same_v<J, JobDiag2> || std::is_same_v<J, JobDiag3>;
-    // Off-diagonal square tiles take their B operands straight from global
-    // memory into registers: wave w alone uses column block w, so staging it
-    // through LDS bought no sharing and cost an LDS write and read per byte.
-    // The loads of a stage go out with that stage's A panel and land in a
-    // ring of RS register slots (the stage in use and kDmaDepth in flight).
-    constexpr bool BD = kBDirect && std::is_same_v<J, JobRows4>;
+    constexpr int kDmaDepth = dma_depth<DT>();
+    constexpr int NB = dma_buffers<DT>();
+    constexpr bool kDiagJob = J::kDiag;
+    // off-diagonal 128-tiles load their column operands straight into
+    // registers (each wave alone uses its two column blocks), in a ring of RS
+    // register slots: the stage in use and kDmaDepth in flight
+    constexpr bool BD = kBDirect && J::kDirectB;
     constexpr int RS = BD ? kDmaDepth + 1 : 1;
     static_assert(RS <= 4, "register ring of at most four stages");
-    constexpr int BUF = PANEL + (BD || kDiagJob ? 0 : PANEL_B);   // bytes of one stage buffer
+    constexpr int BUF = PANEL + (BD || kDiagJob ? 0 : PANEL_B);
 
-    const int tid = threadIdx.x, lane = tid & 63, lr = lane & 31, lh = lane >> 5;
+    const int tid = threadIdx.x, lane = tid & 63, lc = lane & 15, lg = lane >> 4;
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int i0 = ti * TILE, j0 = tj * TILE;
     const bool diag = ti == tj;
     const int nb = (S + kSBlk - 1) / kSBlk;
-    const int tail_valid = S - (nb - 1) * kSBlk;             // spectra in the last block
-    // stages, rounded up to a multiple of the register ring (the extra
-    // stages read the last block again and are masked to zero)
+    const int tail_valid = S - (nb - 1) * kSBlk;
     const int n_st = (nb + kStg * RS - 1) / (kStg * RS) * RS;
-    const int n_final = n_st - RS;                           // first stage of the final group
+    const int n_final = n_st - RS;
+    // this lane's K chunk: spectrum block lbl of the stage, plane q of it
+    const int lbl = DT == AFC_I8 ? lg : lg >> 1;
+    const int q = DT == AFC_I8 ? 0 : lg & 1;
 
-    acc_t accR[NP > 0 ? NP : 1], accI[NP > 0 ? NP : 1];
+    acc_t accR[NP], accI[NP];
 #pragma unroll
-    for (int p = 0; p < (NP > 0 ? NP : 1); ++p) {
+    for (int p = 0; p < NP; ++p) {
         accR[p] = acc_t{};
         accI[p] = acc_t{};
     }
-
-    // a panel of `rows` receivers holds block bl at bl * rows * RB
-    auto rd = [&](const char* panel, int rows, int bl, int row, int q) -> uint4 {
-        return *reinterpret_cast<const uint4*>(panel + bl * rows * RB + row * RB + ((q ^ swz<RB, PLANES>(row)) * 16));
-    };
-    // this wave's operands of k-step kk (unconditional, so that the LDS
-    // wait counts stay exact across branches); a diagonal tile's B operands
-    // come from panel A
-    // B operands loaded directly: [ring slot][k-step of the stage]
-    uint4 bdir[RS][BD ? NKK : 1];
-    auto load_ops = [&](auto slot_tag, const char* PA, const char* PB, int kk, uint4 (&oa)[NA], uint4 (&ob)[NBO]) {
-        constexpr int slot = decltype(slot_tag)::value;
-        const int bl = DT == AFC_I8 ? 2 * kk + lh : kk;
-        const int q = DT == AFC_I8 ? 0 : lh;
-#pragma unroll
-        for (int i = 0; i < NA; ++i) oa[i] = rd(PA, TILE, bl, am[i] * 32 + lr, q);
-        if constexpr (BD) {
-            ob[0] = bdir[slot][kk];
-        } else {
-#pragma unroll
-            for (int i = 0; i < NBO; ++i) ob[i] = rd(PB, TILE, bl, bn[i] * 32 + lr, q);
-        }
+    auto rd = [&](const char* panel, int row) -> uint4 {
+        return *reinterpret_cast<const uint4*>(panel + lbl * TILE * RB + row * RB + ((q ^ swz<RB, PLANES>(row)) * 16));
     };
     auto cvt = [](uint4 u) -> V {
         if constexpr (DT == AFC_I8) return v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w};
@@ -359,57 +408,14 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
                                                       (unsigned)jswap_f16((int)u.z), (unsigned)jswap_f16((int)u.w)));
     };
     auto op = [&](acc_t& acc, V x, V y) {
-        if constexpr (DT == AFC_I8) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(x, y, acc, 0, 0, 0);
-        else acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(x, y, acc, 0, 0, 0);
+        if constexpr (DT == AFC_I8) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(x, y, acc, 0, 0, 0);
+        else acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(x, y, acc, 0, 0, 0);
     };
-    // MFMAs of one k-step.  `mid` runs after the first block's two MFMAs
-    // have been issued (the scheduler may not move work across it): loads
-    // of the next operands issued there overlap the remaining MFMAs.
-    // MFMAs of one k-step from A operands oa and the prepared B operands
-    // (bv as loaded, bj J-swapped).  `mid1` runs after the first block's two
-    // MFMAs have been issued (it issues the next k-step's LDS reads), `mid2`
-    // after about half of the blocks (it masks and J-swaps the next k-step's
-    // B operands, whose reads have had those MFMAs to land), so that the
-    // VALU work of the next k-step overlaps this one's MFMAs instead of
-    // standing between two k-steps.  The scheduler may not move work across
-    // the fences.
-    constexpr int SPLIT = NP >= 4 ? NP / 2 + 1 : (NP > 1 ? NP - 1 : 1);
-    auto mma = [&](const uint4 (&oa)[NA], const V (&bv)[NBO], const V (&bj)[NBO], auto&& mid1, auto&& mid2) {
-        if constexpr (NP > 0) {
-            const V a0 = cvt(oa[J::IA[0]]);
-            op(accR[0], a0, bv[J::IB[0]]);
-            op(accI[0], a0, bj[J::IB[0]]);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        mid1();
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int p = 1; p < SPLIT && p < NP; ++p) {
-            const V a = cvt(oa[J::IA[p]]);
-            op(accR[p], a, bv[J::IB[p]]);
-            op(accI[p], a, bj[J::IB[p]]);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        mid2();
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int p = SPLIT; p < NP; ++p) {
-            const V a = cvt(oa[J::IA[p]]);
-            op(accR[p], a, bv[J::IB[p]]);
-            op(accI[p], a, bj[J::IB[p]]);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-    };
-    // zero the spectra >= S of this lane's operands of k-step kk of stage st
-    auto mask_tail_ops = [&](int st, int kk, uint4 (&a)[NA], uint4 (&b)[NBO]) {
-        const int blk = st * kStg + (DT == AFC_I8 ? 2 * kk + lh : kk);
-        const int q = DT == AFC_I8 ? 0 : lh;
+    // zero the spectra >= S of an operand chunk of stage st
+    auto mask_op = [&](int st, uint4& v) {
+        const int blk = st * kStg + lbl;
         if (blk < nb - 1 || (blk == nb - 1 && tail_valid == kSBlk)) return;
-        const int valid = blk == nb - 1 ? tail_valid : 0;
-#pragma unroll
-        for (int i = 0; i < NA; ++i) a[i] = mask_tail<DT>(a[i], q, valid);
-#pragma unroll
-        for (int i = 0; i < NBO; ++i) b[i] = mask_tail<DT>(b[i], q, valid);
+        v = mask_tail<DT>(v, q, blk == nb - 1 ? tail_valid : 0);
     };
 
     // Samples go straight from global memory to LDS (buffer loads with the
@@ -417,238 +423,238 @@ __device__ __forceinline__ void xtile_mm(const char* __restrict__ z, char* __res
     // of NB stage buffers.  Buffer rather than global loads: the compiler
     // must assume that global (flat) ones may also touch LDS and would then
     // wait for every LDS read at once.  Rows beyond N read row N-1 (they only
-    // feed outputs that are never stored); in the last stage, blocks beyond
-    // the data read the last block again, and the operands of the partial
-    // last block are masked in registers.
+    // feed outputs that are never stored); blocks beyond the data read the
+    // last block again, and the operands of the partial last block are
+    // masked in registers.
     //
-    // One barrier per stage st, placed before its last k-step: by then stage
-    // st+1 has landed (each wave waits for its own loads first) and every
-    // wave has finished stage st-1, so the loads of stage st+1+kDmaDepth
-    // refill st-1's buffer, and the first operands of st+1 are read while the
-    // last MFMAs of st run.  Operands are double-buffered one k-step ahead.
-    //
-    // Offsets within the channel: voffset = this thread's chunk in stage 0,
-    // soffset = the stage (a channel of samples is far below 2 GiB: the entry
-    // points bound one subband of input to 2^31 values).
+    // One barrier per stage, after the stage's first MFMAs: by then every
+    // wave has waited for its own loads of the next stage and has finished
+    // the previous stage, so the DMA of stage st + 1 + depth refills the
+    // previous stage's buffer and the next stage's operands may be read.
     const int z_bytes = nb * N * RB;
-    // source offset of chunk c of a panel of `rows` receivers starting at r0
-    auto chunk_src = [&](int c, int rows, int r0) {
+    auto chunk_src = [&](int c, int r0) {
         const int chunk = tid + c * kThreads;
-        const int bl = chunk / (rows * PLANES);
-        const int rem = chunk % (rows * PLANES);
+        const int bl = chunk / (TILE * PLANES);
+        const int rem = chunk % (TILE * PLANES);
         const int row = rem / PLANES, sl = rem % PLANES;
-        const int q = sl ^ swz<RB, PLANES>(row);
-        return (bl * N + min(r0 + row, N - 1)) * RB + q * 16;
+        const int qq = sl ^ swz<RB, PLANES>(row);
+        return (bl * N + min(r0 + row, N - 1)) * RB + qq * 16;
     };
     int src_a[CPT], src_b[CPT_B];
 #pragma unroll
-    for (int c = 0; c < CPT; ++c) src_a[c] = chunk_src(c, TILE, i0);
+    for (int c = 0; c < CPT; ++c) src_a[c] = chunk_src(c, i0);
 #pragma unroll
-    for (int c = 0; c < CPT_B; ++c) src_b[c] = chunk_src(c, TILE, j0);
+    for (int c = 0; c < CPT_B; ++c) src_b[c] = chunk_src(c, j0);
     const int stage_bytes = kStg * N * RB;
-    auto issue_panel = [&](int st, char* panel, int c, int src, int rows) {
+    // A stage whose blocks all lie in the data takes its offset as the
+    // scalar part of the load; past the end (the last stages) the block is
+    // clamped to nb - 1 per lane.  Only the offsets sit behind the (uniform)
+    // branch, not the loads.
+    // kClamp: the stage may lie past the end (not for the main loop's loads)
+    auto issue_panel = [&](auto clamp_tag, int st, char* panel, int c, int src) {
         char* dst = panel + (c * kThreads + wid * 64) * 16;
-        const int bl = (tid + c * kThreads) / (rows * PLANES);
-        if constexpr (BD) {           // branch-free: block clamped to nb - 1 in voffset
-            buffer_load_lds16(z, z_bytes, dst, src + (min(st * kStg + bl, nb - 1) - bl) * N * RB, 0);
-            return;
-        }
         int voff = src, soff = st * stage_bytes;
-        if ((st + 1) * kStg > nb) {   // past the end (uniform): whole offset in voffset, block clamped to nb - 1
+        if (decltype(clamp_tag)::value && (st + 1) * kStg > nb) {
+            const int bl = (tid + c * kThreads) / (TILE * PLANES);
             voff += (min(st * kStg + bl, nb - 1) - bl) * N * RB;
             soff = 0;
         }
         buffer_load_lds16(z, z_bytes, dst, voff, soff);
     };
-    // this lane's B row and, per k-step of a stage, its block and chunk
-    const int b_row = min(j0 + bn[0] * 32 + lr, N - 1);
-    auto issue = [&](auto slot_tag, int st) {
+    // the column operands' per-lane offsets within a stage
+    int b_off[NBO];
+#pragma unroll
+    for (int x = 0; x < NBO; ++x) b_off[x] = (lbl * N + min(j0 + bn[x] * 16 + lc, N - 1)) * RB + q * 16;
+    uint4 bdir[RS][BD ? NBO : 1];
+    auto issue_b = [&](auto clamp_tag, auto slot_tag, int st) {
         constexpr int slot = decltype(slot_tag)::value;
+        int soff = st * stage_bytes, dv = 0;
+        if (decltype(clamp_tag)::value && (st + 1) * kStg > nb) {
+            dv = (min(st * kStg + lbl, nb - 1) - lbl) * N * RB;
+            soff = 0;
+        }
+#pragma unroll
+        for (int x = 0; x < NBO; ++x) bdir[slot][x] = buffer_load16(z, z_bytes, b_off[x] + dv, soff);
+    };
+    auto issue_a = [&](auto clamp_tag, int st) {
         char* buf = lds_raw + (st % NB) * BUF;
 #pragma unroll
-        for (int c = 0; c < CPT; ++c) issue_panel(st, buf, c, src_a[c], TILE);
-        if constexpr (BD) {
-            // no branch around these loads (the compiler's wait counts for
-            // their registers stay exact): the block index is clamped to
-            // nb - 1 arithmetically
+        for (int c = 0; c < CPT; ++c) issue_panel(clamp_tag, st, buf, c, src_a[c]);
+        if constexpr (!BD) {
+            if (!diag) {
 #pragma unroll
-            for (int kk = 0; kk < NKK; ++kk) {
-                const int lbl = DT == AFC_I8 ? 2 * kk + lh : kk;
-                const int q = DT == AFC_I8 ? 0 : lh;
-                const int blk = min(st * kStg + lbl, nb - 1);
-                bdir[slot][kk] = buffer_load16(z, z_bytes, (blk * N + b_row) * RB + q * 16, 0);
+                for (int c = 0; c < CPT_B; ++c) issue_panel(clamp_tag, st, buf + PANEL, c, src_b[c]);
             }
-        } else if (!diag) {
-#pragma unroll
-            for (int c = 0; c < CPT_B; ++c) issue_panel(st, buf + PANEL, c, src_b[c], TILE);
         }
     };
-    // wait until this wave's loads of stage s have landed, given that the
-    // stages up to min(s + kDmaDepth - 1, n_st - 1) have been issued
+    auto issue = [&](auto slot_tag, int st) {
+        issue_a(std::true_type{}, st);
+        if constexpr (BD) issue_b(std::true_type{}, slot_tag, st);
+    };
     auto wait_landed = [&](int s) {
         const int later = min(n_st - 1 - s, kDmaDepth - 1);
-        if (diag) wait_vmcnt_runtime<CPT>(later);
-        else wait_vmcnt_runtime<CPT + CPT_B>(later);
+        if (diag) wait_vmcnt_runtime<CPT, kDmaDepth>(later);
+        else wait_vmcnt_runtime<CPT + CPT_B, kDmaDepth>(later);
     };
-    // the same for the direct-B form, where `later` is known at compile time
-    auto wait_landed_bd = [&](auto later_tag) {
-        wait_vmcnt<(CPT + NKK) * decltype(later_tag)::value>();
-    };
-    auto panels = [&](int st, const char*& PA, const char*& PB) {
-        const char* buf = lds_raw + (st % NB) * BUF;
-        PA = buf;
-        PB = diag ? buf : buf + PANEL;
-    };
-    // operand set kk & 1 holds k-step kk of the current stage; the last
-    // stage is peeled off so that the loop body has no branch around LDS
-    // reads and the compiler's LDS wait counts stay exact
-    uint4 oa[2][NA], ob[2][NBO];
-    V bv[2][NBO], bj[2][NBO];
-    // B operands of slot `slot` as MFMA values: as loaded and J-swapped
-    auto prep = [&](uint4 (&b)[NBO], V (&v)[NBO], V (&j)[NBO]) {
+    auto wait_landed_bd = [&](auto later_tag) { wait_vmcnt<(CPT + NBO) * decltype(later_tag)::value>(); };
+    auto buf_a = [&](int st) -> const char* { return lds_raw + (st % NB) * BUF; };
+    auto buf_b = [&](int st) -> const char* { return lds_raw + (st % NB) * BUF + (diag ? 0 : PANEL); };
+
+    // this stage's operands: rows as read, columns as read and J-swapped;
+    // each is replaced by the next stage's right after its last MFMA
+    uint4 a_op[NA];
+    V bv[NBO], bj[NBO];
+    uint4 b_raw[NBO];                  // the next stage's columns as read (LDS-staged forms)
+    auto read_b = [&](int st) {
 #pragma unroll
-        for (int i = 0; i < NBO; ++i) {
-            v[i] = cvt(b[i]);
-            j[i] = jsw(b[i]);
-        }
+        for (int x = 0; x < NBO; ++x) b_raw[x] = rd(buf_b(st), bn[x] * 16 + lc);
     };
-    // stage st (using register slot R of the direct B ring); the stages of
-    // the final group mask the operands of blocks at or past the partial one
-    auto run_stage = [&](auto r_tag, int st, auto has_next_tag, auto mask_tag) {
+
+    // stage st in ring slot R; kMask: the stage is in the final group (its
+    // wait counts are those of the last stages); kMaskNext: the operands it
+    // loads for stage st + 1 may hold blocks at or past the partial one
+    auto run_stage = [&](auto r_tag, int st, auto has_next_tag, auto mask_tag, auto mask_next_tag, auto clamp_tag) {
         constexpr int R = decltype(r_tag)::value;
-        constexpr int RN = (R + 1) % RS;                     // slot of stage st + 1
+        constexpr int RN = (R + 1) % RS;
         constexpr bool kNext = decltype(has_next_tag)::value;
         constexpr bool kMask = decltype(mask_tag)::value;
-        const char *PA, *PB;
-        panels(st, PA, PB);
-#pragma unroll
-        for (int kk = 0; kk + 1 < NKK; ++kk) {
-            mma(oa[kk & 1], bv[kk & 1], bj[kk & 1],
-                [&] { load_ops(r_tag, PA, PB, kk + 1, oa[(kk + 1) & 1], ob[(kk + 1) & 1]); },
-                [&] {
-                    if constexpr (kMask) mask_tail_ops(st, kk + 1, oa[(kk + 1) & 1], ob[(kk + 1) & 1]);
-                    prep(ob[(kk + 1) & 1], bv[(kk + 1) & 1], bj[(kk + 1) & 1]);
-                });
-        }
-        mma(oa[(NKK - 1) & 1], bv[(NKK - 1) & 1], bj[(NKK - 1) & 1],
-            [&] {
-                if constexpr (kNext) {
-                    if constexpr (BD) {
-                        // stages issued after st + 1: kDmaDepth - 1 before
-                        // the final group, RS - 2 - R inside it
-                        wait_landed_bd(std::integral_constant<int, kMask ? RS - 2 - R : kDmaDepth - 1>{});
-                        dma_barrier();
-                        // stage st + 1 + kDmaDepth reuses this stage's slot
-                        // R; it exists exactly for the stages before the
-                        // final group
-                        if constexpr (!kMask) issue(r_tag, st + 1 + kDmaDepth);
-                    } else {
-                        wait_landed(st + 1);
-                        dma_barrier();
-                        if (st + 1 + kDmaDepth < n_st) issue(r_tag, st + 1 + kDmaDepth);
-                    }
-                    const char *NA_, *NB_;
-                    panels(st + 1, NA_, NB_);
-                    load_ops(std::integral_constant<int, RN>{}, NA_, NB_, 0, oa[0], ob[0]);
+        constexpr bool kMaskNext = decltype(mask_next_tag)::value;
+        static_for<NP>([&](auto p_tag) {
+            constexpr int p = decltype(p_tag)::value;
+            constexpr int ia = J::T.IA[p], ib = J::T.IB[p];
+            const V av = cvt(a_op[ia]);
+            op(accR[p], av, bv[ib]);
+            op(accI[p], av, bj[ib]);
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (kNext && p == 0) {
+                // stage st + 1 has landed for every wave, and every wave has
+                // finished stage st - 1, whose buffer the next DMA refills
+                if constexpr (BD) {
+                    // (clamped: the count is formed even where the branch
+                    // is discarded, on the last stage)
+                    constexpr int later = kMask ? (RS - 2 - R > 0 ? RS - 2 - R : 0) : kDmaDepth - 1;
+                    wait_landed_bd(std::integral_constant<int, later>{});
+                    dma_barrier();
+                    if constexpr (!kMask) issue_a(clamp_tag, st + 1 + kDmaDepth);
+                } else {
+                    wait_landed(st + 1);
+                    dma_barrier();
+                    if (st + 1 + kDmaDepth < n_st) issue_a(clamp_tag, st + 1 + kDmaDepth);
+                    read_b(st + 1);
                 }
-            },
-            [&] {
-                if constexpr (kNext) {
-                    if (st + 1 >= n_final) mask_tail_ops(st + 1, 0, oa[0], ob[0]);
-                    prep(ob[0], bv[0], bj[0]);
-                }
-            });
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if constexpr (kNext && last_use<J>(ia) == p) {
+                a_op[ia] = rd(buf_a(st + 1), am[ia] * 16 + lc);
+                if constexpr (kMaskNext) mask_op(st + 1, a_op[ia]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if constexpr (kNext && last_use_b<J>(ib) == p) {
+                uint4 u = BD ? bdir[RN][ib] : b_raw[ib];
+                if constexpr (kMaskNext) mask_op(st + 1, u);
+                bv[ib] = cvt(u);
+                bj[ib] = jsw(u);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            // the column loads of stage st + 1 + kDmaDepth go into this
+            // stage's ring slot once its last MFMA is issued, so that the
+            // operands can be used from the slot itself
+            if constexpr (BD && kNext && !kMask && p == NP - 1) {
+                issue_b(clamp_tag, r_tag, st + 1 + kDmaDepth);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        });
     };
-    // scalar loads still in flight would turn every LDS wait in the loop
-    // into lgkmcnt(0): settle them here
     __builtin_amdgcn_s_waitcnt(0xC07F);
     static_for<kDmaDepth>([&](auto d) {
-        // (the direct-B form always has at least RS stages)
         if (BD || d < n_st) issue(std::integral_constant<int, decltype(d)::value % RS>{}, d);
     });
     if constexpr (BD) wait_landed_bd(std::integral_constant<int, kDmaDepth - 1>{});
     else wait_landed(0);
     dma_barrier();
     if (BD || kDmaDepth < n_st) issue(std::integral_constant<int, kDmaDepth % RS>{}, kDmaDepth);
-    {
-        const char *PA, *PB;
-        panels(0, PA, PB);
-        load_ops(std::integral_constant<int, 0>{}, PA, PB, 0, oa[0], ob[0]);
-        if (n_final == 0) mask_tail_ops(0, 0, oa[0], ob[0]);
-        prep(ob[0], bv[0], bj[0]);
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        a_op[i] = rd(buf_a(0), am[i] * 16 + lc);
+        if (n_final == 0) mask_op(0, a_op[i]);
     }
-    // the stage loop is unrolled by the ring size so that every slot index
-    // is a constant; the final RS stages are peeled off
-    for (int st = 0; st < n_final; st += RS)
-        static_for<RS>([&](auto r) { run_stage(r, st + r, std::true_type{}, std::false_type{}); });
+    if constexpr (!BD) read_b(0);
+#pragma unroll
+    for (int x = 0; x < NBO; ++x) {
+        uint4 u = BD ? bdir[0][x] : b_raw[x];
+        if (n_final == 0) mask_op(0, u);
+        bv[x] = cvt(u);
+        bj[x] = jsw(u);
+    }
+    // main loop, then the group that ends with the stage loading the first
+    // stage of the final group (all stages before the final group hold whole
+    // blocks), then the final group
+    for (int st = 0; st < n_final - RS; st += RS)
+        static_for<RS>([&](auto r) {
+            run_stage(r, st + r, std::true_type{}, std::false_type{}, std::false_type{}, std::false_type{});
+        });
+    if (n_final >= RS)
+        static_for<RS>([&](auto r) {
+            run_stage(r, n_final - RS + r, std::true_type{}, std::false_type{},
+                      std::integral_constant<bool, (decltype(r)::value + 1 == RS)>{}, std::true_type{});
+        });
     static_for<RS>([&](auto r) {
-        run_stage(r, n_final + r, std::integral_constant<bool, (decltype(r)::value + 1 < RS)>{}, std::true_type{});
+        run_stage(r, n_final + r, std::integral_constant<bool, (decltype(r)::value + 1 < RS)>{}, std::true_type{},
+                  std::true_type{}, std::true_type{});
     });
     lds_barrier();
 
-    // ---- epilogue: 2x2 polarisation blocks of antennas a >= b
-    if constexpr (NP > 0) {
-        // flags of this lane's row antennas (8 per row block) and column
-        // antennas, fetched together before the stores
-        bool frow[NA][8], fcol[NBO];
+    // ---- epilogue: 2 x 2 polarisation blocks of antennas a >= b.  Rows
+    // 4 (lane / 16) + {0, 1} and {2, 3} of a lane are the two polarisations
+    // of two antennas, lanes lc, lc ^ 1 the two of one antenna b: a lane pair
+    // holds the four values of a baseline, swaps one value so that the even
+    // lane owns (p, q) = (0, 0), (0, 1) and the odd lane (1, 0), (1, 1), and
+    // each lane stores 16 contiguous bytes.
+    bool frow[NA][2], fcol[NBO];
 #pragma unroll
-        for (int i = 0; i < NBO; ++i) fcol[i] = false;
+    for (int x = 0; x < NBO; ++x) fcol[x] = false;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) frow[i][0] = frow[i][1] = false;
+    if (fl_sb) {
+        uint8_t fc[NBO], fr[NA][2];
+#pragma unroll
+        for (int x = 0; x < NBO; ++x) fc[x] = fl_sb[min(j0 + bn[x] * 16 + lc, N - 1) >> 1];
 #pragma unroll
         for (int i = 0; i < NA; ++i)
 #pragma unroll
-            for (int k = 0; k < 8; ++k) frow[i][k] = false;
-        if (fl_sb) {
-            uint8_t fc[NBO], fr[NA][8];
+            for (int k = 0; k < 2; ++k) fr[i][k] = fl_sb[min(i0 + am[i] * 16 + 4 * lg + 2 * k, N - 1) >> 1];
 #pragma unroll
-            for (int i = 0; i < NBO; ++i) fc[i] = fl_sb[min(j0 + bn[i] * 32 + lr, N - 1) >> 1];
+        for (int x = 0; x < NBO; ++x) fcol[x] = fc[x] != 0;
 #pragma unroll
-            for (int i = 0; i < NA; ++i)
+        for (int i = 0; i < NA; ++i)
 #pragma unroll
-                for (int k = 0; k < 8; ++k)
-                    fr[i][k] = fl_sb[min(i0 + am[i] * 32 + 8 * (k >> 1) + 4 * lh + 2 * (k & 1), N - 1) >> 1];
+            for (int k = 0; k < 2; ++k) frow[i][k] = fr[i][k] != 0;
+    }
+    using E = std::conditional_t<DT == AFC_I8, int, float>;
+    const bool odd = (lc & 1) != 0;
 #pragma unroll
-            for (int i = 0; i < NBO; ++i) fcol[i] = fc[i] != 0;
+    for (int p = 0; p < NP; ++p) {
+        const int ia = J::T.IA[p], ib = J::T.IB[p];
+        const int Jc = j0 + bn[ib] * 16 + lc;
+        const int b = Jc >> 1;
 #pragma unroll
-            for (int i = 0; i < NA; ++i)
-#pragma unroll
-                for (int k = 0; k < 8; ++k) frow[i][k] = fr[i][k] != 0;
-        }
-        // Rows r, r + 1 of a lane are the two polarisations of one antenna a
-        // and lanes lr, lr ^ 1 the two of one antenna b, so a lane pair holds
-        // the four values of baseline (a, b).  The pair swaps one value so
-        // that the even lane owns (p, q) = (0, 0), (0, 1) and the odd lane
-        // (1, 0), (1, 1): each lane then stores 16 contiguous bytes and the
-        // pair the whole 32-byte baseline.  Validity, flags and the antenna
-        // indices are uniform over the pair.
-        using E = std::conditional_t<DT == AFC_I8, int, float>;
-        const bool odd = (lr & 1) != 0;
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            const int Jc = j0 + bn[J::IB[p]] * 32 + lr;
-            const int b = Jc >> 1;
-            const bool fb = fcol[J::IB[p]];
-#pragma unroll
-            for (int r = 0; r < 16; r += 2) {
-                const E r0 = accR[p][r], i0v = accI[p][r], r1 = accR[p][r + 1], i1v = accI[p][r + 1];
-                // the even lane sends its p = 1 values, the odd lane its p = 0 values
-                const E yr = pair_swap(odd ? r0 : r1), yi = pair_swap(odd ? i0v : i1v);
-                E o0 = odd ? yr : r0, o1 = odd ? yi : i0v, o2 = odd ? r1 : yr, o3 = odd ? i1v : yi;
-                const int I = i0 + am[J::IA[p]] * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
-                const int a = I >> 1;
-                if (Jc >= N || I >= N || a < b) continue;
-                if (a == b) {             // inputs equal for (0, 0) and (1, 1)
-                    if (odd) o3 = E(0);
-                    else o1 = E(0);
-                }
-                const bool flagged = fb || frow[J::IA[p]][((r >> 2) << 1) | ((r >> 1) & 1)];
-                if (flagged) o0 = o1 = o2 = o3 = E(0);
-                const int64_t bl = (int64_t)a * (a + 1) / 2 + b;
-                // written once and not read again by this kernel: a streaming
-                // (non-temporal) store
-                typedef E ev4 __attribute__((ext_vector_type(4)));
-                __builtin_nontemporal_store(ev4{o0, o1, o2, o3}, reinterpret_cast<ev4*>(vis_ch) + bl * 2 + (odd ? 1 : 0));
-                if (write_weights && !odd) w_sb[bl] = flagged ? 0 : S;
+        for (int r = 0; r < 4; r += 2) {
+            const E r0 = accR[p][r], i0v = accI[p][r], r1 = accR[p][r + 1], i1v = accI[p][r + 1];
+            const E yr = pair_swap(odd ? r0 : r1), yi = pair_swap(odd ? i0v : i1v);
+            E o0 = odd ? yr : r0, o1 = odd ? yi : i0v, o2 = odd ? r1 : yr, o3 = odd ? i1v : yi;
+            const int I = i0 + am[ia] * 16 + 4 * lg + r;
+            const int a = I >> 1;
+            if (Jc >= N || I >= N || a < b) continue;
+            if (a == b) {
+                if (odd) o3 = E(0);
+                else o1 = E(0);
             }
+            const bool flagged = fcol[ib] || frow[ia][r >> 1];
+            if (flagged) o0 = o1 = o2 = o3 = E(0);
+            const int64_t bl = (int64_t)a * (a + 1) / 2 + b;
+            typedef E ev4 __attribute__((ext_vector_type(4)));
+            __builtin_nontemporal_store(ev4{o0, o1, o2, o3}, reinterpret_cast<ev4*>(vis_ch) + bl * 2 + (odd ? 1 : 0));
+            if (write_weights && !odd) w_sb[bl] = flagged ? 0 : S;
         }
     }
 }
@@ -896,8 +902,8 @@ __device__ __forceinline__ void xtile_f32(const char* __restrict__ z, char* __re
 }
 
 // One tile of one (subband, channel).  int8 / fp16: each wave computes its
-// job of 32 x 32 blocks (diagonal tiles spread their lower-triangle blocks
-// over the waves); fp32: 2 x 2 waves of one block each.
+// job of 16 x 16 blocks (diagonal tiles spread their lower-triangle blocks
+// over the waves); fp32: 2 x 2 waves of one 32 x 32 block each.
 template <int DT, int TILE>
 __device__ __forceinline__ void xtile(const char* __restrict__ z, char* __restrict__ vis_ch,
                                       int32_t* __restrict__ w_sb, const uint8_t* __restrict__ fl_sb,
@@ -906,29 +912,37 @@ __device__ __forceinline__ void xtile(const char* __restrict__ z, char* __restri
         xtile_f32<DT, TILE>(z, vis_ch, w_sb, fl_sb, N, Na, S, ti, tj, write_weights, lds_raw);
     } else {
         const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        auto run = [&](auto job, const int (&am)[4], const int (&bn)[2]) {
-            xtile_mm<DT, TILE, decltype(job)>(z, vis_ch, w_sb, fl_sb, N, Na, S, ti, tj, write_weights, lds_raw,
-                                              am, bn);
+        auto run = [&](auto job, const int (&am)[8], const int (&bn)[2]) {
+            xtile_mm16<DT, TILE, decltype(job)>(z, vis_ch, w_sb, fl_sb, N, Na, S, ti, tj, write_weights, lds_raw,
+                                                am, bn);
         };
         if constexpr (TILE == 128) {
             if (ti != tj) {
-                const int am[4] = {0, 1, 2, 3}, bn[2] = {wid, 0};
-                run(JobRows4{}, am, bn);
+                const int am[8] = {0, 1, 2, 3, 4, 5, 6, 7}, bn[2] = {2 * wid, 2 * wid + 1};
+                run(Job16R8C2{}, am, bn);
             } else if (wid == 0) {
-                run(JobDiag0{}, JobDiag0::AM, JobDiag0::BN);
+                run(Job16D8<0>{}, Job16D8<0>::T.AM, Job16D8<0>::T.BN);
             } else if (wid == 1) {
-                run(JobDiag1{}, JobDiag1::AM, JobDiag1::BN);
+                run(Job16D8<1>{}, Job16D8<1>::T.AM, Job16D8<1>::T.BN);
             } else if (wid == 2) {
-                run(JobDiag2{}, JobDiag2::AM, JobDiag2::BN);
+                run(Job16D8<2>{}, Job16D8<2>::T.AM, Job16D8<2>::T.BN);
             } else {
-                run(JobDiag3{}, JobDiag3::AM, JobDiag3::BN);
+                run(Job16D8<3>{}, Job16D8<3>::T.AM, Job16D8<3>::T.BN);
             }
         } else {
             static_assert(TILE == 64, "int8 / fp16 tiles are 128 or 64 wide");
-            const int wr = wid >> 1, wc = wid & 1;
-            const int am[4] = {wr, 0, 0, 0}, bn[2] = {wc, 0};
-            if (ti == tj && wr < wc) run(JobIdle{}, am, bn);
-            else run(JobOne{}, am, bn);
+            if (ti != tj) {
+                const int am[8] = {0, 1, 2, 3, 0, 0, 0, 0}, bn[2] = {wid, 0};
+                run(Job16R4C1{}, am, bn);
+            } else if (wid == 0) {
+                run(Job16D4<0>{}, Job16D4<0>::T.AM, Job16D4<0>::T.BN);
+            } else if (wid == 1) {
+                run(Job16D4<1>{}, Job16D4<1>::T.AM, Job16D4<1>::T.BN);
+            } else if (wid == 2) {
+                run(Job16D4<2>{}, Job16D4<2>::T.AM, Job16D4<2>::T.BN);
+            } else {
+                run(Job16D4<3>{}, Job16D4<3>::T.AM, Job16D4<3>::T.BN);
+            }
         }
     }
 }
