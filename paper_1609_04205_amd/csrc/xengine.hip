@@ -610,51 +610,91 @@ __device__ __forceinline__ void xtile_mm16(const char* __restrict__ z, char* __r
     // holds the four values of a baseline, swaps one value so that the even
     // lane owns (p, q) = (0, 0), (0, 1) and the odd lane (1, 0), (1, 1), and
     // each lane stores 16 contiguous bytes.
-    bool frow[NA][2], fcol[NBO];
-#pragma unroll
-    for (int x = 0; x < NBO; ++x) fcol[x] = false;
-#pragma unroll
-    for (int i = 0; i < NA; ++i) frow[i][0] = frow[i][1] = false;
-    if (fl_sb) {
-        uint8_t fc[NBO], fr[NA][2];
-#pragma unroll
-        for (int x = 0; x < NBO; ++x) fc[x] = fl_sb[min(j0 + bn[x] * 16 + lc, N - 1) >> 1];
-#pragma unroll
-        for (int i = 0; i < NA; ++i)
-#pragma unroll
-            for (int k = 0; k < 2; ++k) fr[i][k] = fl_sb[min(i0 + am[i] * 16 + 4 * lg + 2 * k, N - 1) >> 1];
-#pragma unroll
-        for (int x = 0; x < NBO; ++x) fcol[x] = fc[x] != 0;
-#pragma unroll
-        for (int i = 0; i < NA; ++i)
-#pragma unroll
-            for (int k = 0; k < 2; ++k) frow[i][k] = fr[i][k] != 0;
-    }
     using E = std::conditional_t<DT == AFC_I8, int, float>;
     const bool odd = (lc & 1) != 0;
+    // rows I, I + 1 (the two polarisations of antenna I / 2) of receiver Jc
+    auto store_pair = [&](E r0, E i0v, E r1, E i1v, int I, int Jc, bool flagged) {
+        // the even lane sends its p = 1 values, the odd lane its p = 0 values
+        const E yr = pair_swap(odd ? r0 : r1), yi = pair_swap(odd ? i0v : i1v);
+        E o0 = odd ? yr : r0, o1 = odd ? yi : i0v, o2 = odd ? r1 : yr, o3 = odd ? i1v : yi;
+        const int a = I >> 1, b = Jc >> 1;
+        if (Jc >= N || I >= N || a < b) return;
+        if (a == b) {             // inputs equal for (0, 0) and (1, 1)
+            if (odd) o3 = E(0);
+            else o1 = E(0);
+        }
+        if (flagged) o0 = o1 = o2 = o3 = E(0);
+        const int64_t bl = (int64_t)a * (a + 1) / 2 + b;
+        // written once and not read again by this kernel: a streaming
+        // (non-temporal) store
+        typedef E ev4 __attribute__((ext_vector_type(4)));
+        __builtin_nontemporal_store(ev4{o0, o1, o2, o3}, reinterpret_cast<ev4*>(vis_ch) + bl * 2 + (odd ? 1 : 0));
+        if (write_weights && !odd) w_sb[bl] = flagged ? 0 : S;
+    };
+    auto flag_of = [&](int rcv) { return fl_sb[min(rcv, N - 1) >> 1] != 0; };
+    auto to_u = [](E v) -> unsigned {
+        if constexpr (DT == AFC_I8) return (unsigned)v;
+        else return __float_as_uint(v);
+    };
+    auto from_u = [](unsigned u) -> E {
+        if constexpr (DT == AFC_I8) return (int)u;
+        else return __uint_as_float(u);
+    };
+    if constexpr (std::is_same_v<J, Job16R8C2>) {
+        // Off the diagonal the wave's two column blocks are 16 consecutive
+        // antennas.  One permlane16 swap per value pair gives the lanes of
+        // rows 0 and 2 (of 16 lanes) column block 0 and the lanes of rows 1
+        // and 3 column block 1, each for the rows of both, so that a store
+        // instruction writes two runs of 16 whole baselines (512 bytes)
+        // instead of four runs of 8.
+        const int cbk = lg & 1, gb = lg & 2;
+        const int Jc = j0 + bn[cbk] * 16 + lc;
+        const bool fc = fl_sb ? flag_of(Jc) : false;
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-        const int ia = J::T.IA[p], ib = J::T.IB[p];
-        const int Jc = j0 + bn[ib] * 16 + lc;
-        const int b = Jc >> 1;
+        for (int i = 0; i < 8; ++i) {
+            bool fr[2][2] = {{false, false}, {false, false}};
+            if (fl_sb) {
 #pragma unroll
-        for (int r = 0; r < 4; r += 2) {
-            const E r0 = accR[p][r], i0v = accI[p][r], r1 = accR[p][r + 1], i1v = accI[p][r + 1];
-            const E yr = pair_swap(odd ? r0 : r1), yi = pair_swap(odd ? i0v : i1v);
-            E o0 = odd ? yr : r0, o1 = odd ? yi : i0v, o2 = odd ? r1 : yr, o3 = odd ? i1v : yi;
-            const int I = i0 + am[ia] * 16 + 4 * lg + r;
-            const int a = I >> 1;
-            if (Jc >= N || I >= N || a < b) continue;
-            if (a == b) {
-                if (odd) o3 = E(0);
-                else o1 = E(0);
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int k = 0; k < 2; ++k) fr[h][k] = flag_of(i0 + am[i] * 16 + 4 * (gb + h) + 2 * k);
             }
-            const bool flagged = fcol[ib] || frow[ia][r >> 1];
-            if (flagged) o0 = o1 = o2 = o3 = E(0);
-            const int64_t bl = (int64_t)a * (a + 1) / 2 + b;
-            typedef E ev4 __attribute__((ext_vector_type(4)));
-            __builtin_nontemporal_store(ev4{o0, o1, o2, o3}, reinterpret_cast<ev4*>(vis_ch) + bl * 2 + (odd ? 1 : 0));
-            if (write_weights && !odd) w_sb[bl] = flagged ? 0 : S;
+            E hr[2][4], hi[2][4];      // [rows 4 gb + r, rows 4 (gb + 1) + r][r]
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                // (elements into scalars first: a bit cast of a vector element
+                // passed straight to the builtin read element 0 for every r)
+                const E xr = accR[2 * i][r], yr = accR[2 * i + 1][r];
+                const E xi = accI[2 * i][r], yi = accI[2 * i + 1][r];
+                const auto sr = __builtin_amdgcn_permlane16_swap(to_u(xr), to_u(yr), false, false);
+                const auto si = __builtin_amdgcn_permlane16_swap(to_u(xi), to_u(yi), false, false);
+                hr[0][r] = from_u(sr[0]);
+                hr[1][r] = from_u(sr[1]);
+                hi[0][r] = from_u(si[0]);
+                hi[1][r] = from_u(si[1]);
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int r = 0; r < 4; r += 2)
+                    store_pair(hr[h][r], hi[h][r], hr[h][r + 1], hi[h][r + 1], i0 + am[i] * 16 + 4 * (gb + h) + r, Jc,
+                               fc || fr[h][r >> 1]);
+        }
+    } else {
+        bool frow[NA][2], fcol[NBO];
+#pragma unroll
+        for (int x = 0; x < NBO; ++x) fcol[x] = fl_sb ? flag_of(j0 + bn[x] * 16 + lc) : false;
+#pragma unroll
+        for (int i = 0; i < NA; ++i)
+#pragma unroll
+            for (int k = 0; k < 2; ++k) frow[i][k] = fl_sb ? flag_of(i0 + am[i] * 16 + 4 * lg + 2 * k) : false;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int ia = J::T.IA[p], ib = J::T.IB[p];
+#pragma unroll
+            for (int r = 0; r < 4; r += 2)
+                store_pair(accR[p][r], accI[p][r], accR[p][r + 1], accI[p][r + 1], i0 + am[ia] * 16 + 4 * lg + r,
+                           j0 + bn[ib] * 16 + lc, fcol[ib] || frow[ia][r >> 1]);
         }
     }
 }
