@@ -448,9 +448,11 @@ __device__ __forceinline__ void xtile_mm16(const char* __restrict__ z, char* __r
     const int stage_bytes = kStg * N * RB;
     // A stage whose blocks all lie in the data takes its offset as the
     // scalar part of the load; past the end (the last stages) the block is
-    // clamped to nb - 1 per lane.  Only the offsets sit behind the (uniform)
-    // branch, not the loads.
-    // kClamp: the stage may lie past the end (not for the main loop's loads)
+    // clamped to nb - 1 per lane, and every offset then lies in the channel's
+    // data (the scalar part of a buffer offset is not range-checked).  Only
+    // the offsets sit behind the (uniform) branch, not the loads.  The clamp
+    // tag is false only where the stage is known to be whole: the loads the
+    // main loop of the register-ring form issues.
     auto issue_panel = [&](auto clamp_tag, int st, char* panel, int c, int src) {
         char* dst = panel + (c * kThreads + wid * 64) * 16;
         int voff = src, soff = st * stage_bytes;
@@ -539,7 +541,9 @@ __device__ __forceinline__ void xtile_mm16(const char* __restrict__ z, char* __r
                 } else {
                     wait_landed(st + 1);
                     dma_barrier();
-                    if (st + 1 + kDmaDepth < n_st) issue_a(clamp_tag, st + 1 + kDmaDepth);
+                    // (with a ring of one stage the main loop also issues the
+                    // last stages, so the offsets are always checked)
+                    if (st + 1 + kDmaDepth < n_st) issue_a(std::true_type{}, st + 1 + kDmaDepth);
                     read_b(st + 1);
                 }
                 __builtin_amdgcn_sched_barrier(0);
