@@ -68,17 +68,11 @@ template <> struct XT<AFC_F32> {
     static constexpr int RB = 64, PLANES = 4;
     using acc_t = v16f;
 };
-// spectrum blocks per LDS stage
-#ifndef AFC_I8_STAGE_BLOCKS
-#define AFC_I8_STAGE_BLOCKS 4
-#endif
-#ifndef AFC_F16_STAGE_BLOCKS
-#define AFC_F16_STAGE_BLOCKS 2
-#endif
+// spectrum blocks per LDS stage: int8 / fp16 one 16 x 16 MFMA k-step (64
+// bytes of each receiver), fp32 four blocks
 template <int DT, int TILE>
 constexpr int stage_blocks() {
-    return DT == AFC_F32 ? 4 : TILE != 128 ? (DT == AFC_I8 ? 4 : 2)
-                                           : DT == AFC_I8 ? AFC_I8_STAGE_BLOCKS : AFC_F16_STAGE_BLOCKS;
+    return DT == AFC_F32 ? 4 : 64 / XT<DT>::RB;
 }
 // fp32: stages of register-staged loads in flight
 template <int DT, int TILE>
@@ -96,12 +90,6 @@ constexpr bool uses_dma() { return DT != AFC_F32; }
 #endif
 template <int DT>
 constexpr int dma_depth() { return DT == AFC_I8 ? AFC_I8_DMA_DEPTH : AFC_F16_DMA_DEPTH; }
-#ifndef AFC_XENGINE_BDIRECT
-#define AFC_XENGINE_BDIRECT 1
-#endif
-// off-diagonal square tiles load their B operands into registers (1) or
-// stage them through LDS with the A panel (0)
-constexpr bool kBDirect = AFC_XENGINE_BDIRECT != 0;
 // DMA ring: the stage being multiplied, the next one (landed before its
 // operands are read) and dma_depth - 1 further stages in flight, plus the
 // buffer being refilled
@@ -112,15 +100,19 @@ constexpr int lds_bytes() {
     // 128-wide int8 / fp16 tiles stage only the row panel (their column
     // operands are loaded into registers, or, on the diagonal, are the row
     // panel); the others stage both
-    constexpr int panels = uses_dma<DT>() && TILE == 128 && kBDirect ? 1 : 2;
+    constexpr int panels = uses_dma<DT>() && TILE == 128 ? 1 : 2;
     return (uses_dma<DT>() ? dma_buffers<DT>() : 2) * panels * stage_blocks<DT, TILE>() * TILE * XT<DT>::RB;
 }
 
 // Workgroup barrier for the DMA pipeline: no memory fence (which would wait
-// for every outstanding global-to-LDS load); a compiler-level memory clobber
-// keeps LDS accesses on their side of it.
+// for every outstanding global-to-LDS load) and no wait for the wave's LDS
+// reads: the buffer refilled after it is the one the previous stage read,
+// and each of those reads has fed an MFMA or an operand conversion of that
+// stage before the wave reaches the barrier; the reads still in flight are
+// of the next stage's buffer.  A compiler-level memory clobber keeps LDS
+// accesses on their side of it.
 __device__ __forceinline__ void dma_barrier() {
-    __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    __asm__ volatile("s_barrier" ::: "memory");
 }
 
 // 16 bytes per lane from base + voff + soff (a raw buffer of `bytes` bytes)
@@ -370,7 +362,7 @@ __device__ __forceinline__ void xtile_mm16(const char* __restrict__ z, char* __r
     // off-diagonal 128-tiles load their column operands straight into
     // registers (each wave alone uses its two column blocks), in a ring of RS
     // register slots: the stage in use and kDmaDepth in flight
-    constexpr bool BD = kBDirect && J::kDirectB;
+    constexpr bool BD = J::kDirectB;
     constexpr int RS = BD ? kDmaDepth + 1 : 1;
     static_assert(RS <= 4, "register ring of at most four stages");
     constexpr int BUF = PANEL + (BD || kDiagJob ? 0 : PANEL_B);
