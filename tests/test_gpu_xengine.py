@@ -118,6 +118,33 @@ def test_int8_extreme_values_exact(afc, dev):
         np.testing.assert_array_equal(v[0, ch].astype(np.int64), Vref)
 
 
+@pytest.mark.parametrize("dtype,B,Na,S", [("i8", 2, 576, 3051), ("f16", 1, 576, 763), ("i8", 2, 150, 300),
+                                          ("f16", 1, 150, 77), ("i8", 1, 70, 37)])
+def test_repeated_launches_bit_identical(afc, dev, dtype, B, Na, S):
+    """The DMA ring's stage barrier orders the refill of a stage buffer after
+    every wave's reads of it; a missing wait would show as launches that
+    differ.  Every repeat (with other work queued in between) must equal the
+    first bit for bit, on 128-wide diagonal and off-diagonal tiles and
+    ragged tails."""
+    log(f"xengine repeats {dtype} B={B} Na={Na} S={S}")
+    z = W.make_channelised(B, 64, S, 2 * Na, dtype, seed=12, device=dev)
+    fl = torch.zeros((B, Na), dtype=torch.uint8, device=dev)
+    fl[:, Na // 3] = 1
+    vis = torch.empty(afc.visibility_shape(B, Na), dtype=torch.int32 if dtype == "i8" else torch.float32,
+                      device=dev)
+    afc.correlate(z, n_spectra=S, out=vis, flags=fl, want_weights=False)
+    torch.cuda.synchronize()
+    first = vis.view(torch.int32).clone()
+    for _ in range(6):
+        vis.fill_(-1)
+        _ = torch.randn(4096, device=dev).sum()
+        afc.correlate(z, n_spectra=S, out=vis, flags=fl, want_weights=False)
+        torch.cuda.synchronize()
+        assert torch.equal(vis.view(torch.int32), first)
+    del z, vis, first
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("dtype", ["i8", "f16", "f32"])
 def test_full_size_sampled(afc, dev, dtype):
     """AARTFAAC-12 shape: 1152 receivers, 16 subbands, 3051 spectra, sampled baselines."""
