@@ -582,12 +582,17 @@ struct afc_plan {
 
 namespace {
 
-// Cost of one tile item in MFMA cycles per spectrum (per SIMD), from the
-// instruction rates: int8 32x32x32 and fp16 32x32x16 take the same cycles,
-// int8 covers twice the spectra; fp32 32x32x2 covers one spectrum per pair.
+// Time of one tile item in MFMA cycles (per SIMD), from the instruction
+// rates: an int8 16x16x64 and an fp16 16x16x32 MFMA take the same cycles,
+// the int8 one covering twice the spectra (4 and 8 cycles per spectrum for
+// the real and imaginary parts of a 32 x 32 area); fp32 32x32x2 blocks take
+// 128.  The waves of a tile run in parallel, so a diagonal tile takes the
+// time of its busiest wave: 9 of 16 blocks (128-wide), 3 of 4 (64-wide
+// int8 / fp16), all of it for fp32 (one block per wave either way).
 double tile_cost(int dt, int tile, int S, bool diag) {
-    const double blocks = (tile / 32.0) * (tile / 32.0) * (diag ? 10.0 / 16.0 : 1.0);
-    const double per_spec = dt == AFC_I8 ? 4.0 : dt == AFC_F16 ? 8.0 : 128.0;   // cycles per 32x32 block-spectrum
+    const double diag_frac = dt == AFC_F32 ? 1.0 : tile == 128 ? 9.0 / 16.0 : 3.0 / 4.0;
+    const double blocks = (tile / 32.0) * (tile / 32.0) * (diag ? diag_frac : 1.0);
+    const double per_spec = dt == AFC_I8 ? 4.0 : dt == AFC_F16 ? 8.0 : 128.0;   // cycles per 32x32 area-spectrum
     return blocks * per_spec * S + 2000.0;                                      // + fixed cost (epilogue)
 }
 
@@ -609,7 +614,6 @@ void build_work(const afc_plan& p, int m, int tile, std::vector<XWork>& work_out
     std::vector<G> groups;
     for (int b = 0; b < p.d.n_subbands; ++b) {
         if (!in_mode(p, m, p.dt[b])) continue;
-        if (!in_mode) continue;
         double c = 0;
         for (int ti = 0; ti < nT; ++ti)
             for (int tj = 0; tj <= ti; ++tj) c += tile_cost(p.dt[b], tile, p.S[b], ti == tj);
