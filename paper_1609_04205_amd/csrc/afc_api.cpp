@@ -745,41 +745,48 @@ int tune_mode0(afc_plan* p, TuneChoice& out) {
         hipFree(vis);
         return hip_fail(e, "tuner scratch fill");
     }
-    hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
     float best = 1e30f;
     out = cands[0];
-    int rc = AFC_OK;
-    for (const auto& c : cands) {
+    int rc = e == hipSuccess ? AFC_OK : hip_fail(e, "tuner events");
+    // every launch and event call is checked: a candidate that failed to
+    // launch would otherwise time as the fastest
+    for (size_t ci = 0; rc == AFC_OK && ci < cands.size(); ++ci) {
+        const TuneChoice& c = cands[ci];
         p->split = c.split != 0;
         rc = upload_mode(p, 0, c.tile);
         if (rc == AFC_OK) rc = upload_mode(p, 2, c.tile);
         if (rc != AFC_OK) break;
         float tmin = 1e30f;
-        for (int rep = 0; rep < 3; ++rep) {
-            hipEventRecord(e0, nullptr);
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+            e = hipEventRecord(e0, nullptr);
             for (int m : {0, 2}) {
                 const afc_plan::Mode& md = p->mode[m];
-                if (md.used)
-                    launch_xengine_list(z, vis, nullptr, nullptr, p->d_sbs, md.d_work, md.ranges, p->N, p->Na, 0,
-                                        md.tile, nullptr);
+                if (e == hipSuccess && md.used)
+                    e = launch_xengine_list(z, vis, nullptr, nullptr, p->d_sbs, md.d_work, md.ranges, p->N, p->Na, 0,
+                                            md.tile, nullptr);
             }
-            hipEventRecord(e1, nullptr);
-            hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0;
-            hipEventElapsedTime(&ms, e0, e1);
-            if (rep > 0) tmin = std::min(tmin, ms);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && rep > 0) tmin = std::min(tmin, ms);
+        }
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "tuner candidate launch");
+            break;
         }
         if (tmin < best) {
             best = tmin;
             out = c;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipFree(z);
-    hipFree(vis);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(z);
+    (void)hipFree(vis);
     return rc;
 }
 
