@@ -82,11 +82,6 @@ __device__ __forceinline__ float2 residual(float2 v, float2 m, float2 ga, float2
     return make_float2(__fadd_rn(rr.hi, __fsub_rn(rr.lo, wr.lo)), __fadd_rn(ri.hi, __fsub_rn(ri.lo, wi.lo)));
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
 __device__ __forceinline__ float wave_sumf(float v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

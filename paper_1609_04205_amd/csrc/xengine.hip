@@ -546,7 +546,9 @@ __device__ __forceinline__ void xtile_mm16(const char* __restrict__ z, char* __r
                 __builtin_amdgcn_sched_barrier(0);
             }
             if constexpr (kNext && last_use_b<J>(ib) == p) {
-                uint4 u = BD ? bdir[RN][ib] : b_raw[ib];
+                uint4 u;
+                if constexpr (BD) u = bdir[RN][ib];
+                else u = b_raw[ib];
                 if constexpr (kMaskNext) mask_op(st + 1, u);
                 bv[ib] = cvt(u);
                 bj[ib] = jsw(u);
@@ -577,7 +579,9 @@ __device__ __forceinline__ void xtile_mm16(const char* __restrict__ z, char* __r
     if constexpr (!BD) read_b(0);
 #pragma unroll
     for (int x = 0; x < NBO; ++x) {
-        uint4 u = BD ? bdir[0][x] : b_raw[x];
+        uint4 u;
+        if constexpr (BD) u = bdir[0][x];
+        else u = b_raw[x];
         if (n_final == 0) mask_op(0, u);
         bv[x] = cvt(u);
         bj[x] = jsw(u);
