@@ -134,7 +134,6 @@ def main():
     B, Na, S, P = cfg.n_subbands, cfg.n_antennas, cfg.n_spectra, 64
     N = 2 * Na
     nbl = Na * (Na + 1) // 2
-    Sb = (S + 7) // 8
     L = cfg.n_rows
     log(f"workload {cfg.name}: B={B} Na={Na} N={N} S={S}")
     x = W.make_voltages(cfg, device=dev)
@@ -234,7 +233,6 @@ def main():
         tv = Timer(torch)
         for it in range(4):
             tm = tv if it > 0 else None
-            marks = []
             for name, fn in (("validity", lambda: afc.validity(pkt, S, W.PACKET_SAMPLES, out=bits)),
                              ("zero", lambda: afc.zero_invalid(z8, bits, S)),
                              ("weights", lambda: afc.validity_weights(bits, S, out=wts)),
@@ -498,7 +496,7 @@ def main():
         for _ in range(3):
             gs.copy_(g_unit)
             e = ts.rec("solve")
-            lsol = afc.calibrate_solve(Vt, Mt, gs, n_it, workspace=wss)
+            afc.calibrate_solve(Vt, Mt, gs, n_it, workspace=wss)
             e.record(torch.cuda.current_stream())
             e = ts.rec("clip")
             afc.sigma_clip(Vt, 5.0, out=flg)
