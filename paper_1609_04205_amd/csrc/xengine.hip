@@ -649,17 +649,9 @@ __device__ __forceinline__ void xtile_mm16(const char* __restrict__ z, char* __r
         // instead of four runs of 8.
         const int cbk = lg & 1, gb = lg & 2;
         const int Jc = j0 + bn[cbk] * 16 + lc;
-        const bool fc = fl_sb ? flag_of(Jc) : false;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            bool fr[2][2] = {{false, false}, {false, false}};
-            if (fl_sb) {
-#pragma unroll
-                for (int h = 0; h < 2; ++h)
-#pragma unroll
-                    for (int k = 0; k < 2; ++k) fr[h][k] = flag_of(i0 + am[i] * 16 + 4 * (gb + h) + 2 * k);
-            }
-            E hr[2][4], hi[2][4];      // [rows 4 gb + r, rows 4 (gb + 1) + r][r]
+        // [rows 4 gb + r, rows 4 (gb + 1) + r][r] of the two column blocks'
+        // row block i
+        auto swap_rows = [&](int i, E (&hr)[2][4], E (&hi)[2][4]) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 // (elements into scalars first: a bit cast of a vector element
@@ -673,12 +665,68 @@ __device__ __forceinline__ void xtile_mm16(const char* __restrict__ z, char* __r
                 hi[0][r] = from_u(si[0]);
                 hi[1][r] = from_u(si[1]);
             }
+        };
+        if (fl_sb == nullptr && !write_weights && i0 + TILE <= N) {
+            // Interior tile without flags or weights (uniform): every baseline
+            // of it exists (a > b, all rows and columns below N), so the
+            // stores need no checks.  The lane's row antennas are a0 + k,
+            // k = 8 i + 2 h + r / 2, and bl(a0 + k, b) - bl(a0, b) =
+            // k a0 + k (k + 1) / 2, so each store's offset is one multiply-add
+            // on the lane's base (32-bit: a channel's visibilities are below
+            // 2^31 bytes at the antenna limit).
+            const int a0 = (i0 >> 1) + 2 * gb, b = Jc >> 1;
+            const int nbl = Na * (Na + 1) / 2;
+            const unsigned vbase = (unsigned)(a0 * (a0 + 1) / 2 + b) * 32u + (odd ? 16u : 0u);
+            const unsigned a32 = (unsigned)a0 * 32u;
+#if defined(__HIP_DEVICE_COMPILE__)
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc((void*)vis_ch, (short)0, nbl * 32, 0x00020000);
+#endif
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+            for (int i = 0; i < 8; ++i) {
+                E hr[2][4], hi[2][4];
+                swap_rows(i, hr, hi);
 #pragma unroll
-                for (int r = 0; r < 4; r += 2)
-                    store_pair(hr[h][r], hi[h][r], hr[h][r + 1], hi[h][r + 1], i0 + am[i] * 16 + 4 * (gb + h) + r, Jc,
-                               fc || fr[h][r >> 1]);
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int r = 0; r < 4; r += 2) {
+                        // the even lane keeps (p, q) = (0, 0), (0, 1), the odd
+                        // lane (1, 0), (1, 1), as in store_pair
+                        const E r0 = hr[h][r], i0v = hi[h][r], r1 = hr[h][r + 1], i1v = hi[h][r + 1];
+                        const E yr = pair_swap(odd ? r0 : r1), yi = pair_swap(odd ? i0v : i1v);
+                        const v4i o{(int)to_u(odd ? yr : r0), (int)to_u(odd ? yi : i0v), (int)to_u(odd ? r1 : yr),
+                                    (int)to_u(odd ? i1v : yi)};
+                        const int k = 8 * am[i] + 2 * h + r / 2;
+                        const unsigned voff = vbase + (unsigned)k * a32 + (unsigned)(k * (k + 1) / 2) * 32u;
+#if defined(__HIP_DEVICE_COMPILE__)
+                        // non-temporal (cache policy bit 1), as the checked stores
+                        __builtin_amdgcn_raw_buffer_store_b128(o, rs, (int)voff, 0, 2);
+#else
+                        (void)o;
+                        (void)voff;
+#endif
+                    }
+            }
+        } else {
+            const bool fc = fl_sb ? flag_of(Jc) : false;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                bool fr[2][2] = {{false, false}, {false, false}};
+                if (fl_sb) {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int k = 0; k < 2; ++k) fr[h][k] = flag_of(i0 + am[i] * 16 + 4 * (gb + h) + 2 * k);
+                }
+                E hr[2][4], hi[2][4];
+                swap_rows(i, hr, hi);
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int r = 0; r < 4; r += 2)
+                        store_pair(hr[h][r], hi[h][r], hr[h][r + 1], hi[h][r + 1], i0 + am[i] * 16 + 4 * (gb + h) + r,
+                                   Jc, fc || fr[h][r >> 1]);
+            }
         }
     } else {
         bool frow[NA][2], fcol[NBO];
