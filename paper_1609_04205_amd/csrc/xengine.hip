@@ -666,10 +666,11 @@ __device__ __forceinline__ void xtile_mm16(const char* __restrict__ z, char* __r
                 hi[1][r] = from_u(si[1]);
             }
         };
-        if (fl_sb == nullptr && !write_weights && i0 + TILE <= N) {
-            // Interior tile without flags or weights (uniform): every baseline
+        if (!write_weights && i0 + TILE <= N) {
+            // Interior tile that writes no weights (uniform): every baseline
             // of it exists (a > b, all rows and columns below N), so the
-            // stores need no checks.  The lane's row antennas are a0 + k,
+            // stores need no checks, and flagged baselines are zeroed by
+            // selection.  The lane's row antennas are a0 + k,
             // k = 8 i + 2 h + r / 2, and bl(a0 + k, b) - bl(a0, b) =
             // k a0 + k (k + 1) / 2, so each store's offset is one multiply-add
             // on the lane's base (32-bit: a channel's visibilities are below
@@ -682,6 +683,19 @@ __device__ __forceinline__ void xtile_mm16(const char* __restrict__ z, char* __r
             const __amdgpu_buffer_rsrc_t rs =
                 __builtin_amdgcn_make_buffer_rsrc((void*)vis_ch, (short)0, nbl * 32, 0x00020000);
 #endif
+            // the lane's flags, all loaded before the first store (stores and
+            // loads share the wave's memory counter, so a flag load waited for
+            // between stores would also wait for every store before it)
+            bool fz[8][2][2] = {};
+            if (fl_sb) {
+                const bool fc = flag_of(Jc);
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int k = 0; k < 2; ++k) fz[i][h][k] = fc || flag_of(i0 + am[i] * 16 + 4 * (gb + h) + 2 * k);
+            }
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 E hr[2][4], hi[2][4];
@@ -694,8 +708,9 @@ __device__ __forceinline__ void xtile_mm16(const char* __restrict__ z, char* __r
                         // lane (1, 0), (1, 1), as in store_pair
                         const E r0 = hr[h][r], i0v = hi[h][r], r1 = hr[h][r + 1], i1v = hi[h][r + 1];
                         const E yr = pair_swap(odd ? r0 : r1), yi = pair_swap(odd ? i0v : i1v);
-                        const v4i o{(int)to_u(odd ? yr : r0), (int)to_u(odd ? yi : i0v), (int)to_u(odd ? r1 : yr),
-                                    (int)to_u(odd ? i1v : yi)};
+                        v4i o{(int)to_u(odd ? yr : r0), (int)to_u(odd ? yi : i0v), (int)to_u(odd ? r1 : yr),
+                              (int)to_u(odd ? i1v : yi)};
+                        if (fz[i][h][r >> 1]) o = v4i{0, 0, 0, 0};
                         const int k = 8 * am[i] + 2 * h + r / 2;
                         const unsigned voff = vbase + (unsigned)k * a32 + (unsigned)(k * (k + 1) / 2) * 32u;
 #if defined(__HIP_DEVICE_COMPILE__)
