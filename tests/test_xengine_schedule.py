@@ -71,3 +71,43 @@ def test_unclamped_last_stage_is_caught():
                 return True
         return False
     assert any(bad(nb) for nb in range(1, 100))
+
+
+def test_check_free_store_offsets():
+    """The check-free epilogue stores of an interior off-diagonal 128-wide
+    tile address baseline (a0 + k, b) as the lane's base plus k a0 + k (k+1)/2
+    (a0 = i0 / 2 + 2 gb with gb in {0, 2}, k = 8 i + 2 h + r / 2 < 64, b below
+    the tile's rows): the same baseline index as bl(a, b) = a (a + 1) / 2 + b,
+    every baseline of the tile written exactly once per lane pair, and the
+    byte offsets below 2^31 at the 4096-antenna limit."""
+    def bl(a, b):
+        return a * (a + 1) // 2 + b
+
+    for Na in (576, 4096):
+        N = 2 * Na
+        n_side = -(-N // 128)
+        max_off = 0
+        for ti in range(n_side):
+            i0 = ti * 128
+            if i0 + 128 > N:
+                continue                                    # edge tiles take the checked path
+            for tj in (0, ti - 1) if ti > 0 else ():
+                j0 = tj * 128
+                seen = set()
+                for gb in (0, 2):
+                    a0 = i0 // 2 + 2 * gb
+                    for col in range(128):                  # column receiver j0 + col, lane pair by antenna
+                        b = (j0 + col) // 2
+                        base = bl(a0, b)
+                        for i in range(8):
+                            for h in range(2):
+                                for r in (0, 2):
+                                    k = 8 * i + 2 * h + r // 2
+                                    a = (i0 + 16 * i + 4 * (gb + h) + r) // 2
+                                    assert a == a0 + k and a > b
+                                    got = base + k * a0 + k * (k + 1) // 2
+                                    assert got == bl(a, b)
+                                    seen.add((a, b))
+                                    max_off = max(max_off, got * 32 + 16)
+                assert seen == {(a, b) for a in range(i0 // 2, i0 // 2 + 64) for b in range(j0 // 2, j0 // 2 + 64)}
+        assert max_off < Na * (Na + 1) // 2 * 32 <= 2 ** 31
