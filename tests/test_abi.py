@@ -237,3 +237,21 @@ def test_plan_launch_rejects_wrong_buffer_sizes_on_host(afc):
         _raises(afc, lambda: plan.launch(x, taps, g, ws, vis), "GPU tensor")     # right sizes: only the device
     finally:
         plan.close()
+
+
+def test_degenerate_sizes_are_rejected_on_host(afc):
+    """No antennas, no subbands or no spectra (and negative sizes) are
+    invalid arguments (the header asks Na >= 1, 1 <= B <= 256, S >= 1) for the
+    channeliser and the correlator, with a message naming the size; the size
+    queries return 0 for them."""
+    lib = afc._lib
+    dummy = C.c_void_p(0x1000)          # never dereferenced: validation fails first
+    for (Na, B, S, word) in [(0, 1, 16, b"n_antennas"), (-1, 1, 16, b"n_antennas"), (48, 0, 16, b"n_subbands"),
+                             (48, 257, 16, b"n_subbands"), (48, 1, 0, b"n_spectra")]:
+        d = afc.Dims(Na, 2, B, 64, 16, S)
+        assert lib.afc_channelise(C.byref(d), dummy, dummy, afc.AFC_I8, 1.0, dummy, None) == -1
+        assert word in lib.afc_last_error()
+        assert lib.afc_correlate(C.byref(d), afc.AFC_I8, dummy, None, None, dummy, None, None) == -1
+        assert word in lib.afc_last_error()
+        assert lib.afc_channelised_bytes(C.byref(d), afc.AFC_I8) == 0
+        assert lib.afc_visibility_bytes(C.byref(d)) == 0
