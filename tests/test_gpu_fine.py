@@ -202,3 +202,26 @@ def test_f32_full_size_sampled(afc, dev):
         assert err <= 1e-5
     del x, z
     torch.cuda.empty_cache()
+
+
+def test_run_length_does_not_change_results(afc, dev):
+    """The host picks the spectra per workgroup from the launch size: the
+    16-subband AARTFAAC-12 launch runs 768 spectra per workgroup, a launch of
+    one of its subbands shorter runs (more workgroups for the CUs).  Each
+    output's FIR is the same 16 products in the same order wherever a run
+    starts, so the subband's fp32 and int8 outputs are identical bit for bit."""
+    Na, B, S = 576, 16, 762
+    log("fine run lengths: 16 subbands against single subbands")
+    x = W.make_voltages(W.A12, device=dev, n_rows=W.fine_rows(S))
+    taps = W.prototype_taps(PF, T)
+    tau = W.cable_delays(2 * Na)
+    w = W.bandpass_weights(PF)
+    nu = [W.subband_frequency(b) for b in range(B)]
+    for dtype, gain in (("f32", 1.0), ("i8", 0.05)):
+        z = _run(afc, dev, x, taps, tau, w, nu, S, dtype, gain)
+        for sb in (0, 15):
+            z1 = _run(afc, dev, x[sb:sb + 1].contiguous(), taps, tau, w, [nu[sb]], S, dtype, gain)
+            assert torch.equal(z1[0].view(torch.int8), z[sb].view(torch.int8)), (dtype, sb)
+        del z, z1
+    del x
+    torch.cuda.empty_cache()
