@@ -145,6 +145,26 @@ def test_repeated_launches_bit_identical(afc, dev, dtype, B, Na, S):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("dtype", ["i8", "f16"])
+def test_checked_and_check_free_stores_agree(afc, dev, dtype):
+    """Channel 0's tiles store through the checked path when weights are
+    asked for and through the check-free one otherwise (interior
+    off-diagonal 128-wide tiles): the visibilities are the same bit for bit,
+    with and without flagged antennas."""
+    Na, S = 576, 300
+    z = W.make_channelised(2, 64, S, 2 * Na, dtype, seed=21, device=dev)
+    for flagged in ([], [0, 200, 575]):
+        fl = torch.zeros((2, Na), dtype=torch.uint8, device=dev)
+        if flagged:
+            fl[:, flagged] = 1
+        v_w, _ = afc.correlate(z, n_spectra=S, flags=fl)
+        v_n, _ = afc.correlate(z, n_spectra=S, flags=fl, want_weights=False)
+        torch.cuda.synchronize()
+        assert torch.equal(v_w.view(torch.int32), v_n.view(torch.int32)), flagged
+    del z, v_w, v_n
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("dtype", ["i8", "f16", "f32"])
 def test_full_size_sampled(afc, dev, dtype):
     """AARTFAAC-12 shape: 1152 receivers, 16 subbands, 3051 spectra, sampled baselines."""
